@@ -1,0 +1,253 @@
+#!/usr/bin/env python3
+"""Benchmark of the triangular-domain hot path on one MI355X.
+
+Default workload (one "step"): the global-memory triangular elementwise
+kernel C[i][j] = a X[i][j] + Y[j][i] over the lower triangle (diagonal
+included) of n = 32768 FP32 matrices in full n x n storage, lambda(omega)
+map, one launch per step, inputs resident in HBM.  Prints ONE JSON line.
+
+The same line carries, under "extra", the other workloads measured on the
+same run: lambda vs bounding box at n = 2048 (int32), the triangular Game of
+Life (n = 16384, 100 steps), and the distance map (n = 65536, d = 128).
+
+    python bench.py [--steps K] [--warmup W] [--tile 32] [--map lambda]
+                    [--no-extra] [--no-cpu] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+class Timer:
+    """HIP events on the stream the kernels are launched on."""
+
+    def __init__(self, torch):
+        self.torch = torch
+
+    def run(self, fn, steps, warmup):
+        torch = self.torch
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        s = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(steps):
+            fn()
+        e1.record(s)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps  # ms per call
+
+
+def src_digest(*names):
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_1609_01490_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel_tag: str, digest: str):
+    """HBM bytes per launch measured with rocprofv3 --pmc (FETCH_SIZE and
+    WRITE_SIZE, scaled by a plain copy of known size), recorded under
+    profiles/ with the digest of the kernel sources they were taken on.
+    None when no record matches the current sources."""
+    pdir = os.path.join(ROOT, "profiles")
+    if not os.path.isdir(pdir):
+        return None
+    for fn in sorted(os.listdir(pdir)):
+        if not fn.endswith(".md"):
+            continue
+        txt = open(os.path.join(pdir, fn)).read()
+        if f"traffic_kernel: {kernel_tag}" not in txt:
+            continue
+        m_d = re.search(r"src_digest: (\w+)", txt)
+        m_b = re.search(r"hbm_bytes_per_launch: ([0-9.eE+]+)", txt)
+        if m_d and m_b and m_d.group(1) == digest:
+            return float(m_b.group(1))
+    return None
+
+
+def cpu_baseline_elementwise(a, X, Y, budget_s=12.0):
+    """The oracle (single-threaded C) on a bounded sample of rows of the same
+    workload: bands of 64 rows spread over the matrix, until budget_s."""
+    import oracle
+    n = X.shape[0]
+    rng = np.random.default_rng(5)
+    starts = rng.permutation(n // 64) * 64
+    out = np.empty((64, n), dtype=np.float32)
+    done_el, t0 = 0, time.perf_counter()
+    bands = 0
+    for r0 in starts.tolist():
+        oracle.c1(a, X, Y, out, r0=r0, r1=r0 + 64)
+        done_el += sum(i + 1 for i in range(r0, r0 + 64))
+        bands += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": done_el / dt, "unit": "elements/s", "cores": 1, "kind": "oracle",
+            "sample": f"{bands} bands of 64 rows ({done_el} cells) of the n=32768 fp32 "
+                      f"elementwise workload, {dt:.1f} s"}
+
+
+def bench_elementwise(tm, torch, args, timer):
+    from paper_1609_01490_amd import inputs
+    n = 32768
+    log("generating fp32 inputs", n)
+    a, X, Y, _ = inputs.f32_elementwise(n, with_fill=False)
+    xd = torch.from_numpy(X).cuda()
+    yd = torch.from_numpy(Y).cuda()
+    c = torch.empty((n, n), dtype=torch.float32, device="cuda")
+    E = n * (n + 1) // 2
+    res = {}
+    for map_name in (args.map, "bb"):
+        p = tm.Plan(n, args.tile, map_name, flags=args.flags)
+        ms = timer.run(lambda: p.elementwise(tm.OP_AXPYT_F32, xd, yd, c, ld=n, a=float(a)),
+                       args.steps, args.warmup)
+        res[map_name] = ms
+        log(f"elementwise {map_name} tile {args.tile}: {ms:.4f} ms")
+    cpu = None if args.no_cpu else cpu_baseline_elementwise(a, X, Y)
+    del xd, yd, c
+    torch.cuda.empty_cache()
+    return n, E, res, cpu
+
+
+def bench_int_elementwise(tm, torch, timer, tile=16):
+    from paper_1609_01490_amd import inputs
+    n = 2048
+    A, B, C0 = inputs.int_elementwise(n)
+    ad, bd, cd = (torch.from_numpy(v).cuda() for v in (A, B, C0))
+    out = {}
+    for map_name in ("lambda", "bb", "rb", "rec", "utm"):
+        p = tm.Plan(n, tile, map_name)
+        ms = timer.run(lambda: p.elementwise(tm.OP_XORMUL_I32, ad, bd, cd, ld=n), 2000, 50)
+        out[map_name] = round(ms * 1e3, 3)
+    return {"n": n, "tile": tile, "us_per_launch": out,
+            "I_lambda_vs_bb": round(out["bb"] / out["lambda"], 4)}
+
+
+def bench_life(tm, torch, timer, tile=32, steps=100):
+    from paper_1609_01490_amd import inputs
+    n = 16384
+    g = inputs.life(n, 0.3)
+    cur = torch.from_numpy(g).cuda()
+    nxt = torch.zeros_like(cur)
+    out = {}
+    for map_name in ("lambda", "bb"):
+        p = tm.Plan(n, tile, map_name)
+        ms = timer.run(lambda: p.stencil(cur, nxt, steps), 3, 1)
+        out[map_name] = ms
+    cells = n * (n + 1) // 2
+    del cur, nxt
+    torch.cuda.empty_cache()
+    return {"n": n, "tile": tile, "steps": steps,
+            "ms_100_steps": {k: round(v, 4) for k, v in out.items()},
+            "cell_updates_per_s": round(cells * steps / (out["lambda"] * 1e-3), 1),
+            "GBps_algorithmic": round(2 * cells * steps / (out["lambda"] * 1e-3) / 1e9, 1),
+            "I_lambda_vs_bb": round(out["bb"] / out["lambda"], 4)}
+
+
+def bench_edm(tm, torch, timer):
+    from paper_1609_01490_amd import inputs
+    n, d = 65536, 128
+    X, _ = inputs.points(n, d)
+    xd = torch.from_numpy(X).cuda()
+    out = torch.empty((n * (n - 1) // 2,), dtype=torch.float32, device="cuda")
+    pairs = n * (n - 1) // 2
+    res = {}
+    p = tm.Plan(n, 64, "lambda", include_diag=False)
+    ms = timer.run(lambda: p.edm(xd, out, mode=tm.EDM_FP32), 3, 1)
+    res["fp32_ms"] = round(ms, 4)
+    res["fp32_pairs_per_s"] = round(pairs / (ms * 1e-3), 1)
+    del xd, out
+    torch.cuda.empty_cache()
+    return {"n": n, "d": d, **res}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--tile", type=int, default=32)
+    ap.add_argument("--map", default="lambda")
+    ap.add_argument("--flags", type=int, default=0)
+    ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    from paper_1609_01490_amd import trimap as tm
+    timer = Timer(torch)
+
+    n, E, res, cpu = bench_elementwise(tm, torch, args, timer)
+    ms = res[args.map]
+    bytes_per_launch = 12 * E
+    achieved = bytes_per_launch / (ms * 1e-3) / 1e9
+    digest = src_digest("elementwise.hip", "maps.hpp")
+    traffic = traffic_from_profiles(f"axpyt_f32_n{n}_{args.map}_t{args.tile}", digest)
+
+    extra = {"I_lambda_vs_bb_elementwise": round(res["bb"] / ms, 4),
+             "bb_ms": round(res["bb"], 4), "src_digest": digest}
+    if not args.no_extra:
+        for name, fn in (("int32_n2048", lambda: bench_int_elementwise(tm, torch, timer)),
+                         ("life_n16384", lambda: bench_life(tm, torch, timer)),
+                         ("edm_n65536_d128", lambda: bench_edm(tm, torch, timer))):
+            log("extra", name)
+            try:
+                extra[name] = fn()
+            except Exception as e:  # keep the main line even if an extra fails
+                extra[name] = {"error": str(e)}
+
+    line = {
+        "metric": "elements/s + HBM GB/s %peak, λ(ω) vs bounding-box; "
+                  "EDM pairs/s BF16 vs FP32",
+        "value": E / (ms * 1e-3),
+        "unit": "elements/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"triangular elementwise C=a*X+Y^T, n={n} fp32 full storage, "
+                               f"lower triangle incl. diagonal ({E} cells), map {args.map}, "
+                               f"tile {args.tile}x{args.tile}",
+                   "n": n, "tile": args.tile, "map": args.map},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

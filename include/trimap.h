@@ -1,0 +1,170 @@
+/*
+ * trimap: triangular-domain GPU kernels driven by the block-space map
+ * lambda(omega), for AMD Instinct MI355X (gfx950).  C ABI.
+ *
+ * Method: C. A. Navarro, B. Bustos, N. Hitschfeld, "A Non-linear GPU Thread
+ * Map for Triangular Domains" (arXiv 1609.01490).
+ *
+ * Conventions common to every entry point
+ * ---------------------------------------
+ *  - Every function returns a tri_status; nothing aborts or exits.  On error
+ *    tri_last_error() returns a message for the calling thread.
+ *  - Pointers named dev_* / x / y / c / cur / nxt / out / ws are DEVICE
+ *    pointers owned by the caller; the library never frees them and never
+ *    allocates device memory inside a launch call.  Host pointers are named
+ *    explicitly (host_*).
+ *  - `stream` is a hipStream_t passed as void* (NULL: the null stream).  All
+ *    launches are asynchronous and ordered on that stream.
+ *  - Matrices are row-major with a leading dimension `ld` in ELEMENTS.
+ *  - Triangular domain of side n: cells (i, j) with 0 <= j <= i < n
+ *    (include_diag = 1) or 0 <= j < i < n (include_diag = 0).
+ *  - A plan is immutable after creation; concurrent launches of one plan on
+ *    different streams are safe.
+ */
+#ifndef TRIMAP_H
+#define TRIMAP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TRI_OK = 0,
+    TRI_E_INVAL = 1,       /* bad argument: null pointer, bad enum, ld < n, misalignment */
+    TRI_E_RANGE = 2,       /* sizes beyond the index or grid limits */
+    TRI_E_NOMEM = 3,       /* host allocation failed, or workspace too small */
+    TRI_E_HIP = 4,         /* a HIP runtime call failed (message kept) */
+    TRI_E_UNSUPPORTED = 5  /* valid request the library does not implement */
+} tri_status;
+
+/* Parallel-space maps (Section 4.2 of the paper; lambda: Section 3.1). */
+typedef enum {
+    TRI_MAP_BB = 0,     /* bounding box: m x m blocks, upper blocks discarded   */
+    TRI_MAP_RB = 1,     /* rectangular box: the triangle folded to a rectangle  */
+    TRI_MAP_REC = 2,    /* recursive partition (m a power of two)               */
+    TRI_MAP_UTM = 3,    /* upper-triangular map, thread space (Avril et al.)    */
+    TRI_MAP_LAMBDA = 4  /* lambda(omega): exactly m(m+1)/2 blocks (Eq. eq_gmap) */
+} tri_map;
+
+/* Plan flags (bit set). */
+enum {
+    TRI_FLAG_XCD_SWIZZLE = 1u, /* lambda: give each XCD a contiguous range of omega   */
+    TRI_FLAG_SQRT_RSQ = 2u,    /* lambda: sqrt(x) as x * rsq(x) (the paper's lambda_R) */
+    TRI_FLAG_SQRT_F64 = 4u     /* lambda: FP64 square root                             */
+};
+
+/* Elementwise bodies. */
+enum {
+    /* C[i][j] = (A[i] XOR B[j]) + i*j, uint32 wrap-around; x = A (uint32[n]),
+     * y = B (uint32[n]), c = C (int32 n x ld).  Dummy-kernel role, Section 4.1. */
+    TRI_OP_XORMUL_I32 = 0,
+    /* C[i][j] = fl(fl(a * X[i][j]) + Y[j][i]), two binary32 roundings, no
+     * fused multiply-add; x = X, y = Y, c = C (float n x ld each). */
+    TRI_OP_AXPYT_F32 = 1
+};
+
+/* Distance-map arithmetic. */
+enum {
+    TRI_EDM_FP32 = 0,   /* direct sum of squared differences in FP32                */
+    TRI_EDM_BF16X3 = 1, /* centred split-BF16 Gram on MFMA (hi*hi + hi*lo + lo*hi)  */
+    TRI_EDM_BF16 = 2    /* centred single-BF16 Gram on MFMA (faster, less accurate) */
+};
+
+typedef struct tri_plan tri_plan;
+
+typedef struct {
+    int64_t n;             /* side of the domain                                     */
+    int64_t tile;          /* rho: tile side in cells                                */
+    int64_t m;             /* tiles per side = ceil(n_eff / rho), n_eff = n or n-1    */
+    int64_t tiles;         /* m (m + 1) / 2                                          */
+    int64_t grid_x;        /* launch grid in blocks                                  */
+    int64_t grid_y;
+    int64_t grid_blocks;   /* grid_x * grid_y                                        */
+    int64_t wasted_blocks; /* blocks of the grid that map to no tile                 */
+    int64_t elements;      /* cells of the domain: n(n+1)/2 or n(n-1)/2              */
+    int64_t dump_entries;  /* entries written by tri_map_dump                         */
+    int32_t map;
+    int32_t include_diag;
+    uint32_t flags;
+    int32_t reserved;
+} tri_plan_info;
+
+/* Create a plan for a triangular domain of side n (0 <= n < 2^31) tiled in
+ * rho x rho tiles, rho in {8, 16, 32, 64}, under one of the five maps.
+ * Tile space (Section 3.1): m = ceil(n_eff / rho) tiles per side with
+ * n_eff = n (include_diag = 1) or n - 1 (include_diag = 0: the strict lower
+ * triangle is handled as the diagonal-including triangle of side n - 1
+ * shifted down one row, which is Eq. eq_theorem_nodiag at rho = 1).
+ * Grids: BB m x m; lambda 1-D of m(m+1)/2 blocks; RB m x (m+1)/2 (m odd) or
+ * (m+1) x m/2 (m even); REC m/2 x (m+1), m a power of two, else
+ * TRI_E_UNSUPPORTED; UTM one thread per cell (thread space).
+ * *out receives a host object freed by tri_plan_destroy. */
+tri_status tri_map_plan(tri_plan **out, int64_t n, int tile, int map, int include_diag,
+                        uint32_t flags);
+tri_status tri_plan_destroy(tri_plan *plan);
+tri_status tri_plan_query(const tri_plan *plan, tri_plan_info *info);
+
+/* Test hook: write the map itself.  Tile maps: for grid block
+ * b = by * grid_x + bx, dev_out[2b], dev_out[2b+1] = its tile (bi, bj) or
+ * (-1, -1) when discarded.  UTM: for thread k < elements, the cell (i, j).
+ * dev_out holds 2 * dump_entries int64. */
+tri_status tri_map_dump(const tri_plan *plan, int64_t *dev_out, void *stream);
+
+/* Test hook: lambda(omega) (include_diag = 1, Eq. eq_gmap) or its variant
+ * without diagonal (Eq. eq_theorem_nodiag), evaluated by the device code for
+ * count arbitrary omega < 2^60 from dev_omega (uint64); writes
+ * dev_out[2t], dev_out[2t+1] = (i, j).  flags selects the square root
+ * (TRI_FLAG_SQRT_*). */
+tri_status tri_lambda_eval(const uint64_t *dev_omega, int64_t count, int include_diag,
+                           uint32_t flags, int64_t *dev_out, void *stream);
+
+/* Apply an elementwise body to every cell of the plan's domain
+ * (include_diag must be 1).  Cells j > i and rows >= n are never written.
+ * Requirements: ld >= n; for TRI_OP_AXPYT_F32 x, y, c all n x ld with the
+ * same ld; for TRI_OP_XORMUL_I32 x, y hold n uint32 and c is n x ld int32.
+ * Rows are accessed 16 bytes at a time when ld % 4 == 0 and the matrix
+ * pointers are 16-byte aligned, one element at a time otherwise.
+ * `a` is used by TRI_OP_AXPYT_F32 only. */
+tri_status tri_launch_elementwise(const tri_plan *plan, int op, const void *x, const void *y,
+                                  void *c, int64_t ld, float a, void *stream);
+
+/* Game of Life B3/S23 on the lower triangle (include_diag must be 1; UTM
+ * is not supported: it has no 2-D block to stage a halo in).  cur and nxt
+ * are uint8 n x ld grids whose domain cells hold 0 or 1; cells above the
+ * diagonal are treated as dead whatever they hold, and are never written.
+ * Runs `steps` synchronous generations, reading cur and writing nxt, then
+ * the other way round: the result is in cur when steps is even, in nxt when
+ * odd.  Requires ld % 4 == 0, ld >= n, 4-byte aligned pointers, steps >= 0.
+ * Each generation is one kernel launch; when use_graph is non-zero the
+ * launches are captured once into a hipGraph and replayed. */
+tri_status tri_launch_stencil(const tri_plan *plan, uint8_t *cur, uint8_t *nxt, int64_t ld,
+                              int steps, int use_graph, void *stream);
+
+/* Euclidean distance map (the EDM test of Section 5): for the plan's strict
+ * lower triangle (include_diag must be 0; map BB or LAMBDA), writes
+ * d(i, j) = sqrt(sum_k (x_ik - x_jk)^2) in FP32 to out[i(i-1)/2 + j] (the
+ * condensed strict lower triangle, n(n-1)/2 floats).  x is n x d FP32,
+ * leading dimension ldx >= d.  mode is a TRI_EDM_* value.  For the MFMA
+ * modes distances whose Gram-based square is below fixup_thr are recomputed
+ * directly in FP32 from x.  ws is a device workspace of at least
+ * tri_edm_workspace_size() bytes (may be NULL when that size is 0).
+ * Supported: d <= 4096, tile 16/32/64 (FP32) or 64/128... see
+ * tri_edm_workspace_size, which returns TRI_E_UNSUPPORTED for a plan the
+ * mode cannot run. */
+tri_status tri_edm_workspace_size(const tri_plan *plan, int64_t d, int mode, size_t *bytes);
+tri_status tri_edm(const tri_plan *plan, const float *x, int64_t d, int64_t ldx, float *out,
+                   int mode, float fixup_thr, void *ws, size_t ws_bytes, void *stream);
+
+/* Human-readable name of a status, and the last error message of the
+ * calling thread ("" if none). */
+const char *tri_status_str(tri_status st);
+const char *tri_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TRIMAP_H */

@@ -1,0 +1,264 @@
+// Triangular elementwise kernels: one workgroup per tile rho x rho, the tile
+// chosen by a parallel-space map (block-space mapping, Section 3.1: the
+// block coordinate is mapped, each thread adds its offset inside the block).
+//
+//  * AXPYT_F32: C[i][j] = fl(fl(a X[i][j]) + Y[j][i]) for j <= i.  The mirror
+//    tile of Y is read row-major (coalesced) and transposed through LDS.
+//  * XORMUL_I32: C[i][j] = (A[i] xor B[j]) + i j (mod 2^32), the dummy
+//    kernel of Section 4.1 with a real per-cell store.
+//
+// Both are HBM-bound: 12 B (fp32) or 4 B (int32) of algorithmic traffic per
+// cell.  Rows move as 16-byte vectors; stores are non-temporal (the output
+// is not re-read).  UTM (thread space) has no tile and gets its own scalar
+// kernel, reading Y[j][i] straight from memory as the map implies.
+#include "common.hpp"
+#include "maps.hpp"
+
+namespace trimap {
+
+TileGrid plan_tile_grid(const tri_plan *p);
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef int i4 __attribute__((ext_vector_type(4)));
+
+struct ElemArgs {
+    TileGrid g;
+    int32_t n;
+    int64_t ld;
+    const void *x;
+    const void *y;
+    void *c;
+    float a;
+};
+
+// threads per workgroup and elements per vector for a tile size
+template <int TILE, bool VECTOR>
+struct ElemShape {
+    static constexpr int VEC = (VECTOR && TILE >= 16) ? 4 : 1;
+    static constexpr int NT_RAW = TILE * TILE / VEC;
+    static constexpr int NT = NT_RAW > 256 ? 256 : NT_RAW;
+    static constexpr int VPR = TILE / VEC;    // vectors per row
+    static constexpr int RPP = NT / VPR;      // rows per pass
+    static constexpr int PASSES = TILE / RPP;
+    static_assert(RPP * PASSES == TILE, "tile shape");
+};
+
+template <int MAP, int TILE, bool VECTOR>
+__global__ void __launch_bounds__((ElemShape<TILE, VECTOR>::NT)) k_axpyt(ElemArgs p)
+{
+    using S = ElemShape<TILE, VECTOR>;
+    int32_t bi, bj;
+    if (!tile_of_block<MAP>(p.g, bi, bj)) return;
+
+    __shared__ float ys[TILE][TILE + 1];
+    const int tr = threadIdx.x / S::VPR;
+    const int tc = (threadIdx.x % S::VPR) * S::VEC;
+    const int32_t n = p.n;
+    const int64_t ld = p.ld;
+    const int32_t i0 = bi * TILE, j0 = bj * TILE;
+    const float *X = (const float *)p.x;
+    const float *Y = (const float *)p.y;
+    float *C = (float *)p.c;
+    const float a = p.a;
+    // every cell of the tile is in the domain
+    const bool full = (bj < bi) && (i0 + TILE <= n);
+
+    // mirror tile of Y: rows j0.., columns i0.. ; Y[j][i] lands in ys[j-j0][i-i0]
+#pragma unroll
+    for (int ps = 0; ps < S::PASSES; ++ps) {
+        const int r = tr + ps * S::RPP;
+        const int32_t jr = j0 + r, ic = i0 + tc;
+        const bool need = full || (ic < n && jr < n && jr <= ic + S::VEC - 1);
+        if constexpr (S::VEC == 4) {
+            f4 v = {0.f, 0.f, 0.f, 0.f};
+            if (need) v = __builtin_nontemporal_load((const f4 *)(Y + (int64_t)jr * ld + ic));
+            ys[r][tc + 0] = v.x;
+            ys[r][tc + 1] = v.y;
+            ys[r][tc + 2] = v.z;
+            ys[r][tc + 3] = v.w;
+        } else {
+            ys[r][tc] = need ? __builtin_nontemporal_load(Y + (int64_t)jr * ld + ic) : 0.f;
+        }
+    }
+    __syncthreads();
+
+#pragma unroll
+    for (int ps = 0; ps < S::PASSES; ++ps) {
+        const int r = tr + ps * S::RPP;
+        const int32_t i = i0 + r, jc = j0 + tc;
+        if (!full && (i >= n || jc > i)) continue;
+        float *crow = C + (int64_t)i * ld + jc;
+        const float *xrow = X + (int64_t)i * ld + jc;
+        if constexpr (S::VEC == 4) {
+            const f4 xv = __builtin_nontemporal_load((const f4 *)xrow);
+            f4 o;
+            o.x = __fadd_rn(__fmul_rn(a, xv.x), ys[tc + 0][r]);
+            o.y = __fadd_rn(__fmul_rn(a, xv.y), ys[tc + 1][r]);
+            o.z = __fadd_rn(__fmul_rn(a, xv.z), ys[tc + 2][r]);
+            o.w = __fadd_rn(__fmul_rn(a, xv.w), ys[tc + 3][r]);
+            if (full || jc + 3 <= i) {
+                __builtin_nontemporal_store(o, (f4 *)crow);
+            } else {  // the vector straddles the diagonal
+                crow[0] = o.x;
+                if (jc + 1 <= i) crow[1] = o.y;
+                if (jc + 2 <= i) crow[2] = o.z;
+            }
+        } else {
+            const float xv = __builtin_nontemporal_load(xrow);
+            __builtin_nontemporal_store(__fadd_rn(__fmul_rn(a, xv), ys[tc][r]), crow);
+        }
+    }
+}
+
+template <int MAP, int TILE, bool VECTOR>
+__global__ void __launch_bounds__((ElemShape<TILE, VECTOR>::NT)) k_xormul(ElemArgs p)
+{
+    using S = ElemShape<TILE, VECTOR>;
+    int32_t bi, bj;
+    if (!tile_of_block<MAP>(p.g, bi, bj)) return;
+
+    const int tr = threadIdx.x / S::VPR;
+    const int tc = (threadIdx.x % S::VPR) * S::VEC;
+    const int32_t n = p.n;
+    const int64_t ld = p.ld;
+    const int32_t i0 = bi * TILE, j0 = bj * TILE;
+    const uint32_t *A = (const uint32_t *)p.x;
+    const uint32_t *B = (const uint32_t *)p.y;
+    int32_t *C = (int32_t *)p.c;
+    const bool full = (bj < bi) && (i0 + TILE <= n);
+
+#pragma unroll
+    for (int ps = 0; ps < S::PASSES; ++ps) {
+        const int r = tr + ps * S::RPP;
+        const int32_t i = i0 + r, jc = j0 + tc;
+        if (!full && (i >= n || jc > i)) continue;
+        const uint32_t ai = A[i];
+        int32_t *crow = C + (int64_t)i * ld + jc;
+        if constexpr (S::VEC == 4) {
+            // B[jc .. jc+3]: jc + 3 may pass n on the last tile row, so read
+            // element by element there (B holds exactly n values)
+            uint32_t b0 = B[jc], b1 = 0, b2 = 0, b3 = 0;
+            if (full || jc + 3 < n) { b1 = B[jc + 1]; b2 = B[jc + 2]; b3 = B[jc + 3]; }
+            else {
+                if (jc + 1 < n) b1 = B[jc + 1];
+                if (jc + 2 < n) b2 = B[jc + 2];
+            }
+            const uint32_t ui = (uint32_t)i;
+            i4 o;
+            o.x = (int32_t)((ai ^ b0) + ui * (uint32_t)(jc + 0));
+            o.y = (int32_t)((ai ^ b1) + ui * (uint32_t)(jc + 1));
+            o.z = (int32_t)((ai ^ b2) + ui * (uint32_t)(jc + 2));
+            o.w = (int32_t)((ai ^ b3) + ui * (uint32_t)(jc + 3));
+            if (full || jc + 3 <= i) {
+                __builtin_nontemporal_store(o, (i4 *)crow);
+            } else {
+                crow[0] = o.x;
+                if (jc + 1 <= i) crow[1] = o.y;
+                if (jc + 2 <= i) crow[2] = o.z;
+            }
+        } else {
+            const uint32_t v = (ai ^ B[jc]) + (uint32_t)i * (uint32_t)jc;
+            __builtin_nontemporal_store((int32_t)v, crow);
+        }
+    }
+}
+
+// UTM: thread k owns cell utm_cell(k); no tile, no LDS.
+template <int OP>
+__global__ void __launch_bounds__(kUtmThreads) k_elem_utm(ElemArgs p, int64_t elements)
+{
+    const uint64_t k = ((uint64_t)blockIdx.y * gridDim.x + blockIdx.x) * kUtmThreads + threadIdx.x;
+    if (k >= (uint64_t)elements) return;
+    int32_t i, j;
+    utm_cell(k, p.n, i, j);
+    if ((uint32_t)i >= (uint32_t)p.n || (uint32_t)j > (uint32_t)i) return;
+    const int64_t ld = p.ld;
+    if constexpr (OP == TRI_OP_AXPYT_F32) {
+        const float *X = (const float *)p.x;
+        const float *Y = (const float *)p.y;
+        ((float *)p.c)[(int64_t)i * ld + j] =
+            __fadd_rn(__fmul_rn(p.a, X[(int64_t)i * ld + j]), Y[(int64_t)j * ld + i]);
+    } else {
+        const uint32_t *A = (const uint32_t *)p.x;
+        const uint32_t *B = (const uint32_t *)p.y;
+        ((int32_t *)p.c)[(int64_t)i * ld + j] =
+            (int32_t)((A[i] ^ B[j]) + (uint32_t)i * (uint32_t)j);
+    }
+}
+
+template <int OP, int MAP, int TILE, bool VECTOR>
+static void launch_tile(const tri_plan *p, const ElemArgs &args, hipStream_t s)
+{
+    const dim3 grid(p->gx, p->gy);
+    constexpr int NT = ElemShape<TILE, VECTOR>::NT;
+    if constexpr (OP == TRI_OP_AXPYT_F32)
+        k_axpyt<MAP, TILE, VECTOR><<<grid, NT, 0, s>>>(args);
+    else
+        k_xormul<MAP, TILE, VECTOR><<<grid, NT, 0, s>>>(args);
+}
+
+template <int OP, int MAP, bool VECTOR>
+static bool dispatch_tile(const tri_plan *p, const ElemArgs &args, hipStream_t s)
+{
+    switch (p->tile) {
+    case 8: launch_tile<OP, MAP, 8, VECTOR>(p, args, s); return true;
+    case 16: launch_tile<OP, MAP, 16, VECTOR>(p, args, s); return true;
+    case 32: launch_tile<OP, MAP, 32, VECTOR>(p, args, s); return true;
+    case 64: launch_tile<OP, MAP, 64, VECTOR>(p, args, s); return true;
+    }
+    return false;
+}
+
+template <int OP, bool VECTOR>
+static bool dispatch_map(const tri_plan *p, const ElemArgs &args, hipStream_t s)
+{
+    switch (p->map) {
+    case TRI_MAP_BB: return dispatch_tile<OP, MAP_BB, VECTOR>(p, args, s);
+    case TRI_MAP_RB: return dispatch_tile<OP, MAP_RB, VECTOR>(p, args, s);
+    case TRI_MAP_REC: return dispatch_tile<OP, MAP_REC, VECTOR>(p, args, s);
+    case TRI_MAP_LAMBDA: return dispatch_tile<OP, MAP_LAMBDA, VECTOR>(p, args, s);
+    case TRI_MAP_UTM:
+        k_elem_utm<OP><<<dim3(p->gx, p->gy), kUtmThreads, 0, s>>>(args, p->elements);
+        return true;
+    }
+    return false;
+}
+
+}  // namespace trimap
+
+using namespace trimap;
+
+extern "C" tri_status tri_launch_elementwise(const tri_plan *p, int op, const void *x,
+                                             const void *y, void *c, int64_t ld, float a,
+                                             void *stream)
+{
+    clear_error();
+    if (!p) return fail(TRI_E_INVAL, "tri_launch_elementwise: plan is NULL");
+    if (op != TRI_OP_XORMUL_I32 && op != TRI_OP_AXPYT_F32)
+        return fail(TRI_E_INVAL, "tri_launch_elementwise: op = %d", op);
+    if (!p->diag)
+        return fail(TRI_E_UNSUPPORTED, "tri_launch_elementwise: needs include_diag = 1");
+    if (p->tile > 64)
+        return fail(TRI_E_UNSUPPORTED, "tri_launch_elementwise: tile %d > 64", p->tile);
+    if (p->n == 0) return TRI_OK;
+    if (!x || !y || !c) return fail(TRI_E_INVAL, "tri_launch_elementwise: NULL buffer");
+    if (ld < p->n) return fail(TRI_E_INVAL, "tri_launch_elementwise: ld %lld < n %lld",
+                               (long long)ld, (long long)p->n);
+    const uintptr_t cx = (uintptr_t)c, xx = (uintptr_t)x, yx = (uintptr_t)y;
+    if ((cx | xx | yx) & 3) return fail(TRI_E_INVAL, "tri_launch_elementwise: unaligned buffer");
+    bool vector = (ld % 4 == 0) && ((cx & 15) == 0);
+    if (op == TRI_OP_AXPYT_F32) vector = vector && ((xx & 15) == 0) && ((yx & 15) == 0);
+
+    ElemArgs args{plan_tile_grid(p), (int32_t)p->n, ld, x, y, c, a};
+    hipStream_t s = (hipStream_t)stream;
+    bool ok;
+    if (op == TRI_OP_AXPYT_F32)
+        ok = vector ? dispatch_map<TRI_OP_AXPYT_F32, true>(p, args, s)
+                    : dispatch_map<TRI_OP_AXPYT_F32, false>(p, args, s);
+    else
+        ok = vector ? dispatch_map<TRI_OP_XORMUL_I32, true>(p, args, s)
+                    : dispatch_map<TRI_OP_XORMUL_I32, false>(p, args, s);
+    if (!ok) return fail(TRI_E_UNSUPPORTED, "tri_launch_elementwise: tile %d", p->tile);
+    TRI_HIP(hipGetLastError());
+    return TRI_OK;
+}

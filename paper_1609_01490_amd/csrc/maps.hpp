@@ -1,0 +1,160 @@
+// Device side of the parallel-space maps: grid block -> tile (bi, bj) of the
+// lower triangle of an m x m tile grid (0 <= bj <= bi < m), and the
+// thread-space UTM map.  Each map is a self-contained function with no side
+// effects (Section 6 of the paper makes this point for lambda).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "trimap.h"
+
+namespace trimap {
+
+// Uniform description of the tile grid handed to every tile kernel.
+struct TileGrid {
+    int32_t m;       // tiles per side
+    uint32_t flags;  // TRI_FLAG_*
+    uint64_t T;      // tiles, m (m + 1) / 2
+};
+
+// ---------------------------------------------------------------------------
+// lambda(omega), Eq. eq_gmap: row i = floor((sqrt(8 omega + 1) - 1) / 2),
+// column j = omega - i (i + 1) / 2.
+//
+// The square root is taken in floating point and the row is then corrected
+// by one integer step so that T_i <= omega < T_{i+1} (T_i = i (i + 1) / 2).
+// For omega < 2^32 the FP32 estimate is within 0.05 of the true row (8w+1 is
+// rounded twice to 24 bits, the hardware square root adds at most a few
+// units in the last place, and the row is below 2^16.5), so one step makes
+// it exact; that is why no epsilon is added as in the paper's lambda_N and
+// lambda_R.  omega >= 2^32 always takes the FP64 root.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t lambda_row(uint64_t w, uint32_t flags)
+{
+    int32_t r;
+    if ((flags & TRI_FLAG_SQRT_F64) || (w >> 32)) {
+        double s = __builtin_sqrt(8.0 * (double)w + 1.0);
+        r = (int32_t)((s - 1.0) * 0.5);
+    } else {
+        float x = __builtin_fmaf(8.0f, (float)(uint32_t)w, 1.0f);
+        float s = (flags & TRI_FLAG_SQRT_RSQ) ? x * __builtin_amdgcn_rsqf(x)
+                                              : __builtin_amdgcn_sqrtf(x);
+        r = (int32_t)((s - 1.0f) * 0.5f);
+    }
+    uint32_t i = r < 0 ? 0u : (uint32_t)r;
+    uint64_t t = (uint64_t)i * (i + 1) / 2;  // first block of row i
+    if (t > w)
+        --i;
+    else if (t + i + 1 <= w)
+        ++i;
+    return i;
+}
+
+__device__ __forceinline__ void lambda_tile(uint64_t w, uint32_t flags, int32_t &bi, int32_t &bj)
+{
+    uint32_t i = lambda_row(w, flags);
+    bi = (int32_t)i;
+    bj = (int32_t)(w - (uint64_t)i * (i + 1) / 2);
+}
+
+// Give each of the 8 XCDs a contiguous range of omega.  Workgroups are
+// dispatched to XCDs round-robin by linear id; block L runs on XCD L mod 8.
+// With G = 8q + r blocks, XCD x holds q + (x < r) blocks, so its range starts
+// at x q + min(x, r).  A bijection of [0, G).
+__device__ __forceinline__ uint64_t xcd_swizzle(uint64_t L, uint64_t G)
+{
+    uint64_t x = L & 7, l = L >> 3, q = G >> 3, r = G & 7;
+    return x * q + (x < r ? x : r) + l;
+}
+
+enum { MAP_BB = TRI_MAP_BB, MAP_RB = TRI_MAP_RB, MAP_REC = TRI_MAP_REC,
+       MAP_UTM = TRI_MAP_UTM, MAP_LAMBDA = TRI_MAP_LAMBDA };
+
+// Tile of this workgroup under a tile-space map, or false when the block is
+// discarded.  BB, RB and REC use a 2-D grid (blockIdx.x = column); lambda a
+// 1-D grid (2-D only when the tile count exceeds one grid dimension).
+template <int MAP>
+__device__ __forceinline__ bool tile_of_block_raw(const TileGrid &g, int32_t &bi, int32_t &bj)
+{
+    const int32_t bx = (int32_t)blockIdx.x, by = (int32_t)blockIdx.y;
+    if constexpr (MAP == MAP_BB) {
+        // Section 4.2: the block test (on or below the diagonal) comes before
+        // any thread coordinate is formed.
+        if (bx > by) return false;
+        bi = by;
+        bj = bx;
+        return true;
+    } else if constexpr (MAP == MAP_RB) {
+        const int32_t m = g.m;
+        if (m & 1) {
+            if (bx < by) { bi = by - 1; bj = bx; }
+            else { bi = m - 1 - by; bj = m - 1 - bx; }
+        } else {
+            if (bx <= by) { bi = by; bj = bx; }
+            else { bi = m - 1 - by; bj = bx - by - 1; }
+        }
+        return true;
+    } else if constexpr (MAP == MAP_REC) {
+        const int32_t m = g.m;
+        if (m == 1) { bi = bj = 0; return true; }
+        if (by >= m - 1) {  // the diagonal pass: two grid rows of m/2 tiles
+            bi = bj = (by - (m - 1)) * (m >> 1) + bx;
+            return true;
+        }
+        const int32_t lg = 31 - __builtin_clz((uint32_t)(by + 1));  // level: side s = 2^lg
+        const int32_t s = 1 << lg;
+        const int32_t r = by - (s - 1);
+        const int32_t q = bx >> lg, c = bx & (s - 1);
+        bi = q * 2 * s + s + r;
+        bj = q * 2 * s + c;
+        return true;
+    } else {  // MAP_LAMBDA
+        uint64_t L = (uint64_t)blockIdx.y * gridDim.x + blockIdx.x;
+        if (g.flags & TRI_FLAG_XCD_SWIZZLE)
+            L = xcd_swizzle(L, (uint64_t)gridDim.x * gridDim.y);
+        if (L >= g.T) return false;
+        lambda_tile(L, g.flags, bi, bj);
+        return true;
+    }
+}
+
+// Same, plus a range check (0 <= bj <= bi < m) so that no kernel can address
+// memory outside the domain's rows whatever a map returns.
+template <int MAP>
+__device__ __forceinline__ bool tile_of_block(const TileGrid &g, int32_t &bi, int32_t &bj)
+{
+    if (!tile_of_block_raw<MAP>(g, bi, bj)) return false;
+    return (uint32_t)bi < (uint32_t)g.m && (uint32_t)bj <= (uint32_t)bi;
+}
+
+// ---------------------------------------------------------------------------
+// UTM (Section 4.2, Avril et al.): thread k of a problem of size N owns the
+// k-th pair (a, b), 1 <= a < b <= N, in lexicographic order:
+//   a = floor((2N + 1 - sqrt(4N^2 - 4N - 8k + 1)) / 2),
+//   b = a + 1 + k - (a - 1)(2N - a) / 2.
+// The root is taken in FP32 and a is corrected by integer steps against
+// the row starts S(a) = (a - 1)(2N - a) / 2, which removes the accuracy limit
+// of the original (k <= 1e8).  A lower-triangle cell is then
+//   (i, j) = (N - 1 - a, N - b)   with N = side + 1,
+// which enumerates 0 <= j <= i < side (consecutive k: consecutive j).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void utm_cell(uint64_t k, int64_t side, int32_t &i, int32_t &j)
+{
+    const int64_t N = side + 1;
+    const double Dd = 4.0 * (double)N * (double)N - 4.0 * (double)N - 8.0 * (double)k + 1.0;
+    const float s = __builtin_amdgcn_sqrtf((float)Dd);
+    int64_t a = (int64_t)(((double)(2 * N + 1) - (double)s) * 0.5);
+    a = a < 1 ? 1 : (a > N - 1 ? N - 1 : a);
+    auto S = [N](int64_t aa) { return (aa - 1) * (2 * N - aa) / 2; };
+    // S is strictly increasing on [1, N), so both loops end; for the sizes
+    // a 32-bit grid can reach they run at most once.
+    while (a > 1 && S(a) > (int64_t)k) --a;
+    while (a < N - 1 && S(a + 1) <= (int64_t)k) ++a;
+    const int64_t b = a + 1 + (int64_t)k - S(a);
+    i = (int32_t)(N - 1 - a);
+    j = (int32_t)(N - b);
+}
+
+}  // namespace trimap

@@ -1,0 +1,193 @@
+"""Python binding of libtrimap.so: argument marshalling only.
+
+Every step of the triangular-domain path runs in the HIP library; this module
+turns torch tensors into device pointers, picks the current HIP stream, and
+turns a non-zero tri_status into an exception.  PyTorch provides device
+memory and streams, nothing else.  There is no fallback: if the library is
+missing, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtrimap.so")
+
+BB, RB, REC, UTM, LAMBDA = 0, 1, 2, 3, 4
+MAPS = {"bb": BB, "rb": RB, "rec": REC, "utm": UTM, "lambda": LAMBDA}
+MAP_NAMES = {v: k for k, v in MAPS.items()}
+
+FLAG_XCD_SWIZZLE, FLAG_SQRT_RSQ, FLAG_SQRT_F64 = 1, 2, 4
+OP_XORMUL_I32, OP_AXPYT_F32 = 0, 1
+EDM_FP32, EDM_BF16X3, EDM_BF16 = 0, 1, 2
+
+OK, E_INVAL, E_RANGE, E_NOMEM, E_HIP, E_UNSUPPORTED = range(6)
+
+
+class TrimapError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{status_str(status)}: {msg}")
+        self.status = status
+
+
+class tri_plan_info(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int64) for name in (
+        "n", "tile", "m", "tiles", "grid_x", "grid_y", "grid_blocks", "wasted_blocks",
+        "elements", "dump_entries")] + [
+        ("map", ctypes.c_int32), ("include_diag", ctypes.c_int32),
+        ("flags", ctypes.c_uint32), ("reserved", ctypes.c_int32)]
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_1609_01490_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    i64, u32, vp, i32 = ctypes.c_int64, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_int
+    st = ctypes.c_int
+    L.tri_map_plan.restype = st
+    L.tri_map_plan.argtypes = [ctypes.POINTER(vp), i64, i32, i32, i32, u32]
+    L.tri_plan_destroy.restype = st
+    L.tri_plan_destroy.argtypes = [vp]
+    L.tri_plan_query.restype = st
+    L.tri_plan_query.argtypes = [vp, ctypes.POINTER(tri_plan_info)]
+    L.tri_map_dump.restype = st
+    L.tri_map_dump.argtypes = [vp, vp, vp]
+    L.tri_lambda_eval.restype = st
+    L.tri_lambda_eval.argtypes = [vp, i64, i32, u32, vp, vp]
+    L.tri_launch_elementwise.restype = st
+    L.tri_launch_elementwise.argtypes = [vp, i32, vp, vp, vp, i64, ctypes.c_float, vp]
+    L.tri_launch_stencil.restype = st
+    L.tri_launch_stencil.argtypes = [vp, vp, vp, i64, i32, i32, vp]
+    L.tri_edm_workspace_size.restype = st
+    L.tri_edm_workspace_size.argtypes = [vp, i64, i32, ctypes.POINTER(ctypes.c_size_t)]
+    L.tri_edm.restype = st
+    L.tri_edm.argtypes = [vp, vp, i64, i64, vp, i32, ctypes.c_float, vp, ctypes.c_size_t, vp]
+    L.tri_status_str.restype = ctypes.c_char_p
+    L.tri_status_str.argtypes = [st]
+    L.tri_last_error.restype = ctypes.c_char_p
+    L.tri_last_error.argtypes = []
+    return L
+
+
+lib = _load()
+
+
+def status_str(status: int) -> str:
+    return lib.tri_status_str(status).decode()
+
+
+def _check(status: int):
+    if status != OK:
+        raise TrimapError(status, lib.tri_last_error().decode())
+
+
+def _stream(stream=None) -> int | None:
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+def _dptr(t) -> int:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    return t.data_ptr()
+
+
+@dataclass
+class PlanInfo:
+    n: int
+    tile: int
+    m: int
+    tiles: int
+    grid_x: int
+    grid_y: int
+    grid_blocks: int
+    wasted_blocks: int
+    elements: int
+    dump_entries: int
+    map: int
+    include_diag: int
+    flags: int
+
+
+class Plan:
+    """A tile space of a triangular domain under one map (tri_map_plan)."""
+
+    def __init__(self, n: int, tile: int = 32, map: int | str = LAMBDA,
+                 include_diag: bool = True, flags: int = 0):
+        if isinstance(map, str):
+            map = MAPS[map]
+        h = ctypes.c_void_p()
+        _check(lib.tri_map_plan(ctypes.byref(h), int(n), int(tile), int(map),
+                                1 if include_diag else 0, int(flags)))
+        self._h = h
+        info = tri_plan_info()
+        _check(lib.tri_plan_query(h, ctypes.byref(info)))
+        self.info = PlanInfo(**{f: getattr(info, f) for f in PlanInfo.__dataclass_fields__})
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            lib.tri_plan_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __repr__(self):
+        i = self.info
+        return (f"Plan(n={i.n}, tile={i.tile}, map={MAP_NAMES[i.map]}, diag={i.include_diag}, "
+                f"m={i.m}, tiles={i.tiles}, grid={i.grid_x}x{i.grid_y})")
+
+    # -- test hooks -------------------------------------------------------
+    def dump(self, stream=None):
+        import torch
+        out = torch.empty((self.info.dump_entries, 2), dtype=torch.int64, device="cuda")
+        if self.info.dump_entries:
+            _check(lib.tri_map_dump(self._h, _dptr(out), _stream(stream)))
+        return out
+
+    # -- kernels ----------------------------------------------------------
+    def elementwise(self, op: int, x, y, c, ld: int | None = None, a: float = 0.0,
+                    stream=None):
+        ld = c.stride(0) if ld is None else ld
+        _check(lib.tri_launch_elementwise(self._h, int(op), _dptr(x), _dptr(y), _dptr(c),
+                                          int(ld), float(a), _stream(stream)))
+
+    def stencil(self, cur, nxt, steps: int, ld: int | None = None, use_graph: bool = False,
+                stream=None):
+        ld = cur.stride(0) if ld is None else ld
+        _check(lib.tri_launch_stencil(self._h, _dptr(cur), _dptr(nxt), int(ld), int(steps),
+                                      1 if use_graph else 0, _stream(stream)))
+
+    def edm_workspace_size(self, d: int, mode: int) -> int:
+        b = ctypes.c_size_t()
+        _check(lib.tri_edm_workspace_size(self._h, int(d), int(mode), ctypes.byref(b)))
+        return b.value
+
+    def edm(self, x, out, mode: int = EDM_FP32, fixup_thr: float = 1e-2, ws=None,
+            stream=None):
+        d = x.shape[1]
+        wsb = 0 if ws is None else ws.numel() * ws.element_size()
+        _check(lib.tri_edm(self._h, _dptr(x), int(d), int(x.stride(0)), _dptr(out), int(mode),
+                           float(fixup_thr), _dptr(ws), int(wsb), _stream(stream)))
+
+
+def lambda_eval(omega, include_diag: bool = True, flags: int = 0, stream=None):
+    """Device lambda(omega) for a uint64/int64 device tensor of omegas."""
+    import torch
+    out = torch.empty((omega.numel(), 2), dtype=torch.int64, device=omega.device)
+    _check(lib.tri_lambda_eval(_dptr(omega), int(omega.numel()), 1 if include_diag else 0,
+                               int(flags), _dptr(out), _stream(stream)))
+    return out

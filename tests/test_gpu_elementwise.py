@@ -1,0 +1,140 @@
+"""GPU parity of the triangular elementwise kernels against the oracle:
+bit-exact on every cell of the domain, cells above the diagonal untouched,
+for every map and tile size, ragged sizes, aligned (16-byte vector) and
+unaligned (scalar) leading dimensions, and at full size (n = 32768 fp32)."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import dev, host, note, padded_ld
+from paper_1609_01490_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+MAPS = ["bb", "rb", "rec", "utm", "lambda"]
+SIZES = [1, 2, 3, 17, 64, 100, 257, 300, 1024]
+
+
+def _tm():
+    from paper_1609_01490_amd import trimap
+    return trimap
+
+
+def _plan_or_none(tm, n, tile, map_name):
+    m = -(-n // tile)
+    if map_name == "rec" and (m & (m - 1)):
+        return None
+    return tm.Plan(n, tile, map_name)
+
+
+def _low(n, ld):
+    r = np.arange(n)[:, None]
+    c = np.arange(ld)[None, :]
+    return c <= r
+
+
+@pytest.mark.parametrize("map_name", MAPS)
+@pytest.mark.parametrize("tile", [8, 16, 32, 64])
+def test_xormul_i32_bit_exact(map_name, tile):
+    tm = _tm()
+    for n in SIZES:
+        for ld in sorted({n, padded_ld(n), padded_ld(n) + 4}):
+            p = _plan_or_none(tm, n, tile, map_name)
+            if p is None:
+                continue
+            A, B, C0 = inputs.int_elementwise(n, seed=1000 + n, ld=ld)
+            exp = C0.copy()
+            oracle.c0(A, B, exp)
+            note("xormul", map_name, tile, n, ld)
+            c = dev(C0)
+            p.elementwise(tm.OP_XORMUL_I32, dev(A), dev(B), c, ld=ld)
+            got = host(c)
+            assert (got.view(np.uint32) == exp.view(np.uint32)).all(), (map_name, tile, n, ld)
+
+
+@pytest.mark.parametrize("map_name", MAPS)
+@pytest.mark.parametrize("tile", [8, 16, 32, 64])
+def test_axpyt_f32_bit_exact(map_name, tile):
+    tm = _tm()
+    for n in SIZES:
+        for ld in sorted({n, padded_ld(n)}):
+            p = _plan_or_none(tm, n, tile, map_name)
+            if p is None:
+                continue
+            a, X, Y, C0 = inputs.f32_elementwise(n, seed=2000 + n, ld=ld)
+            exp = C0.copy()
+            oracle.c1(a, X, Y, exp, n=n)
+            note("axpyt", map_name, tile, n, ld)
+            c = dev(C0)
+            p.elementwise(tm.OP_AXPYT_F32, dev(X), dev(Y), c, ld=ld, a=float(a))
+            got = host(c)
+            assert (got.view(np.uint32) == exp.view(np.uint32)).all(), (map_name, tile, n, ld)
+
+
+def test_empty_domain_is_a_no_op():
+    import torch
+    tm = _tm()
+    p = tm.Plan(0, 16, "lambda")
+    c = torch.zeros(4, device="cuda")
+    p.elementwise(tm.OP_AXPYT_F32, c, c, c, ld=1, a=1.0)
+    assert host(c).sum() == 0
+
+
+def test_argument_errors():
+    import torch
+    tm = _tm()
+    p = tm.Plan(64, 16, "lambda")
+    x = torch.zeros((64, 64), device="cuda")
+    with pytest.raises(tm.TrimapError) as e:
+        p.elementwise(tm.OP_AXPYT_F32, x, x, x, ld=63, a=1.0)
+    assert e.value.status == tm.E_INVAL
+    with pytest.raises(tm.TrimapError) as e:
+        p.elementwise(7, x, x, x, ld=64)
+    assert e.value.status == tm.E_INVAL
+    q = tm.Plan(64, 16, "lambda", include_diag=False)
+    with pytest.raises(tm.TrimapError) as e:
+        q.elementwise(tm.OP_AXPYT_F32, x, x, x, ld=64, a=1.0)
+    assert e.value.status == tm.E_UNSUPPORTED
+
+
+@pytest.fixture(scope="module")
+def full_inputs():
+    import torch
+    n = 32768
+    a, X, Y, _ = inputs.f32_elementwise(n, with_fill=False)
+    note("axpyt full inputs", n)
+    xd, yd = dev(X), dev(Y)
+    yield n, a, X, Y, xd, yd
+    del xd, yd
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("map_name,tile", [("lambda", 32), ("bb", 32), ("lambda", 16)])
+def test_axpyt_full_size_sampled_rows(full_inputs, map_name, tile):
+    """n = 32768 (12 GiB of operands), the configuration the benchmark times;
+    64 sampled rows plus the first and last rows are checked bit for bit
+    against the oracle, and the upper part of those rows is untouched."""
+    import torch
+    tm = _tm()
+    n, a, X, Y, xd, yd = full_inputs
+    note("axpyt full", map_name, tile, n)
+    fill = np.float32(-7.5)
+    c = torch.full((n, n), float(fill), dtype=torch.float32, device="cuda")
+    p = tm.Plan(n, tile, map_name)
+    p.elementwise(tm.OP_AXPYT_F32, xd, yd, c, ld=n, a=float(a))
+    torch.cuda.synchronize()
+    rows = np.concatenate([[0, 1, n - 1], np.random.default_rng(14).choice(n, 64, replace=False)])
+    for r in rows.tolist():
+        got = c[r].cpu().numpy()
+        exp = np.empty((1, n), dtype=np.float32)
+        oracle.c1(a, X, Y, exp, r0=r, r1=r + 1)
+        assert (got[: r + 1].view(np.uint32) == exp[0, : r + 1].view(np.uint32)).all(), r
+        assert (got[r + 1:] == fill).all(), r
+    # the upper triangle as a whole is untouched
+    upper = torch.ones((1024, 1024), dtype=torch.bool, device="cuda").triu(1)
+    for r0 in (0, 16384, n - 1024):
+        blk = c[r0:r0 + 1024, r0:r0 + 1024]
+        assert bool((blk[upper] == float(fill)).all())
+    del c
+    torch.cuda.empty_cache()

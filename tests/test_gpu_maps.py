@@ -1,0 +1,115 @@
+"""GPU parity of the maps: the device map must equal the oracle's map block
+for block (tile maps) or thread for thread (UTM), and the device lambda must
+be exact at every row boundary of the 32-bit range (Eq. eq_gmap)."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import dev, host, note
+
+pytestmark = pytest.mark.gpu
+
+def _tm():
+    from paper_1609_01490_amd import trimap
+    return trimap
+
+
+TILE_MAPS = ["bb", "rb", "rec", "lambda"]
+
+
+@pytest.mark.parametrize("map_name", TILE_MAPS)
+@pytest.mark.parametrize("tile", [8, 16, 32, 64])
+def test_tile_map_dump_equals_oracle(map_name, tile):
+    tm = _tm()
+    for n in (1, 7, 8, 9, 100, 255, 256, 257, 1000, 2048, 4100):
+        for diag in (True, False):
+            ne = n if diag else n - 1
+            m = -(-ne // tile)
+            if map_name == "rec" and (m & (m - 1)):
+                with pytest.raises(tm.TrimapError):
+                    tm.Plan(n, tile, map_name, include_diag=diag)
+                continue
+            p = tm.Plan(n, tile, map_name, include_diag=diag)
+            if p.info.grid_blocks == 0:
+                continue
+            note("map dump", map_name, tile, n, diag)
+            got = host(p.dump())
+            exp = oracle.map_dump(oracle.MAP_NAMES[map_name], m)
+            assert got.shape == exp.shape
+            assert (got == exp).all(), (map_name, tile, n, diag)
+
+
+@pytest.mark.parametrize("tile", [16, 32])
+def test_lambda_xcd_swizzle_is_a_permutation(tile):
+    tm = _tm()
+    for n in (100, 257, 2048, 32768):
+        p = tm.Plan(n, tile, "lambda", flags=tm.FLAG_XCD_SWIZZLE)
+        note("swizzle dump", tile, n)
+        got = host(p.dump())
+        m = p.info.m
+        exp = oracle.map_dump(oracle.LAMBDA, m)
+        # same set of tiles, each once
+        assert sorted(map(tuple, got.tolist())) == sorted(map(tuple, exp.tolist()))
+        # XCD x (blocks b = x mod 8) walks a contiguous range of omega
+        T = p.info.tiles
+        omega = (got[:, 0] * (got[:, 0] + 1)) // 2 + got[:, 1]
+        for x in range(8):
+            w = omega[x::8]
+            assert (np.diff(w) == 1).all()
+
+
+def test_utm_dump_equals_oracle():
+    tm = _tm()
+    for n in (1, 2, 3, 10, 64, 100, 301):
+        for diag in (True, False):
+            p = tm.Plan(n, 32, "utm", include_diag=diag)
+            if p.info.elements == 0:
+                continue
+            note("utm dump", n, diag)
+            got = host(p.dump())
+            N = n + 1 if diag else n
+            exp = []
+            for k in range(p.info.elements):
+                a, b = oracle.utm_pair(N, k)
+                exp.append((n - a, n + 1 - b) if diag else (n - a, n - b))
+            assert (got == np.array(exp)).all(), (n, diag)
+
+
+def _boundary_omegas():
+    rows = np.arange(0, 92683, dtype=np.uint64)       # every row with T_i < 2^32
+    T = rows * (rows + 1) // 2
+    w = np.concatenate([T, T + rows, np.maximum(T, 1) - 1])
+    rng = np.random.default_rng(11)
+    w = np.concatenate([w, rng.integers(0, 2**32, 200000, dtype=np.uint64),
+                        np.array([2**32 - 1, 2**32, 2**32 + 7, 2**40 + 3, 2**59 - 1],
+                                 dtype=np.uint64),
+                        rng.integers(2**32, 2**59, 2000, dtype=np.uint64)])
+    return np.unique(w)
+
+
+@pytest.mark.parametrize("flags", [0, 2, 4])
+def test_lambda_exact_at_row_boundaries(flags):
+    tm = _tm()
+    w = _boundary_omegas()
+    note("lambda eval", flags, w.size)
+    got = host(tm.lambda_eval(dev(w.view(np.int64)), True, flags))
+    # oracle: integer square root (exact); checked row by row
+    i = got[:, 0].astype(np.uint64)
+    j = got[:, 1].astype(np.uint64)
+    assert (got[:, 1] >= 0).all() and (j <= i).all()
+    assert ((i * (i + 1) // 2 + j) == w).all()
+    sample = np.random.default_rng(12).choice(w.size, 3000, replace=False)
+    for s in sample:
+        assert oracle.lam(int(w[s])) == tuple(got[s])
+
+
+def test_lambda_nodiag_eval():
+    tm = _tm()
+    w = _boundary_omegas()[:300000]
+    note("lambda nodiag eval", w.size)
+    got = host(tm.lambda_eval(dev(w.view(np.int64)), False, 0))
+    for s in np.random.default_rng(13).choice(w.size, 3000, replace=False):
+        assert oracle.lam_nodiag(int(w[s])) == tuple(got[s])
+    i = got[:, 0].astype(np.uint64)
+    j = got[:, 1].astype(np.uint64)
+    assert (j < i).all() and (((i - 1) * i // 2 + j) == w).all()

@@ -1,0 +1,137 @@
+"""GPU parity of the triangular Game of Life against the oracle: bit-exact
+final grid, cells above the diagonal untouched whatever they hold, every tile
+map and tile size, ragged sizes, odd and even step counts, and the full
+16384 x 16384, 100-step case checked on light-cone windows."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import dev, host, note, padded_ld
+from paper_1609_01490_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+MAPS = ["bb", "rb", "rec", "lambda"]
+
+
+def _tm():
+    from paper_1609_01490_amd import trimap
+    return trimap
+
+
+def _run(tm, p, g, steps, garbage_seed=None):
+    """Run on device; the upper triangle of both buffers holds garbage that
+    must be ignored and left untouched."""
+    n, ld = g.shape
+    cur = g.copy()
+    nxt = np.zeros_like(g)
+    if garbage_seed is not None:
+        rng = np.random.default_rng(garbage_seed)
+        up = np.triu(np.ones((n, ld), dtype=bool), 1)
+        cur[up] = rng.integers(0, 256, up.sum(), dtype=np.uint8)
+        nxt[up] = rng.integers(0, 256, up.sum(), dtype=np.uint8)
+    up_cur, up_nxt = cur.copy(), nxt.copy()
+    dc, dn = dev(cur), dev(nxt)
+    p.stencil(dc, dn, steps, ld=ld)
+    res = host(dc if steps % 2 == 0 else dn)
+    other = host(dn if steps % 2 == 0 else dc)
+    up = np.triu(np.ones((n, ld), dtype=bool), 1)
+    assert (res[up] == (up_cur if steps % 2 == 0 else up_nxt)[up]).all(), "upper triangle written"
+    assert (other[up] == (up_nxt if steps % 2 == 0 else up_cur)[up]).all(), "upper triangle written"
+    return res
+
+
+@pytest.mark.parametrize("map_name", MAPS)
+@pytest.mark.parametrize("tile", [8, 16, 32, 64])
+def test_life_bit_exact(map_name, tile):
+    tm = _tm()
+    for n in (1, 2, 5, 33, 100, 257):
+        m = -(-n // tile)
+        if map_name == "rec" and (m & (m - 1)):
+            continue
+        ld = padded_ld(n)
+        g = inputs.life(n, 0.3, seed=3000 + n, ld=ld)
+        p = tm.Plan(n, tile, map_name)
+        for steps in (1, 2, 7):
+            note("life", map_name, tile, n, steps)
+            got = _run(tm, p, g, steps, garbage_seed=n + steps)
+            exp = oracle.gol(g, n, steps)
+            low = np.tril(np.ones((n, n), dtype=bool))
+            assert (got[:, :n][low] == exp[low]).all(), (map_name, tile, n, steps)
+
+
+def test_life_long_run_and_composition():
+    tm = _tm()
+    n = 300
+    ld = padded_ld(n)
+    g = inputs.life(n, 0.3, seed=77, ld=ld)
+    p = tm.Plan(n, 32, "lambda")
+    note("life long", n)
+    got = _run(tm, p, g, 60)
+    exp = oracle.gol(g, n, 60)
+    low = np.tril(np.ones((n, n), dtype=bool))
+    assert (got[:, :n][low] == exp[low]).all()
+    half = _run(tm, p, g, 30)
+    again = _run(tm, p, half, 30)
+    assert (again == got).all()
+
+
+def test_life_textbook_glider_on_device():
+    tm = _tm()
+    n = 128
+    g = np.zeros((n, n), dtype=np.uint8)
+    for r, c in [(0, 1), (1, 2), (2, 0), (2, 1), (2, 2)]:
+        g[60 + r, 10 + c] = 1
+    p = tm.Plan(n, 16, "lambda")
+    note("glider")
+    got = _run(tm, p, g, 8)
+    exp = np.zeros_like(g)
+    for r, c in [(0, 1), (1, 2), (2, 0), (2, 1), (2, 2)]:
+        exp[62 + r, 12 + c] = 1
+    assert (got == exp).all()
+
+
+def test_life_errors():
+    import torch
+    tm = _tm()
+    x = torch.zeros((64, 64), dtype=torch.uint8, device="cuda")
+    y = torch.zeros((64, 64), dtype=torch.uint8, device="cuda")
+    with pytest.raises(tm.TrimapError):
+        tm.Plan(64, 16, "utm").stencil(x, y, 1)
+    with pytest.raises(tm.TrimapError):
+        tm.Plan(64, 16, "lambda").stencil(x, y, 1, ld=63)
+    with pytest.raises(tm.TrimapError):
+        tm.Plan(64, 16, "lambda").stencil(x, x, 1)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("map_name,tile", [("lambda", 32), ("bb", 32)])
+def test_life_full_size_windows(map_name, tile):
+    """n = 16384, density 0.3, 100 steps.  The oracle recomputes 64 x 64 cell
+    blocks from their light cones (the initial state within 100 cells):
+    at the diagonal, the bottom edge, the left edge, a corner and inside."""
+    import torch
+    tm = _tm()
+    n, steps = 16384, 100
+    g = inputs.life(n, 0.3)
+    note("life full", map_name, tile, n, steps)
+    cur = dev(g)
+    nxt = torch.zeros_like(cur)
+    p = tm.Plan(n, tile, map_name)
+    p.stencil(cur, nxt, steps)
+    res = cur if steps % 2 == 0 else nxt
+    torch.cuda.synchronize()
+    blocks = [(8000, 7970), (n - 64, 5000), (9000, 0), (n - 64, n - 64), (12000, 3000),
+              (64, 0), (5000, 4990)]
+    for (r, c) in blocks:
+        h = w = 64
+        win = oracle.gol(g, n, steps, r - steps, c - steps, h + 2 * steps, w + 2 * steps)
+        exp = win[steps:steps + h, steps:steps + w]
+        got = res[r:r + h, c:c + w].cpu().numpy()
+        rr = np.arange(r, r + h)[:, None]
+        cc = np.arange(c, c + w)[None, :]
+        dom = cc <= rr
+        assert (got[dom] == exp[dom]).all(), (r, c)
+        assert not got[~dom].any(), (r, c)
+    del cur, nxt
+    torch.cuda.empty_cache()

@@ -176,6 +176,15 @@ def bench_edm(tm, torch, timer):
     ms = timer.run(lambda: p.edm(xd, out, mode=tm.EDM_FP32), 3, 1)
     res["fp32_ms"] = round(ms, 4)
     res["fp32_pairs_per_s"] = round(pairs / (ms * 1e-3), 1)
+    q = tm.Plan(n, 128, "lambda", include_diag=False)
+    for mode, name in ((tm.EDM_BF16X3, "bf16x3"), (tm.EDM_BF16, "bf16")):
+        ws = torch.empty(q.edm_workspace_size(d, mode), dtype=torch.uint8, device="cuda")
+        ms = timer.run(lambda: q.edm(xd, out, mode=mode, fixup_thr=1e-2, ws=ws), 5, 2)
+        res[f"{name}_ms"] = round(ms, 4)
+        res[f"{name}_pairs_per_s"] = round(pairs / (ms * 1e-3), 1)
+        res[f"{name}_write_GBps"] = round(4 * pairs / (ms * 1e-3) / 1e9, 1)
+        res[f"{name}_speedup_vs_fp32"] = round(res["fp32_ms"] / ms, 3)
+        del ws
     del xd, out
     torch.cuda.empty_cache()
     return {"n": n, "d": d, **res}

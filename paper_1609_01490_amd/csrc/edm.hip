@@ -11,6 +11,19 @@
 // blocks staged in LDS dimension-major so that a lane's 4x4 register block
 // reads broadcast / consecutive words.  Bound by the vector ALU (2 VALU ops
 // per pair and dimension).
+//
+// TRI_EDM_BF16X3 / TRI_EDM_BF16: d^2 = |x_i|^2 + |x_j|^2 - 2 x_i.x_j with the
+// Gram term on the matrix cores.  A pre-pass centres the points on their mean
+// (distances are translation invariant; centring shrinks the norms and with
+// them the cancellation), splits each centred coordinate into a BF16 high
+// part and a BF16 low part (hi = bf16(x), lo = bf16(x - hi)), and computes the
+// norms from the same rounded operands the matrix cores see.  Each 128 x 128
+// output tile is then four waves of 64 x 64, each a 2 x 2 grid of
+// v_mfma_f32_32x32x16_bf16 blocks accumulating hi.hi + hi.lo + lo.hi in FP32
+// (hi.hi only for TRI_EDM_BF16).  Distances whose Gram-based square falls
+// below fixup_thr are recomputed directly in FP32 from the original
+// coordinates, which removes the cancellation error for near-duplicates.
+// The output write (4 B per pair) bounds this path.
 #include "common.hpp"
 #include "maps.hpp"
 
@@ -122,6 +135,209 @@ static bool edm_f32(const tri_plan *p, const EdmArgs &a, hipStream_t s)
     return false;
 }
 
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kEdmTile = 128;     // output tile of the MFMA kernel
+constexpr int kColsumRows = 256;  // rows per block of the column-sum pass
+
+// Workspace of the MFMA modes (all offsets 256-byte aligned).
+struct EdmWs {
+    size_t hi, lo, norms, mean, partial, total;
+    int64_t dp, nb;
+};
+
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+static EdmWs edm_ws_layout(int64_t n, int64_t d)
+{
+    EdmWs w{};
+    w.dp = (d + 15) / 16 * 16;
+    w.nb = (n + kColsumRows - 1) / kColsumRows;
+    size_t o = 0;
+    w.hi = o;      o = align256(o + (size_t)n * w.dp * 2);
+    w.lo = o;      o = align256(o + (size_t)n * w.dp * 2);
+    w.norms = o;   o = align256(o + (size_t)n * 4);
+    w.mean = o;    o = align256(o + (size_t)w.dp * 4);
+    w.partial = o; o = align256(o + (size_t)w.nb * w.dp * 4);
+    w.total = o;
+    return w;
+}
+
+// Column sums of blocks of kColsumRows rows, in row order (deterministic).
+__global__ void __launch_bounds__(256) k_edm_colsum(const float *x, int32_t n, int32_t d,
+                                                    int64_t ldx, int32_t dp, float *partial)
+{
+    const int32_t r0 = blockIdx.x * kColsumRows;
+    const int32_t r1 = min(n, r0 + kColsumRows);
+    for (int32_t k = threadIdx.x; k < dp; k += 256) {
+        float s = 0.f;
+        if (k < d)
+            for (int32_t r = r0; r < r1; ++r) s += x[(int64_t)r * ldx + k];
+        partial[(int64_t)blockIdx.x * dp + k] = s;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_edm_mean(const float *partial, int32_t nb, int32_t n,
+                                                  int32_t dp, float *mean)
+{
+    for (int32_t k = threadIdx.x; k < dp; k += 256) {
+        float s = 0.f;
+        for (int32_t b = 0; b < nb; ++b) s += partial[(int64_t)b * dp + k];
+        mean[k] = s / (float)n;
+    }
+}
+
+// One wave per point: centre, split into BF16 hi/lo, and the norm of the
+// rounded operands, hi.hi + 2 hi.lo (hi.hi only without the split), reduced
+// across the wave in a fixed butterfly order.
+template <bool SPLIT>
+__global__ void __launch_bounds__(64) k_edm_split(const float *x, int32_t d, int64_t ldx,
+                                                  int32_t dp, const float *mean, __bf16 *hi,
+                                                  __bf16 *lo, float *norms)
+{
+    const int64_t row = blockIdx.x;
+    float acc = 0.f;
+    for (int32_t k = threadIdx.x; k < dp; k += 64) {
+        float c = 0.f;
+        if (k < d) c = x[row * ldx + k] - mean[k];
+        const __bf16 h = (__bf16)c;
+        const float hf = (float)h;
+        const __bf16 l = (__bf16)(c - hf);
+        const float lf = (float)l;
+        hi[row * dp + k] = h;
+        if (SPLIT) {
+            lo[row * dp + k] = l;
+            acc = __builtin_fmaf(hf, hf, __builtin_fmaf(2.f * hf, lf, acc));
+        } else {
+            acc = __builtin_fmaf(hf, hf, acc);
+        }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (threadIdx.x == 0) norms[row] = acc;
+}
+
+struct EdmMfmaArgs {
+    TileGrid g;
+    int32_t n, d, dp;
+    int64_t ldx;
+    const float *x;
+    const __bf16 *hi;
+    const __bf16 *lo;
+    const float *norms;
+    float *out;
+    float thr;
+};
+
+__device__ __forceinline__ float direct_d2(const float *x, int64_t ldx, int32_t d, int32_t i,
+                                           int32_t j)
+{
+    const float *xi = x + (int64_t)i * ldx, *xj = x + (int64_t)j * ldx;
+    float s = 0.f;
+    for (int32_t k = 0; k < d; ++k) {
+        const float df = xi[k] - xj[k];
+        s = __builtin_fmaf(df, df, s);
+    }
+    return s;
+}
+
+template <int MAP, bool SPLIT>
+__global__ void __launch_bounds__(256) k_edm_mfma(EdmMfmaArgs p)
+{
+    int32_t bi, bj;
+    if (!tile_of_block<MAP>(p.g, bi, bj)) return;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int32_t n = p.n;
+    const int32_t R0 = 1 + bi * kEdmTile + 64 * (w >> 1);  // first row of this wave
+    const int32_t C0 = bj * kEdmTile + 64 * (w & 1);       // first column of this wave
+    // no barrier in this kernel: a wave with no pair j < i < n leaves early
+    if (R0 >= n || C0 >= R0 + 63) return;
+
+    const int lr = l & 31, lk = (l >> 5) * 8;
+    const int32_t dp = p.dp;
+    const __bf16 *ah[2], *bh[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        const int32_t r = min(R0 + 32 * a + lr, n - 1);
+        const int32_t c = min(C0 + 32 * a + lr, n - 1);
+        ah[a] = p.hi + (int64_t)r * dp + lk;
+        bh[a] = p.hi + (int64_t)c * dp + lk;
+    }
+    const int64_t lo_off = p.lo - p.hi;
+
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
+
+    for (int32_t k0 = 0; k0 < dp; k0 += 16) {
+        bf16x8 Ah[2], Bh[2], Al[2], Bl[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            Ah[a] = *(const bf16x8 *)(ah[a] + k0);
+            Bh[a] = *(const bf16x8 *)(bh[a] + k0);
+            if (SPLIT) {
+                Al[a] = *(const bf16x8 *)(ah[a] + lo_off + k0);
+                Bl[a] = *(const bf16x8 *)(bh[a] + lo_off + k0);
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah[a], Bh[b], acc[a][b], 0, 0, 0);
+                if (SPLIT) {
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah[a], Bl[b], acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Al[a], Bh[b], acc[a][b], 0, 0, 0);
+                }
+            }
+    }
+
+    // D[m][n] of a 32 x 32 block: lane l holds column n = l % 32 and, in
+    // register r, row m = 8 (r / 4) + 4 (l / 32) + r % 4
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        const int32_t j = C0 + 32 * b + lr;
+        const float nj = p.norms[min(j, n - 1)];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int32_t i = R0 + 32 * a + 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
+                if (i >= n || j >= i) continue;
+                float d2 = p.norms[i] + nj - 2.f * acc[a][b][r];
+                if (d2 < p.thr) d2 = direct_d2(p.x, p.ldx, p.d, i, j);
+                __builtin_nontemporal_store(__builtin_sqrtf(fmaxf(d2, 0.f)),
+                                            p.out + (int64_t)i * (i - 1) / 2 + j);
+            }
+    }
+}
+
+template <int MAP>
+static void edm_mfma_launch(const tri_plan *p, const EdmMfmaArgs &a, bool split, hipStream_t s)
+{
+    const dim3 grid(p->gx, p->gy);
+    if (split)
+        k_edm_mfma<MAP, true><<<grid, 256, 0, s>>>(a);
+    else
+        k_edm_mfma<MAP, false><<<grid, 256, 0, s>>>(a);
+}
+
+static bool edm_mfma(const tri_plan *p, const EdmMfmaArgs &a, bool split, hipStream_t s)
+{
+    switch (p->map) {
+    case TRI_MAP_BB: edm_mfma_launch<MAP_BB>(p, a, split, s); return true;
+    case TRI_MAP_RB: edm_mfma_launch<MAP_RB>(p, a, split, s); return true;
+    case TRI_MAP_REC: edm_mfma_launch<MAP_REC>(p, a, split, s); return true;
+    case TRI_MAP_LAMBDA: edm_mfma_launch<MAP_LAMBDA>(p, a, split, s); return true;
+    }
+    return false;
+}
+
 static tri_status edm_check(const tri_plan *p, int64_t d, int mode)
 {
     if (!p) return fail(TRI_E_INVAL, "tri_edm: plan is NULL");
@@ -133,8 +349,11 @@ static tri_status edm_check(const tri_plan *p, int64_t d, int mode)
             return fail(TRI_E_UNSUPPORTED, "tri_edm: FP32 mode needs tile 16, 32 or 64");
         return TRI_OK;
     }
-    if (mode == TRI_EDM_BF16X3 || mode == TRI_EDM_BF16)
-        return fail(TRI_E_UNSUPPORTED, "tri_edm: MFMA modes not built yet");
+    if (mode == TRI_EDM_BF16X3 || mode == TRI_EDM_BF16) {
+        if (p->tile != kEdmTile)
+            return fail(TRI_E_UNSUPPORTED, "tri_edm: MFMA modes need tile %d", kEdmTile);
+        return TRI_OK;
+    }
     return fail(TRI_E_INVAL, "tri_edm: mode = %d", mode);
 }
 
@@ -149,6 +368,7 @@ extern "C" tri_status tri_edm_workspace_size(const tri_plan *p, int64_t d, int m
     *bytes = 0;
     tri_status st = edm_check(p, d, mode);
     if (st != TRI_OK) return st;
+    if (mode != TRI_EDM_FP32) *bytes = edm_ws_layout(p->n, d).total;
     return TRI_OK;
 }
 
@@ -159,16 +379,37 @@ extern "C" tri_status tri_edm(const tri_plan *p, const float *x, int64_t d, int6
     clear_error();
     tri_status st = edm_check(p, d, mode);
     if (st != TRI_OK) return st;
-    (void)fixup_thr;
-    (void)ws;
-    (void)ws_bytes;
     if (p->n < 2) return TRI_OK;
     if (!x || !out) return fail(TRI_E_INVAL, "tri_edm: NULL buffer");
     if (ldx < d) return fail(TRI_E_INVAL, "tri_edm: ldx < d");
     if (((uintptr_t)x | (uintptr_t)out) & 3) return fail(TRI_E_INVAL, "tri_edm: unaligned buffer");
-    EdmArgs a{plan_tile_grid(p), (int32_t)p->n, (int32_t)d, ldx, x, out};
     hipStream_t s = (hipStream_t)stream;
-    if (!edm_f32(p, a, s)) return fail(TRI_E_UNSUPPORTED, "tri_edm: tile");
+    if (mode == TRI_EDM_FP32) {
+        EdmArgs a{plan_tile_grid(p), (int32_t)p->n, (int32_t)d, ldx, x, out};
+        if (!edm_f32(p, a, s)) return fail(TRI_E_UNSUPPORTED, "tri_edm: tile");
+        TRI_HIP(hipGetLastError());
+        return TRI_OK;
+    }
+    const EdmWs L = edm_ws_layout(p->n, d);
+    if (!ws || ws_bytes < L.total)
+        return fail(TRI_E_NOMEM, "tri_edm: workspace of %zu bytes needed", L.total);
+    if ((uintptr_t)ws & 255) return fail(TRI_E_INVAL, "tri_edm: workspace must be 256-byte aligned");
+    if (!(fixup_thr >= 0.f)) return fail(TRI_E_INVAL, "tri_edm: fixup_thr must be >= 0");
+    char *w = (char *)ws;
+    __bf16 *hi = (__bf16 *)(w + L.hi), *lo = (__bf16 *)(w + L.lo);
+    float *norms = (float *)(w + L.norms), *mean = (float *)(w + L.mean);
+    float *partial = (float *)(w + L.partial);
+    const int32_t n = (int32_t)p->n, dd = (int32_t)d, dp = (int32_t)L.dp;
+    const bool split = (mode == TRI_EDM_BF16X3);
+    k_edm_colsum<<<dim3((uint32_t)L.nb), 256, 0, s>>>(x, n, dd, ldx, dp, partial);
+    k_edm_mean<<<1, 256, 0, s>>>(partial, (int32_t)L.nb, n, dp, mean);
+    if (split)
+        k_edm_split<true><<<dim3((uint32_t)n), 64, 0, s>>>(x, dd, ldx, dp, mean, hi, lo, norms);
+    else
+        k_edm_split<false><<<dim3((uint32_t)n), 64, 0, s>>>(x, dd, ldx, dp, mean, hi, lo, norms);
+    TRI_HIP(hipGetLastError());
+    EdmMfmaArgs a{plan_tile_grid(p), n, dd, dp, ldx, x, hi, lo, norms, out, fixup_thr};
+    if (!edm_mfma(p, a, split, s)) return fail(TRI_E_UNSUPPORTED, "tri_edm: map");
     TRI_HIP(hipGetLastError());
     return TRI_OK;
 }

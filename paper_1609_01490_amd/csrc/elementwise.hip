@@ -11,6 +11,8 @@
 // cell.  Rows move as 16-byte vectors; stores are non-temporal (the output
 // is not re-read).  UTM (thread space) has no tile and gets its own scalar
 // kernel, reading Y[j][i] straight from memory as the map implies.
+#include <type_traits>
+
 #include "common.hpp"
 #include "maps.hpp"
 
@@ -63,6 +65,20 @@ __global__ void __launch_bounds__((ElemShape<TILE, VECTOR>::NT)) k_axpyt(ElemArg
     // every cell of the tile is in the domain
     const bool full = (bj < bi) && (i0 + TILE <= n);
 
+    // X rows of this thread: issued first so that both streams are in flight
+    // while the mirror tile goes through LDS
+    using V = typename std::conditional<S::VEC == 4, f4, float>::type;
+    V xv[S::PASSES];
+#pragma unroll
+    for (int ps = 0; ps < S::PASSES; ++ps) {
+        const int r = tr + ps * S::RPP;
+        const int32_t i = i0 + r, jc = j0 + tc;
+        if (full || (i < n && jc <= i))
+            xv[ps] = __builtin_nontemporal_load((const V *)(X + (int64_t)i * ld + jc));
+        else
+            xv[ps] = V{};
+    }
+
     // mirror tile of Y: rows j0.., columns i0.. ; Y[j][i] lands in ys[j-j0][i-i0]
 #pragma unroll
     for (int ps = 0; ps < S::PASSES; ++ps) {
@@ -88,14 +104,13 @@ __global__ void __launch_bounds__((ElemShape<TILE, VECTOR>::NT)) k_axpyt(ElemArg
         const int32_t i = i0 + r, jc = j0 + tc;
         if (!full && (i >= n || jc > i)) continue;
         float *crow = C + (int64_t)i * ld + jc;
-        const float *xrow = X + (int64_t)i * ld + jc;
         if constexpr (S::VEC == 4) {
-            const f4 xv = __builtin_nontemporal_load((const f4 *)xrow);
+            const f4 x4 = xv[ps];
             f4 o;
-            o.x = __fadd_rn(__fmul_rn(a, xv.x), ys[tc + 0][r]);
-            o.y = __fadd_rn(__fmul_rn(a, xv.y), ys[tc + 1][r]);
-            o.z = __fadd_rn(__fmul_rn(a, xv.z), ys[tc + 2][r]);
-            o.w = __fadd_rn(__fmul_rn(a, xv.w), ys[tc + 3][r]);
+            o.x = __fadd_rn(__fmul_rn(a, x4.x), ys[tc + 0][r]);
+            o.y = __fadd_rn(__fmul_rn(a, x4.y), ys[tc + 1][r]);
+            o.z = __fadd_rn(__fmul_rn(a, x4.z), ys[tc + 2][r]);
+            o.w = __fadd_rn(__fmul_rn(a, x4.w), ys[tc + 3][r]);
             if (full || jc + 3 <= i) {
                 __builtin_nontemporal_store(o, (f4 *)crow);
             } else {  // the vector straddles the diagonal
@@ -104,8 +119,7 @@ __global__ void __launch_bounds__((ElemShape<TILE, VECTOR>::NT)) k_axpyt(ElemArg
                 if (jc + 2 <= i) crow[2] = o.z;
             }
         } else {
-            const float xv = __builtin_nontemporal_load(xrow);
-            __builtin_nontemporal_store(__fadd_rn(__fmul_rn(a, xv), ys[tc][r]), crow);
+            __builtin_nontemporal_store(__fadd_rn(__fmul_rn(a, xv[ps]), ys[tc][r]), crow);
         }
     }
 }

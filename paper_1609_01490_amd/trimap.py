@@ -41,6 +41,10 @@ class tri_plan_info(ctypes.Structure):
 
 
 def _load() -> ctypes.CDLL:
+    # torch owns the device memory and the streams handed to the library, so
+    # the library must resolve libamdhip64.so.7 to the HIP runtime torch has
+    # loaded (same soname): import torch before the library is opened.
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError(
             f"{LIB_PATH} is missing: build it with `python -m paper_1609_01490_amd.build`")

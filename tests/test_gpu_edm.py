@@ -81,3 +81,118 @@ def test_edm_fp32_full_size_sampled_rows():
         assert rel.max() <= _fp32_bound(d), (r, rel.max())
     del out
     torch.cuda.empty_cache()
+
+
+# --------------------------------------------------------------------------
+# MFMA modes.  The distance map target is a maximum relative error of 1e-3
+# against FP64: split BF16 (hi.hi + hi.lo + lo.hi, 16 significant bits per
+# operand) is held to it.  Single BF16 rounds each centred coordinate to
+# 8 significant bits (relative error <= 2^-8), so its distance error is
+# absolute: |d_gpu - d| <= 2^-8 (|x~_i| + |x~_j|) plus FP32 accumulation;
+# it is held to twice that.  Near-duplicates below the fix-up threshold are
+# recomputed in FP32 and held to the FP32 bound.
+# --------------------------------------------------------------------------
+
+MFMA_TOL = {1: 1e-3}
+
+
+def _check_rows_bf16(X, out_host, rows):
+    Xc = X.astype(np.float64) - X.astype(np.float64).mean(axis=0)
+    nrm = np.sqrt((Xc ** 2).sum(axis=1))
+    exp = oracle.edm_rows(X, rows)
+    for r, e in zip(rows, exp):
+        g = out_host[r * (r - 1) // 2: r * (r - 1) // 2 + r].astype(np.float64)
+        bound = 2.0 ** -7 * (nrm[r] + nrm[:r])
+        assert (np.abs(g - e) <= bound).all(), r
+
+
+def _edm_mfma(tm, p, X, mode, thr=1e-2):
+    import torch
+    n = X.shape[0]
+    ws = torch.empty(p.edm_workspace_size(X.shape[1], mode), dtype=torch.uint8, device="cuda")
+    out = torch.full((n * (n - 1) // 2,), -1.0, dtype=torch.float32, device="cuda")
+    p.edm(dev(X), out, mode=mode, fixup_thr=thr, ws=ws)
+    return out
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("map_name", ["bb", "lambda", "rb"])
+def test_edm_mfma_small(mode, map_name):
+    tm = _tm()
+    for n in (2, 3, 50, 129, 130, 257, 700):
+        for d in (1, 4, 33, 128):
+            X, pairs = inputs.points(n, d, dup_frac=0.02, seed=5000 + n + d)
+            p = tm.Plan(n, 128, map_name, include_diag=False)
+            note("edm mfma", mode, map_name, n, d)
+            got = host(_edm_mfma(tm, p, X, mode))
+            assert (got >= 0).all()
+            if mode == 1:
+                _check_rows(X, got, list(range(n)), MFMA_TOL[mode])
+            else:
+                _check_rows_bf16(X, got, list(range(n)))
+            # near-duplicates go through the FP32 recompute
+            exp = oracle.edm_rows(X, [int(max(a, b)) for a, b in pairs])
+            for (a, b), e in zip(pairs.tolist(), exp):
+                i, j = max(a, b), min(a, b)
+                g = float(got[i * (i - 1) // 2 + j])
+                if e[j] > 0 and e[j] ** 2 < 1e-2:
+                    assert abs(g - e[j]) / e[j] <= _fp32_bound(d)
+
+
+def test_edm_mfma_exact_duplicates_are_zero():
+    tm = _tm()
+    n, d = 300, 64
+    X, _ = inputs.points(n, d, dup_frac=0.0, seed=9)
+    X[17] = X[250]
+    X[299] = X[0]
+    p = tm.Plan(n, 128, "lambda", include_diag=False)
+    for mode in (1, 2):
+        note("edm dup", mode)
+        got = host(_edm_mfma(tm, p, X, mode))
+        assert got[250 * 249 // 2 + 17] == 0.0
+        assert got[299 * 298 // 2 + 0] == 0.0
+
+
+def test_edm_mfma_argument_errors():
+    import torch
+    tm = _tm()
+    p = tm.Plan(100, 64, "lambda", include_diag=False)
+    with pytest.raises(tm.TrimapError) as e:
+        p.edm_workspace_size(16, tm.EDM_BF16X3)
+    assert e.value.status == tm.E_UNSUPPORTED
+    q = tm.Plan(100, 128, "lambda", include_diag=False)
+    x = torch.zeros((100, 16), device="cuda")
+    out = torch.zeros(4950, device="cuda")
+    small = torch.empty(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(tm.TrimapError) as e:
+        q.edm(x, out, mode=tm.EDM_BF16X3, ws=small)
+    assert e.value.status == tm.E_NOMEM
+
+
+@pytest.mark.slow
+def test_edm_bf16x3_full_size_sampled_rows():
+    """n = 65536, d = 128 with 1 % near-duplicates: 24 random rows plus the
+    rows of 64 duplicate pairs, against the FP64 oracle; max relative error
+    reported and held to 1e-3."""
+    import torch
+    tm = _tm()
+    n, d = 65536, 128
+    X, pairs = inputs.points(n, d)
+    p = tm.Plan(n, 128, "lambda", include_diag=False)
+    note("edm bf16x3 full", n, d)
+    out = _edm_mfma(tm, p, X, tm.EDM_BF16X3)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(16)
+    rows = sorted(set([1, 2, n - 1] + rng.choice(n, 24, replace=False).tolist()
+                      + pairs[:64].max(axis=1).tolist()))
+    worst = 0.0
+    for r in rows:
+        g = out[r * (r - 1) // 2: r * (r - 1) // 2 + r].cpu().numpy().astype(np.float64)
+        e = oracle.edm_rows(X, [r])[0]
+        nz = e > 0
+        worst = max(worst, float((np.abs(g[nz] - e[nz]) / e[nz]).max()))
+    print(f"[edm bf16x3 n={n} d={d}] max relative error {worst:.3e} over {len(rows)} rows",
+          flush=True)
+    assert worst <= 1e-3
+    del out
+    torch.cuda.empty_cache()

@@ -190,6 +190,95 @@ def bench_edm(tm, torch, timer):
     return {"n": n, "d": d, **res}
 
 
+def bench_batch(tm, torch, timer, edm_tile=32, life_tile=32, steps=20, d=32):
+    """512 uneven instances (n log-uniform in [64, 8192]), even index distance
+    map (d = 32), odd index Life (20 generations): one hipGraph launch of the
+    persistent queue vs the same bodies launched per instance."""
+    from paper_1609_01490_amd import inputs
+    spec = inputs.batch_instances()
+    kinds, ns, A, B = [], [], [], []
+    pairs = cells = 0
+    for k, (kind, n) in enumerate(spec):
+        if kind == "edm":
+            X, _ = inputs.points(n, d, dup_frac=0.0, seed=inputs.seed_for(4) * 1000 + k)
+            A.append(torch.from_numpy(X).cuda())
+            B.append(torch.empty((n * (n - 1) // 2,), dtype=torch.float32, device="cuda"))
+            kinds.append(tm.KIND_EDM)
+            pairs += n * (n - 1) // 2
+        else:
+            ld = (n + 3) // 4 * 4
+            g = inputs.life(n, 0.3, seed=inputs.seed_for(4) * 1000 + k, ld=ld)
+            A.append(torch.from_numpy(g).cuda())
+            B.append(torch.zeros_like(A[-1]))
+            kinds.append(tm.KIND_LIFE)
+            cells += n * (n + 1) // 2
+        ns.append(n)
+    b = tm.Batch(kinds, ns, [d] * len(ns), edm_tile=edm_tile, life_tile=life_tile,
+                 life_steps=steps)
+    b.bind(A, B)
+    res = {}
+    for how, name in ((tm.BATCH_GRAPH, "graph"), (tm.BATCH_STREAM, "stream"),
+                      (tm.BATCH_PER_INSTANCE, "per_instance")):
+        res[name] = round(timer.run(lambda: b.launch(how), 3, 1), 4)
+    alg_bytes = 4 * pairs + 2 * cells * steps
+    out = {"instances": len(spec), "edm_tile": edm_tile, "life_tile": life_tile,
+           "life_steps": steps, "d": d, "edm_pairs": pairs, "life_cells": cells,
+           "launches_per_instance_mode": sum(1 if k == tm.KIND_EDM else steps for k in kinds),
+           "ms": res, "speedup_graph_vs_per_instance": round(res["per_instance"] / res["graph"], 3),
+           "GBps_algorithmic_graph": round(alg_bytes / (res["graph"] * 1e-3) / 1e9, 1),
+           "persistent_workgroups": b.info["persistent_workgroups"]}
+    b.close()
+    del A, B
+    torch.cuda.empty_cache()
+    return out
+
+
+def profile_target(tm, torch, args):
+    """A few launches of one workload, nothing else, for counter runs."""
+    from paper_1609_01490_amd import inputs
+    t = args.profile_target
+    reps = max(1, args.steps)
+    if t == "copy":
+        # plain device copy of known size: 1 GiB read + 1 GiB written per launch
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(reps):
+            b.copy_(a)
+    elif t == "elementwise":
+        n = 32768
+        a, X, Y, _ = inputs.f32_elementwise(n, with_fill=False)
+        xd, yd = torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda()
+        c = torch.empty((n, n), dtype=torch.float32, device="cuda")
+        p = tm.Plan(n, args.tile, args.map, flags=args.flags)
+        for _ in range(reps):
+            p.elementwise(tm.OP_AXPYT_F32, xd, yd, c, ld=n, a=float(a))
+    elif t == "edm":
+        n, d = 65536, 128
+        X, _ = inputs.points(n, d)
+        xd = torch.from_numpy(X).cuda()
+        out = torch.empty((n * (n - 1) // 2,), dtype=torch.float32, device="cuda")
+        q = tm.Plan(n, 128, "lambda", include_diag=False, flags=tm.FLAG_XCD_SWIZZLE)
+        ws = torch.empty(q.edm_workspace_size(d, tm.EDM_BF16X3), dtype=torch.uint8,
+                         device="cuda")
+        for _ in range(reps):
+            q.edm(xd, out, mode=tm.EDM_BF16X3, fixup_thr=1e-2, ws=ws)
+    elif t == "life":
+        n = 16384
+        cur = torch.from_numpy(inputs.life(n, 0.3)).cuda()
+        nxt = torch.zeros_like(cur)
+        p = tm.Plan(n, args.tile, args.map, flags=args.flags)
+        p.stencil(cur, nxt, reps)
+    elif t == "int":
+        n = 2048
+        A, B, C0 = inputs.int_elementwise(n)
+        ad, bd, cd = (torch.from_numpy(v).cuda() for v in (A, B, C0))
+        for map_name in ("lambda", "bb"):
+            p = tm.Plan(n, 16, map_name)
+            for _ in range(reps):
+                p.elementwise(tm.OP_XORMUL_I32, ad, bd, cd, ld=n)
+    torch.cuda.synchronize()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -200,6 +289,9 @@ def main():
     ap.add_argument("--flags", type=int, default=0)
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--profile-target", choices=["elementwise", "edm", "life", "int", "copy"],
+                    help="only launch this workload's kernels a few times (for rocprofv3 runs); "
+                         "prints no JSON line")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -212,6 +304,9 @@ def main():
         sys.exit(1)
     from paper_1609_01490_amd import trimap as tm
     timer = Timer(torch)
+    if args.profile_target:
+        profile_target(tm, torch, args)
+        return
 
     n, E, res, cpu = bench_elementwise(tm, torch, args, timer)
     ms = res[args.map]
@@ -225,7 +320,8 @@ def main():
     if not args.no_extra:
         for name, fn in (("int32_n2048", lambda: bench_int_elementwise(tm, torch, timer)),
                          ("life_n16384", lambda: bench_life(tm, torch, timer)),
-                         ("edm_n65536_d128", lambda: bench_edm(tm, torch, timer))):
+                         ("edm_n65536_d128", lambda: bench_edm(tm, torch, timer)),
+                         ("batch_512", lambda: bench_batch(tm, torch, timer))):
             log("extra", name)
             try:
                 extra[name] = fn()

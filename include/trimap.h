@@ -18,7 +18,8 @@
  *  - Matrices are row-major with a leading dimension `ld` in ELEMENTS.
  *  - Triangular domain of side n: cells (i, j) with 0 <= j <= i < n
  *    (include_diag = 1) or 0 <= j < i < n (include_diag = 0).
- *  - A plan is immutable after creation; concurrent launches of one plan on
+ *  - A plan is immutable after creation (apart from its cache of stencil
+ *    graphs, guarded by a lock); concurrent launches of one plan on
  *    different streams are safe.
  */
 #ifndef TRIMAP_H
@@ -139,24 +140,134 @@ tri_status tri_launch_elementwise(const tri_plan *plan, int op, const void *x, c
  * the other way round: the result is in cur when steps is even, in nxt when
  * odd.  Requires ld % 4 == 0, ld >= n, 4-byte aligned pointers, steps >= 0.
  * Each generation is one kernel launch; when use_graph is non-zero the
- * launches are captured once into a hipGraph and replayed. */
+ * generations are built once into a hipGraph of kernel nodes for this
+ * (cur, nxt, ld, steps), kept with the plan and replayed by every later call
+ * with the same arguments (the graph is freed by tri_plan_destroy, which must
+ * then not race with launches still in flight). */
 tri_status tri_launch_stencil(const tri_plan *plan, uint8_t *cur, uint8_t *nxt, int64_t ld,
                               int steps, int use_graph, void *stream);
 
 /* Euclidean distance map (the EDM test of Section 5): for the plan's strict
- * lower triangle (include_diag must be 0; map BB or LAMBDA), writes
+ * lower triangle (include_diag must be 0; any tile map but UTM), writes
  * d(i, j) = sqrt(sum_k (x_ik - x_jk)^2) in FP32 to out[i(i-1)/2 + j] (the
- * condensed strict lower triangle, n(n-1)/2 floats).  x is n x d FP32,
- * leading dimension ldx >= d.  mode is a TRI_EDM_* value.  For the MFMA
- * modes distances whose Gram-based square is below fixup_thr are recomputed
- * directly in FP32 from x.  ws is a device workspace of at least
- * tri_edm_workspace_size() bytes (may be NULL when that size is 0).
- * Supported: d <= 4096, tile 16/32/64 (FP32) or 64/128... see
- * tri_edm_workspace_size, which returns TRI_E_UNSUPPORTED for a plan the
- * mode cannot run. */
+ * condensed strict lower triangle, n(n-1)/2 floats; n(n-1)/2 < 2^32).  x is
+ * n x d FP32 (1 <= d <= 4096), leading dimension ldx >= d, 4-byte aligned.
+ * mode is a TRI_EDM_* value:
+ *  - TRI_EDM_FP32: plan tile 16, 32 or 64; no workspace (ws may be NULL).
+ *  - TRI_EDM_BF16X3 / TRI_EDM_BF16: plan tile 128; `out` 16-byte aligned
+ *    (rows are written as 16-byte vectors); ws a device buffer of at least
+ *    tri_edm_workspace_size() bytes, 256-byte aligned, else TRI_E_NOMEM /
+ *    TRI_E_INVAL.  Distances whose Gram-based square is below fixup_thr
+ *    (>= 0) are recomputed directly in FP32 from x.
+ * tri_edm_workspace_size returns the workspace bytes for (plan, d, mode),
+ * 0 for TRI_EDM_FP32, and TRI_E_UNSUPPORTED when the plan's tile does not
+ * fit the mode. */
 tri_status tri_edm_workspace_size(const tri_plan *plan, int64_t d, int mode, size_t *bytes);
 tri_status tri_edm(const tri_plan *plan, const float *x, int64_t d, int64_t ldx, float *out,
                    int mode, float fixup_thr, void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Batched uneven domains in one persistent launch per generation.
+ *
+ * Instance k (0 <= k < count) is a distance map (TRI_KIND_EDM: strict lower
+ * triangle of n_k points in d_k dimensions, FP32 direct arithmetic, edm_tile
+ * in {16, 32, 64}) or a Game of Life (TRI_KIND_LIFE: lower triangle of side
+ * n_k, life_tile in {8, 16, 32, 64}, life_steps generations).  Each instance
+ * contributes m_k (m_k + 1) / 2 tiles (Section 3.1); a global work item g is
+ * located by the exclusive prefix sum of these counts and mapped to its tile
+ * by lambda(g - P_k) (Eq. eq_gmap).  Persistent workgroups take items from an
+ * atomic counter; generation s of the Life instances is one kernel, so the
+ * whole batch is one hipGraph (a counter-reset node, then one node per
+ * generation; distance-map items run in generation 0).  Results equal the
+ * per-instance kernels bit for bit.
+ * ------------------------------------------------------------------------ */
+typedef struct tri_batch tri_batch;
+
+enum { TRI_KIND_EDM = 0, TRI_KIND_LIFE = 1 };
+
+/* How tri_batch_launch runs the batch. */
+enum {
+    TRI_BATCH_GRAPH = 0,        /* one hipGraphLaunch of the instantiated graph       */
+    TRI_BATCH_STREAM = 1,       /* the same persistent kernels launched on the stream */
+    TRI_BATCH_PER_INSTANCE = 2  /* one launch per instance and generation (baseline)  */
+};
+
+typedef struct {
+    int32_t count;
+    int32_t life_instances;
+    int32_t edm_tile;
+    int32_t life_tile;
+    int32_t life_steps;
+    int32_t persistent_workgroups;
+    int64_t items_generation0;          /* tiles in generation 0                  */
+    int64_t items_per_later_generation; /* Life tiles in each later generation    */
+} tri_batch_info;
+
+/* Plan a batch from host arrays kind[count], n[count], d[count] (d ignored
+ * for Life).  Needs the device that will run it to be current: it queries
+ * the CU count and occupancy and allocates the plan's own device arrays
+ * (prefix sums, instance descriptors, counters).  n_k < 2^20; at most 2^32
+ * tiles per generation. */
+tri_status tri_batch_plan(tri_batch **out, int32_t count, const int32_t *host_kind,
+                          const int64_t *host_n, const int64_t *host_d, int edm_tile,
+                          int life_tile, int life_steps);
+
+/* Bind the instances' device buffers (host arrays of device pointers):
+ * distance map k: a[k] = x (n_k x d_k FP32, leading dimension ld[k] >= d_k),
+ * b[k] = condensed output (n_k (n_k - 1) / 2 FP32); Life k: a[k] = the grid
+ * holding generation 0 on entry, b[k] = the other grid (both uint8, row
+ * pitch ld[k] >= n_k, a multiple of 4).  After an even number of
+ * generations the Life result is in a[k], after an odd number in b[k].
+ * Copies the descriptors to the device (synchronously) and builds and
+ * instantiates the graph.  Rebinding replaces both. */
+tri_status tri_batch_bind(tri_batch *b, void *const *host_a, void *const *host_b,
+                          const int64_t *host_ld);
+
+/* Run the bound batch on `stream` (how = TRI_BATCH_*).  Launches of one
+ * batch plan share its counters: calls that overlap in time race. */
+tri_status tri_batch_launch(tri_batch *b, int how, void *stream);
+tri_status tri_batch_query(const tri_batch *b, tri_batch_info *info);
+tri_status tri_batch_destroy(tri_batch *b);
+
+/* ------------------------------------------------------------------------
+ * Autotuner: tile size and map for a workload and problem size.
+ *
+ * tri_autotune times every candidate (tiles 8/16/32/64 — 16/32/64 for the
+ * FP32 distance map, 128 for the MFMA one — times maps BB, RB, REC (when m is
+ * a power of two), lambda and lambda with TRI_FLAG_XCD_SWIZZLE, plus UTM for
+ * the elementwise bodies) on this GPU: one warm-up and `reps` timed calls
+ * with HIP events on `stream`, on zeroed scratch buffers of the problem's
+ * size that it allocates and frees itself (so it is not for graph capture).
+ * Life is timed over two generations and reported per generation.  The
+ * fastest candidate goes to *best and into a process-wide cache keyed by GPU
+ * architecture, CU count, workload, floor(log2 n) and d (distance maps); with
+ * use_cache non-zero a cached entry is returned without timing.  When `all`
+ * is non-NULL up to all_cap timed candidates are written there and their
+ * number to *all_count.
+ * ------------------------------------------------------------------------ */
+enum {
+    TRI_TUNE_ELEMENTWISE_F32 = 0,
+    TRI_TUNE_ELEMENTWISE_I32 = 1,
+    TRI_TUNE_LIFE = 2,
+    TRI_TUNE_EDM_FP32 = 3,
+    TRI_TUNE_EDM_BF16X3 = 4
+};
+
+typedef struct {
+    int32_t tile;
+    int32_t map;
+    uint32_t flags;
+    float ms; /* mean time of one call (Life: one generation) */
+} tri_tune_choice;
+
+tri_status tri_autotune(int workload, int64_t n, int64_t d, int reps, int use_cache, void *stream,
+                        tri_tune_choice *best, tri_tune_choice *all, int32_t all_cap,
+                        int32_t *all_count);
+/* Save / load / clear the tuning cache (a small JSON file, one entry per
+ * line: arch, cus, workload, bucket, d, tile, map, flags, ms). */
+tri_status tri_tune_cache_save(const char *path);
+tri_status tri_tune_cache_load(const char *path);
+tri_status tri_tune_cache_clear(void);
 
 /* Human-readable name of a status, and the last error message of the
  * calling thread ("" if none). */

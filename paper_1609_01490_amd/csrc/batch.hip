@@ -1,0 +1,447 @@
+// Batched triangular domains of uneven size in one persistent launch per
+// generation, driven by a work queue over per-instance lambda numberings.
+//
+// Instance k owns B_k = m_k (m_k + 1) / 2 tiles (Section 3.1, block count of
+// lambda).  The exclusive prefix P_k of the B_k numbers all tiles of all
+// instances as one global range, so a work item g belongs to the instance k
+// with P_k <= g < P_{k+1} and is that instance's block omega = g - P_k,
+// whose tile is lambda(omega) (Eq. eq_gmap).  The prefix array grows with the
+// number of instances, not with n, which keeps the paper's rule that a map
+// uses no table growing with the problem size (Section 4.2).
+//
+// Persistent workgroups take items from an atomic counter until the range is
+// exhausted, so small and large instances share the machine without one
+// launch per instance.  Distance-map instances are independent tiles
+// (generation 0 only); Game-of-Life instances need a grid-wide dependency
+// between generations, so each generation is one node of a hipGraph (one
+// persistent kernel per node, each with its own counter), and a small kernel
+// node at the head of the graph clears the counters (no memset node).
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "bodies.hpp"
+#include "common.hpp"
+#include "maps.hpp"
+
+struct tri_batch;
+
+namespace trimap {
+
+bool launch_edm_f32_lambda(int tile, const TileGrid &g, const EdmTile &t, hipStream_t s);
+bool launch_life_lambda(int tile, const TileGrid &g, const LifeTile &t, hipStream_t s);
+
+struct BatchDesc {
+    int32_t kind;  // TRI_KIND_*
+    int32_t n;
+    int32_t d;
+    int32_t pad;
+    int64_t ld;    // distance map: ldx; Life: row pitch in bytes
+    void *a;       // distance map: x; Life: grid of even generations
+    void *b;       // distance map: out; Life: grid of odd generations
+};
+
+struct BatchStepArgs {
+    const BatchDesc *desc;
+    const int64_t *prefix;  // count + 1 entries, prefix[0] = 0, prefix[count] = total
+    const int32_t *idx;     // queue position -> instance (Life-only queues); null = identity
+    int32_t count;
+    int32_t step;           // generation
+    int64_t total;
+    uint32_t *head;         // this generation's counter
+};
+
+constexpr int kBatchThreads = 256;
+constexpr int kPrefixLds = 1024;  // prefix entries kept in LDS (else searched in memory)
+
+template <int TE, int TL>
+struct BatchLds {
+    static constexpr int EDM_BYTES = EdmF32Shape<TE>::LDS_FLOATS * 4;
+    static constexpr int LIFE_BYTES = LifeShape<TL, kBatchThreads>::LDS_WORDS * 4;
+    static constexpr int BYTES = EDM_BYTES > LIFE_BYTES ? EDM_BYTES : LIFE_BYTES;
+};
+
+template <int TE, int TL>
+__global__ void __launch_bounds__(kBatchThreads) k_batch_step(BatchStepArgs a)
+{
+    __shared__ __attribute__((aligned(16))) unsigned char body_lds[BatchLds<TE, TL>::BYTES];
+    __shared__ int64_t pfx[kPrefixLds];
+    __shared__ int64_t slot;
+
+    const bool in_lds = a.count + 1 <= kPrefixLds;
+    if (in_lds)
+        for (int k = threadIdx.x; k <= a.count; k += kBatchThreads) pfx[k] = a.prefix[k];
+
+    for (;;) {
+        __syncthreads();  // the previous item is done with the LDS and with slot
+        if (threadIdx.x == 0) slot = (int64_t)atomicAdd(a.head, 1u);
+        __syncthreads();
+        const int64_t g = slot;
+        if (g >= a.total) return;  // uniform over the workgroup
+
+        // instance: the largest q with prefix[q] <= g
+        int lo = 0, hi = a.count;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            const int64_t pm = in_lds ? pfx[mid] : a.prefix[mid];
+            if (pm <= g) lo = mid;
+            else hi = mid;
+        }
+        const int64_t base = in_lds ? pfx[lo] : a.prefix[lo];
+        const int k = a.idx ? a.idx[lo] : lo;
+        const BatchDesc D = a.desc[k];
+        int32_t bi, bj;
+        lambda_tile((uint64_t)(g - base), 0u, bi, bj);
+        if (D.kind == TRI_KIND_EDM) {
+            const EdmTile t{D.n, D.d, D.ld, (const float *)D.a, (float *)D.b};
+            edm_f32_tile_body<TE>(t, bi, bj, (float *)body_lds);
+        } else {
+            const bool even = (a.step & 1) == 0;
+            const LifeTile t{D.n, D.ld, (const uint8_t *)(even ? D.a : D.b),
+                             (uint8_t *)(even ? D.b : D.a)};
+            life_tile_body<TL, kBatchThreads>(t, bi, bj, (uint32_t *)body_lds);
+        }
+    }
+}
+
+__global__ void k_batch_reset(uint32_t *heads, int32_t count)
+{
+    for (int k = threadIdx.x; k < count; k += blockDim.x) heads[k] = 0u;
+}
+
+typedef void (*StepKernel)(BatchStepArgs);
+
+template <int TE, int TL>
+static StepKernel step_kernel_tl() { return k_batch_step<TE, TL>; }
+
+template <int TE>
+static StepKernel step_kernel_te(int tl)
+{
+    switch (tl) {
+    case 8: return step_kernel_tl<TE, 8>();
+    case 16: return step_kernel_tl<TE, 16>();
+    case 32: return step_kernel_tl<TE, 32>();
+    case 64: return step_kernel_tl<TE, 64>();
+    }
+    return nullptr;
+}
+
+static StepKernel step_kernel(int te, int tl)
+{
+    switch (te) {
+    case 16: return step_kernel_te<16>(tl);
+    case 32: return step_kernel_te<32>(tl);
+    case 64: return step_kernel_te<64>(tl);
+    }
+    return nullptr;
+}
+
+}  // namespace trimap
+
+using namespace trimap;
+
+struct tri_batch {
+    int32_t count = 0, edm_tile = 0, life_tile = 0, steps = 0;
+    std::vector<int32_t> kind;
+    std::vector<int64_t> n, d, tiles;   // tiles: lambda blocks of each instance
+    std::vector<int64_t> prefix0;       // every instance (generation 0)
+    std::vector<int64_t> prefix1;       // Life instances (generations >= 1)
+    std::vector<int32_t> idx1;
+    std::vector<BatchDesc> desc;        // host copy (per-instance mode)
+    int device = 0;
+    uint32_t grid = 0;                  // persistent workgroups
+    StepKernel kernel = nullptr;
+    // device memory owned by the plan
+    BatchDesc *d_desc = nullptr;
+    int64_t *d_prefix0 = nullptr, *d_prefix1 = nullptr;
+    int32_t *d_idx1 = nullptr;
+    uint32_t *d_heads = nullptr;
+    bool bound = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+static void batch_free(tri_batch *b)
+{
+    if (!b) return;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    (void)hipFree(b->d_desc);
+    (void)hipFree(b->d_prefix0);
+    (void)hipFree(b->d_prefix1);
+    (void)hipFree(b->d_idx1);
+    (void)hipFree(b->d_heads);
+    delete b;
+}
+
+static BatchStepArgs step_args(const tri_batch *b, int s)
+{
+    BatchStepArgs a{};
+    a.desc = b->d_desc;
+    a.step = s;
+    a.head = b->d_heads + s;
+    if (s == 0) {
+        a.prefix = b->d_prefix0;
+        a.idx = nullptr;
+        a.count = b->count;
+        a.total = b->prefix0.back();
+    } else {
+        a.prefix = b->d_prefix1;
+        a.idx = b->d_idx1;
+        a.count = (int32_t)b->idx1.size();
+        a.total = b->prefix1.back();
+    }
+    return a;
+}
+
+// the persistent launches: counter reset, then one kernel per generation
+static tri_status batch_enqueue(const tri_batch *b, hipStream_t s)
+{
+    const int S = std::max(1, b->steps);
+    k_batch_reset<<<1, 256, 0, s>>>(b->d_heads, S);
+    TRI_HIP(hipGetLastError());
+    for (int k = 0; k < S; ++k) {
+        BatchStepArgs a = step_args(b, k);
+        if (a.total == 0) continue;
+        hipLaunchKernelGGL(b->kernel, dim3(b->grid), dim3(kBatchThreads), 0, s, a);
+        TRI_HIP(hipGetLastError());
+    }
+    return TRI_OK;
+}
+
+static tri_status batch_build_graph(tri_batch *b)
+{
+    const int S = std::max(1, b->steps);
+    TRI_HIP(hipGraphCreate(&b->graph, 0));
+    hipGraphNode_t prev = nullptr;
+    {
+        hipKernelNodeParams np{};
+        uint32_t *heads = b->d_heads;
+        int32_t cnt = S;
+        void *args[] = {&heads, &cnt};
+        np.func = (void *)k_batch_reset;
+        np.gridDim = dim3(1);
+        np.blockDim = dim3(256);
+        np.sharedMemBytes = 0;
+        np.kernelParams = args;
+        np.extra = nullptr;
+        TRI_HIP(hipGraphAddKernelNode(&prev, b->graph, nullptr, 0, &np));
+    }
+    for (int k = 0; k < S; ++k) {
+        BatchStepArgs a = step_args(b, k);
+        if (a.total == 0) continue;
+        hipKernelNodeParams np{};
+        void *args[] = {&a};
+        np.func = (void *)b->kernel;
+        np.gridDim = dim3(b->grid);
+        np.blockDim = dim3(kBatchThreads);
+        np.sharedMemBytes = 0;
+        np.kernelParams = args;
+        np.extra = nullptr;
+        hipGraphNode_t node;
+        TRI_HIP(hipGraphAddKernelNode(&node, b->graph, &prev, 1, &np));
+        prev = node;
+    }
+    TRI_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    return TRI_OK;
+}
+
+extern "C" {
+
+tri_status tri_batch_plan(tri_batch **out, int32_t count, const int32_t *host_kind,
+                          const int64_t *host_n, const int64_t *host_d, int edm_tile,
+                          int life_tile, int life_steps)
+{
+    clear_error();
+    if (!out) return fail(TRI_E_INVAL, "tri_batch_plan: out is NULL");
+    *out = nullptr;
+    if (count < 1 || !host_kind || !host_n || !host_d)
+        return fail(TRI_E_INVAL, "tri_batch_plan: need count >= 1 and host arrays");
+    if (edm_tile != 16 && edm_tile != 32 && edm_tile != 64)
+        return fail(TRI_E_INVAL, "tri_batch_plan: edm_tile %d not in {16,32,64}", edm_tile);
+    if (life_tile != 8 && life_tile != 16 && life_tile != 32 && life_tile != 64)
+        return fail(TRI_E_INVAL, "tri_batch_plan: life_tile %d not in {8,16,32,64}", life_tile);
+    if (life_steps < 0 || life_steps > 4096)
+        return fail(TRI_E_INVAL, "tri_batch_plan: life_steps %d not in [0, 4096]", life_steps);
+
+    tri_batch *b = new (std::nothrow) tri_batch();
+    if (!b) return fail(TRI_E_NOMEM, "tri_batch_plan: out of host memory");
+    b->count = count;
+    b->edm_tile = edm_tile;
+    b->life_tile = life_tile;
+    b->steps = life_steps;
+    b->kernel = step_kernel(edm_tile, life_tile);
+    b->prefix0.push_back(0);
+    b->prefix1.push_back(0);
+    for (int32_t k = 0; k < count; ++k) {
+        const int32_t kd = host_kind[k];
+        const int64_t nk = host_n[k], dk = host_d[k];
+        if (kd != TRI_KIND_EDM && kd != TRI_KIND_LIFE) {
+            batch_free(b);
+            return fail(TRI_E_INVAL, "tri_batch_plan: kind[%d] = %d", k, kd);
+        }
+        if (nk < 1 || nk >= (1ll << 20)) {
+            batch_free(b);
+            return fail(TRI_E_RANGE, "tri_batch_plan: n[%d] = %lld not in [1, 2^20)", k, (long long)nk);
+        }
+        if (kd == TRI_KIND_EDM && (dk < 1 || dk > 4096)) {
+            batch_free(b);
+            return fail(TRI_E_RANGE, "tri_batch_plan: d[%d] = %lld not in [1, 4096]", k, (long long)dk);
+        }
+        const int64_t ne = kd == TRI_KIND_EDM ? nk - 1 : nk;
+        const int tile = kd == TRI_KIND_EDM ? edm_tile : life_tile;
+        const int64_t m = (ne + tile - 1) / tile;
+        const int64_t T = m * (m + 1) / 2;
+        b->kind.push_back(kd);
+        b->n.push_back(nk);
+        b->d.push_back(dk);
+        b->tiles.push_back(T);
+        // generation 0 holds every distance-map tile and the Life tiles of
+        // the first generation (none when no generation is asked for)
+        b->prefix0.push_back(b->prefix0.back() + ((kd == TRI_KIND_LIFE && life_steps == 0) ? 0 : T));
+        if (kd == TRI_KIND_LIFE) {
+            b->prefix1.push_back(b->prefix1.back() + T);
+            b->idx1.push_back(k);
+        }
+    }
+    if (b->prefix0.back() >= (1ll << 32)) {
+        batch_free(b);
+        return fail(TRI_E_RANGE, "tri_batch_plan: more than 2^32 tiles in one generation");
+    }
+
+    hipError_t e = hipGetDevice(&b->device);
+    int cus = 0, per_cu = 0;
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)b->kernel,
+                                                         kBatchThreads, 0);
+    if (e != hipSuccess) {
+        batch_free(b);
+        return hip_fail(e, "tri_batch_plan: device query");
+    }
+    b->grid = (uint32_t)std::max(1, cus * std::max(1, per_cu));
+
+    const size_t nl = b->idx1.size();
+    const int S = std::max(1, life_steps);
+    e = hipMalloc(&b->d_desc, sizeof(BatchDesc) * count);
+    if (e == hipSuccess) e = hipMalloc(&b->d_prefix0, sizeof(int64_t) * (count + 1));
+    if (e == hipSuccess) e = hipMalloc(&b->d_prefix1, sizeof(int64_t) * (nl + 1));
+    if (e == hipSuccess && nl) e = hipMalloc(&b->d_idx1, sizeof(int32_t) * nl);
+    if (e == hipSuccess) e = hipMalloc(&b->d_heads, sizeof(uint32_t) * S);
+    if (e == hipSuccess)
+        e = hipMemcpy(b->d_prefix0, b->prefix0.data(), sizeof(int64_t) * (count + 1),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(b->d_prefix1, b->prefix1.data(), sizeof(int64_t) * (nl + 1),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess && nl)
+        e = hipMemcpy(b->d_idx1, b->idx1.data(), sizeof(int32_t) * nl, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        batch_free(b);
+        return hip_fail(e, "tri_batch_plan: device allocation");
+    }
+    *out = b;
+    return TRI_OK;
+}
+
+tri_status tri_batch_bind(tri_batch *b, void *const *host_a, void *const *host_b,
+                          const int64_t *host_ld)
+{
+    clear_error();
+    if (!b || !host_a || !host_b || !host_ld) return fail(TRI_E_INVAL, "tri_batch_bind: NULL argument");
+    std::vector<BatchDesc> desc(b->count);
+    for (int32_t k = 0; k < b->count; ++k) {
+        BatchDesc &D = desc[k];
+        D.kind = b->kind[k];
+        D.n = (int32_t)b->n[k];
+        D.d = (int32_t)b->d[k];
+        D.pad = 0;
+        D.ld = host_ld[k];
+        D.a = host_a[k];
+        D.b = host_b[k];
+        if (!D.a || !D.b || D.a == D.b)
+            return fail(TRI_E_INVAL, "tri_batch_bind: buffers of instance %d", k);
+        if (D.kind == TRI_KIND_EDM) {
+            if (D.ld < D.d || (((uintptr_t)D.a | (uintptr_t)D.b) & 3))
+                return fail(TRI_E_INVAL, "tri_batch_bind: instance %d: ldx < d or unaligned", k);
+        } else {
+            if (D.ld < D.n || D.ld % 4 || (((uintptr_t)D.a | (uintptr_t)D.b) & 3))
+                return fail(TRI_E_INVAL,
+                            "tri_batch_bind: instance %d: ld must be >= n, a multiple of 4", k);
+        }
+    }
+    TRI_HIP(hipMemcpy(b->d_desc, desc.data(), sizeof(BatchDesc) * b->count,
+                      hipMemcpyHostToDevice));
+    b->desc = desc;
+    if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+    if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+    tri_status st = batch_build_graph(b);
+    if (st != TRI_OK) return st;
+    b->bound = true;
+    return TRI_OK;
+}
+
+tri_status tri_batch_launch(tri_batch *b, int how, void *stream)
+{
+    clear_error();
+    if (!b) return fail(TRI_E_INVAL, "tri_batch_launch: plan is NULL");
+    if (!b->bound) return fail(TRI_E_INVAL, "tri_batch_launch: call tri_batch_bind first");
+    hipStream_t s = (hipStream_t)stream;
+    switch (how) {
+    case TRI_BATCH_GRAPH:
+        TRI_HIP(hipGraphLaunch(b->exec, s));
+        return TRI_OK;
+    case TRI_BATCH_STREAM:
+        return batch_enqueue(b, s);
+    case TRI_BATCH_PER_INSTANCE: {
+        // the same tile bodies, one launch per instance and generation
+        for (int32_t k = 0; k < b->count; ++k) {
+            const BatchDesc &D = b->desc[k];
+            const int64_t ne = D.kind == TRI_KIND_EDM ? D.n - 1 : D.n;
+            const int tile = D.kind == TRI_KIND_EDM ? b->edm_tile : b->life_tile;
+            const int64_t m = (ne + tile - 1) / tile;
+            const TileGrid g{(int32_t)m, 0u, (uint64_t)b->tiles[k]};
+            if (b->tiles[k] == 0) continue;
+            if (D.kind == TRI_KIND_EDM) {
+                const EdmTile t{D.n, D.d, D.ld, (const float *)D.a, (float *)D.b};
+                launch_edm_f32_lambda(tile, g, t, s);
+                TRI_HIP(hipGetLastError());
+            } else {
+                for (int st = 0; st < b->steps; ++st) {
+                    const bool even = (st & 1) == 0;
+                    const LifeTile t{D.n, D.ld, (const uint8_t *)(even ? D.a : D.b),
+                                     (uint8_t *)(even ? D.b : D.a)};
+                    launch_life_lambda(tile, g, t, s);
+                    TRI_HIP(hipGetLastError());
+                }
+            }
+        }
+        return TRI_OK;
+    }
+    }
+    return fail(TRI_E_INVAL, "tri_batch_launch: how = %d", how);
+}
+
+tri_status tri_batch_query(const tri_batch *b, tri_batch_info *info)
+{
+    clear_error();
+    if (!b || !info) return fail(TRI_E_INVAL, "tri_batch_query: NULL argument");
+    info->count = b->count;
+    info->life_instances = (int32_t)b->idx1.size();
+    info->edm_tile = b->edm_tile;
+    info->life_tile = b->life_tile;
+    info->life_steps = b->steps;
+    info->persistent_workgroups = (int32_t)b->grid;
+    info->items_generation0 = b->prefix0.back();
+    info->items_per_later_generation = b->prefix1.back();
+    return TRI_OK;
+}
+
+tri_status tri_batch_destroy(tri_batch *b)
+{
+    clear_error();
+    batch_free(b);
+    return TRI_OK;
+}
+
+}  // extern "C"

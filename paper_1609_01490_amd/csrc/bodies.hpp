@@ -1,0 +1,208 @@
+// Tile bodies shared by the one-launch-per-domain kernels and the batched
+// persistent kernel: a body computes one rho x rho tile (bi, bj) of one
+// triangular domain with NT threads, using the LDS buffer it is given.
+// Every body contains barriers, so all NT threads of the workgroup call it.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace trimap {
+
+// ---------------------------------------------------------------------------
+// Game of Life B3/S23 on the lower triangle (cells j > i and outside the
+// n x n square are dead and never written).  The tile plus a one-cell halo is
+// staged in LDS as 32-bit words of four cells; each thread updates a vertical
+// strip of words with byte-sliced arithmetic (neighbour sums never exceed 9,
+// so bytes never carry).
+// ---------------------------------------------------------------------------
+struct LifeTile {
+    int32_t n;
+    int64_t ld;
+    const uint8_t *cur;
+    uint8_t *nxt;
+};
+
+template <int TILE, int NT>
+struct LifeShape {
+    static constexpr int WPR = TILE / 4;                          // words per row
+    static constexpr int STRIPS_RAW = NT / WPR;
+    static constexpr int STRIPS = STRIPS_RAW < TILE ? STRIPS_RAW : TILE;  // strips
+    static constexpr int SH = TILE / STRIPS;                      // rows per strip
+    static constexpr int ACTIVE = STRIPS * WPR;                   // computing threads
+    static constexpr int LW = WPR + 2;                            // LDS words per row
+    static constexpr int LR = TILE + 2;                           // LDS rows
+    static constexpr int LDS_WORDS = LR * LW;
+    static_assert(SH * STRIPS == TILE && SH >= 1 && ACTIVE <= NT, "life tile shape");
+};
+
+// bytes of the word at column j (4-aligned) of row i that lie in the domain
+// (j + b <= i); 0 when none does
+__device__ __forceinline__ uint32_t life_domain_mask(int32_t i, int32_t j)
+{
+    const int32_t k = i - j;  // number of in-domain bytes minus one
+    if (k >= 3) return 0xFFFFFFFFu;
+    if (k < 0) return 0u;
+    return 0xFFFFFFFFu >> (8 * (3 - k));
+}
+
+// one byte (0x01) per zero byte of t, for bytes below 0x80
+__device__ __forceinline__ uint32_t life_zero_bytes(uint32_t t)
+{
+    const uint32_t nz = (t + 0x7F7F7F7Fu) | t;
+    return (~nz & 0x80808080u) >> 7;
+}
+
+// horizontal 3-sums of a word given its west and east neighbour words
+__device__ __forceinline__ uint32_t life_hsum3(uint32_t west, uint32_t w, uint32_t east)
+{
+    const uint32_t wl = __builtin_amdgcn_alignbit(w, west, 24);  // (w << 8) | (west >> 24)
+    const uint32_t wr = __builtin_amdgcn_alignbit(east, w, 8);   // (w >> 8) | (east << 24)
+    return w + wl + wr;
+}
+
+template <int TILE, int NT>
+__device__ __forceinline__ void life_tile_body(const LifeTile &p, int32_t bi, int32_t bj,
+                                               uint32_t *lds)
+{
+    using S = LifeShape<TILE, NT>;
+    const int32_t n = p.n;
+    const int64_t ld = p.ld;
+    const int32_t i0 = bi * TILE, j0 = bj * TILE;
+    // the halo and the tile lie wholly inside the domain and the square
+    const bool interior = (bi != bj) && bj > 0 && (i0 + TILE < n) && (j0 + TILE + 3 < i0);
+
+    // stage rows i0-1 .. i0+TILE, words at columns j0-4 .. j0+TILE
+    for (int idx = threadIdx.x; idx < S::LDS_WORDS; idx += NT) {
+        const int lr = idx / S::LW, lw = idx % S::LW;
+        const int32_t gi = i0 - 1 + lr;
+        const int32_t gj = j0 - 4 + 4 * lw;
+        uint32_t v = 0;
+        if (interior) {
+            v = *(const uint32_t *)(p.cur + (int64_t)gi * ld + gj);
+        } else if (gi >= 0 && gi < n && gj >= 0 && gj <= gi) {
+            v = *(const uint32_t *)(p.cur + (int64_t)gi * ld + gj) & life_domain_mask(gi, gj);
+        }
+        lds[idx] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x >= S::ACTIVE) return;
+
+    const int wc = threadIdx.x % S::WPR;  // word column inside the tile
+    const int st = threadIdx.x / S::WPR;  // strip
+    const int lw = wc + 1;
+    const int r0 = st * S::SH + 1;        // first LDS row of the strip
+    auto L = [lds](int r, int c) { return lds[r * S::LW + c]; };
+
+    uint32_t hprev = life_hsum3(L(r0 - 1, lw - 1), L(r0 - 1, lw), L(r0 - 1, lw + 1));
+    uint32_t hcur = life_hsum3(L(r0, lw - 1), L(r0, lw), L(r0, lw + 1));
+#pragma unroll
+    for (int k = 0; k < S::SH; ++k) {
+        const int lr = r0 + k;
+        const uint32_t hnext = life_hsum3(L(lr + 1, lw - 1), L(lr + 1, lw), L(lr + 1, lw + 1));
+        const uint32_t self = L(lr, lw);
+        const uint32_t s9 = hprev + hcur + hnext;  // 3x3 sum including the cell
+        // alive next: s9 == 3, or s9 == 4 and alive now
+        const uint32_t nv =
+            life_zero_bytes(s9 ^ 0x03030303u) | (life_zero_bytes(s9 ^ 0x04040404u) & self);
+        hprev = hcur;
+        hcur = hnext;
+
+        const int32_t gi = i0 + lr - 1;
+        const int32_t gj = j0 + 4 * wc;
+        if (interior || (gi < n && gj + 3 <= gi)) {
+            *(uint32_t *)(p.nxt + (int64_t)gi * ld + gj) = nv;
+        } else if (gi < n && gj <= gi) {  // the word holding the diagonal cell
+            uint8_t *q = p.nxt + (int64_t)gi * ld + gj;
+            for (int b = 0; b <= gi - gj; ++b) q[b] = (uint8_t)(nv >> (8 * b));
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Euclidean distance map, direct FP32: d(i, j) = sqrt(sum_k (x_ik - x_jk)^2)
+// for the strict lower triangle, tile (bi, bj) covering rows 1 + bi rho ..
+// and columns bj rho .., written to out[i (i - 1) / 2 + j].  Both point blocks
+// are staged in LDS dimension-major; each lane accumulates an RB x CB block.
+// ---------------------------------------------------------------------------
+struct EdmTile {
+    int32_t n;
+    int32_t d;
+    int64_t ldx;
+    const float *x;
+    float *out;
+};
+
+template <int TILE>
+struct EdmF32Shape {
+    static constexpr int NT = 256;
+    static constexpr int TX = 16;                  // lanes along columns
+    static constexpr int TY = NT / TX;             // lanes along rows
+    static constexpr int RB = TILE / TY;           // register rows per lane
+    static constexpr int CB = TILE / TX;           // register columns per lane
+    static constexpr int K = TILE >= 64 ? 32 : 64;  // dimensions staged per step
+    static constexpr int LDS_FLOATS = 2 * K * (TILE + 1);
+    static_assert(RB >= 1 && CB >= 1 && RB * TY == TILE && CB * TX == TILE, "edm tile");
+};
+
+template <int TILE>
+__device__ __forceinline__ void edm_f32_tile_body(const EdmTile &p, int32_t bi, int32_t bj,
+                                                  float *lds)
+{
+    using S = EdmF32Shape<TILE>;
+    float *XI = lds;                       // [K][TILE + 1]
+    float *XJ = lds + S::K * (TILE + 1);   // [K][TILE + 1]
+    const int32_t n = p.n, d = p.d;
+    const int64_t ldx = p.ldx;
+    const int32_t ri0 = 1 + bi * TILE;  // first row of the tile
+    const int32_t cj0 = bj * TILE;      // first column of the tile
+    const int tx = threadIdx.x % S::TX, ty = threadIdx.x / S::TX;
+
+    float acc[S::RB][S::CB];
+#pragma unroll
+    for (int a = 0; a < S::RB; ++a)
+#pragma unroll
+        for (int c = 0; c < S::CB; ++c) acc[a][c] = 0.f;
+
+    for (int32_t k0 = 0; k0 < d; k0 += S::K) {
+        for (int idx = threadIdx.x; idx < TILE * S::K; idx += S::NT) {
+            const int row = idx / S::K, kk = idx % S::K;
+            const int32_t k = k0 + kk;
+            const int32_t gi = ri0 + row, gj = cj0 + row;
+            XI[kk * (TILE + 1) + row] = (gi < n && k < d) ? p.x[(int64_t)gi * ldx + k] : 0.f;
+            XJ[kk * (TILE + 1) + row] = (gj < n && k < d) ? p.x[(int64_t)gj * ldx + k] : 0.f;
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int kk = 0; kk < S::K; ++kk) {
+            float xa[S::RB], xb[S::CB];
+#pragma unroll
+            for (int a = 0; a < S::RB; ++a) xa[a] = XI[kk * (TILE + 1) + ty + S::TY * a];
+#pragma unroll
+            for (int c = 0; c < S::CB; ++c) xb[c] = XJ[kk * (TILE + 1) + tx + S::TX * c];
+#pragma unroll
+            for (int a = 0; a < S::RB; ++a)
+#pragma unroll
+                for (int c = 0; c < S::CB; ++c) {
+                    const float df = xa[a] - xb[c];
+                    acc[a][c] = __builtin_fmaf(df, df, acc[a][c]);
+                }
+        }
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int a = 0; a < S::RB; ++a) {
+        const int32_t i = ri0 + ty + S::TY * a;
+        if (i >= n) continue;
+        float *orow = p.out + (int64_t)i * (i - 1) / 2;
+#pragma unroll
+        for (int c = 0; c < S::CB; ++c) {
+            const int32_t j = cj0 + tx + S::TX * c;
+            if (j < i) __builtin_nontemporal_store(__builtin_sqrtf(acc[a][c]), orow + j);
+        }
+    }
+}
+
+}  // namespace trimap

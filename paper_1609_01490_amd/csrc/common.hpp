@@ -7,6 +7,28 @@
 
 #include "trimap.h"
 
+#include <map>
+#include <mutex>
+#include <tuple>
+
+// Instantiated graphs a plan has built (one per buffers / step count), owned
+// by the plan and destroyed with it.
+struct PlanGraphKey {
+    const void *cur;
+    const void *nxt;
+    int64_t ld;
+    int steps;
+    bool operator<(const PlanGraphKey &o) const
+    {
+        return std::tie(cur, nxt, ld, steps) < std::tie(o.cur, o.nxt, o.ld, o.steps);
+    }
+};
+
+struct PlanGraphs {
+    std::mutex mu;
+    std::map<PlanGraphKey, hipGraphExec_t> execs;
+};
+
 // A plan: tile space of a triangular domain under one map (Section 3.1).
 // The strict lower triangle of side n is stored as the diagonal-including
 // triangle of side n - 1 shifted down one row (row_off = 1).
@@ -24,6 +46,7 @@ struct tri_plan {
     // launch grid of the map, in blocks (UTM: blocks of kUtmThreads threads)
     uint32_t gx, gy;
     int64_t blocks;
+    PlanGraphs *graphs;  // graph cache (the only mutable part of a plan)
 };
 
 namespace trimap {
@@ -35,13 +58,6 @@ constexpr uint32_t kMaxGridY = 65535u;
 tri_status fail(tri_status st, const char *fmt, ...);
 tri_status hip_fail(hipError_t e, const char *what);
 void clear_error();
-
-// Grid of a plan for a kernel of `threads` threads per block (tile maps:
-// one block per grid block of the map; UTM: one thread per cell).
-struct Launch {
-    dim3 grid;
-    bool ok;
-};
 
 }  // namespace trimap
 

@@ -24,6 +24,7 @@
 // below fixup_thr are recomputed directly in FP32 from the original
 // coordinates, which removes the cancellation error for near-duplicates.
 // The output write (4 B per pair) bounds this path.
+#include "bodies.hpp"
 #include "common.hpp"
 #include "maps.hpp"
 
@@ -33,83 +34,16 @@ TileGrid plan_tile_grid(const tri_plan *p);
 
 struct EdmArgs {
     TileGrid g;
-    int32_t n;
-    int32_t d;
-    int64_t ldx;
-    const float *x;
-    float *out;
-};
-
-template <int TILE>
-struct EdmF32Shape {
-    static constexpr int NT = 256;
-    static constexpr int TX = 16;                 // lanes along columns
-    static constexpr int TY = NT / TX;            // lanes along rows
-    static constexpr int RB = TILE / TY;          // register rows per lane
-    static constexpr int CB = TILE / TX;          // register columns per lane
-    static constexpr int K = TILE >= 64 ? 32 : 64; // dimensions staged per step
-    static_assert(RB >= 1 && CB >= 1 && RB * TY == TILE && CB * TX == TILE, "edm tile");
+    EdmTile t;
 };
 
 template <int MAP, int TILE>
 __global__ void __launch_bounds__(256) k_edm_f32(EdmArgs p)
 {
-    using S = EdmF32Shape<TILE>;
     int32_t bi, bj;
     if (!tile_of_block<MAP>(p.g, bi, bj)) return;
-
-    __shared__ float XI[S::K][TILE + 1];
-    __shared__ float XJ[S::K][TILE + 1];
-    const int32_t n = p.n, d = p.d;
-    const int64_t ldx = p.ldx;
-    const int32_t ri0 = 1 + bi * TILE;  // first row of the tile
-    const int32_t cj0 = bj * TILE;      // first column of the tile
-    const int tx = threadIdx.x % S::TX, ty = threadIdx.x / S::TX;
-
-    float acc[S::RB][S::CB];
-#pragma unroll
-    for (int a = 0; a < S::RB; ++a)
-#pragma unroll
-        for (int c = 0; c < S::CB; ++c) acc[a][c] = 0.f;
-
-    for (int32_t k0 = 0; k0 < d; k0 += S::K) {
-        for (int idx = threadIdx.x; idx < TILE * S::K; idx += S::NT) {
-            const int row = idx / S::K, kk = idx % S::K;
-            const int32_t k = k0 + kk;
-            const int32_t gi = ri0 + row, gj = cj0 + row;
-            XI[kk][row] = (gi < n && k < d) ? p.x[(int64_t)gi * ldx + k] : 0.f;
-            XJ[kk][row] = (gj < n && k < d) ? p.x[(int64_t)gj * ldx + k] : 0.f;
-        }
-        __syncthreads();
-#pragma unroll 8
-        for (int kk = 0; kk < S::K; ++kk) {
-            float xa[S::RB], xb[S::CB];
-#pragma unroll
-            for (int a = 0; a < S::RB; ++a) xa[a] = XI[kk][ty + S::TY * a];
-#pragma unroll
-            for (int c = 0; c < S::CB; ++c) xb[c] = XJ[kk][tx + S::TX * c];
-#pragma unroll
-            for (int a = 0; a < S::RB; ++a)
-#pragma unroll
-                for (int c = 0; c < S::CB; ++c) {
-                    const float df = xa[a] - xb[c];
-                    acc[a][c] = __builtin_fmaf(df, df, acc[a][c]);
-                }
-        }
-        __syncthreads();
-    }
-
-#pragma unroll
-    for (int a = 0; a < S::RB; ++a) {
-        const int32_t i = ri0 + ty + S::TY * a;
-        if (i >= n) continue;
-        float *orow = p.out + (int64_t)i * (i - 1) / 2;
-#pragma unroll
-        for (int c = 0; c < S::CB; ++c) {
-            const int32_t j = cj0 + tx + S::TX * c;
-            if (j < i) __builtin_nontemporal_store(__builtin_sqrtf(acc[a][c]), orow + j);
-        }
-    }
+    __shared__ float lds[EdmF32Shape<TILE>::LDS_FLOATS];
+    edm_f32_tile_body<TILE>(p.t, bi, bj, lds);
 }
 
 template <int MAP>
@@ -137,9 +71,10 @@ static bool edm_f32(const tri_plan *p, const EdmArgs &a, hipStream_t s)
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kEdmTile = 128;     // output tile of the MFMA kernel
-constexpr int kColsumRows = 256;  // rows per block of the column-sum pass
+constexpr int kColsumRows = 64;   // rows per block of the column-sum pass
 
 // Workspace of the MFMA modes (all offsets 256-byte aligned).
 struct EdmWs {
@@ -178,14 +113,22 @@ __global__ void __launch_bounds__(256) k_edm_colsum(const float *x, int32_t n, i
     }
 }
 
+// mean[k] = (sum over blocks of partial[b][k]) / n: one workgroup per
+// dimension, a fixed-order strided sum per thread, then a fixed tree.
 __global__ void __launch_bounds__(256) k_edm_mean(const float *partial, int32_t nb, int32_t n,
                                                   int32_t dp, float *mean)
 {
-    for (int32_t k = threadIdx.x; k < dp; k += 256) {
-        float s = 0.f;
-        for (int32_t b = 0; b < nb; ++b) s += partial[(int64_t)b * dp + k];
-        mean[k] = s / (float)n;
+    __shared__ float red[256];
+    const int32_t k = blockIdx.x;
+    float s = 0.f;
+    for (int32_t b = threadIdx.x; b < nb; b += 256) s += partial[(int64_t)b * dp + k];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h >= 1; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
     }
+    if (threadIdx.x == 0) mean[k] = red[0] / (float)n;
 }
 
 // One wave per point: centre, split into BF16 hi/lo, and the norm of the
@@ -230,7 +173,7 @@ struct EdmMfmaArgs {
     float thr;
 };
 
-__device__ __forceinline__ float direct_d2(const float *x, int64_t ldx, int32_t d, int32_t i,
+__device__ __noinline__ float direct_d2(const float *x, int64_t ldx, int32_t d, int32_t i,
                                            int32_t j)
 {
     const float *xi = x + (int64_t)i * ldx, *xj = x + (int64_t)j * ldx;
@@ -242,30 +185,98 @@ __device__ __forceinline__ float direct_d2(const float *x, int64_t ldx, int32_t 
     return s;
 }
 
+// LDS staging of the operands: the tile's 128 row points and 128 column
+// points, kKC dimensions at a time, rows padded so that the 16-byte operand
+// reads of eight consecutive rows hit distinct banks.  The next chunk is
+// loaded into registers while the matrix cores work on the current one.
+constexpr int kKC = 64;                // dimensions per LDS chunk
+constexpr int kRS = kKC + 8;           // operand row stride in bf16 (144 bytes)
+constexpr int kPlaneBytes = kEdmTile * kRS * 2;
+constexpr int kVecPerThread = kEdmTile * kKC / 8 / 256;  // 16-byte vectors per plane
+
+// Workgroup barrier that orders LDS traffic only: wait for this wave's LDS
+// operations, then s_barrier.  Unlike __syncthreads() it does not wait for
+// outstanding global stores or prefetch loads.  (A global load that feeds
+// LDS is waited for by the data dependency of the LDS store.)
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0), vmcnt and expcnt untouched
+    __builtin_amdgcn_s_barrier();
+}
+
+template <bool SPLIT>
+struct EdmStage {
+    bf16x8 ha[kVecPerThread], hb[kVecPerThread], la[kVecPerThread], lb[kVecPerThread];
+};
+
+template <bool SPLIT>
+__device__ __forceinline__ void edm_stage_load(const EdmMfmaArgs &p, int32_t RW, int32_t CW,
+                                               int32_t k0, EdmStage<SPLIT> &st)
+{
+    const int32_t n = p.n, dp = p.dp;
+    const int32_t kn = min(kKC, dp - k0);
+#pragma unroll
+    for (int u = 0; u < kVecPerThread; ++u) {
+        const int v = threadIdx.x + 256 * u;
+        const int row = v / (kKC / 8), c8 = (v % (kKC / 8)) * 8;
+        const int32_t ra = min(RW + row, n - 1), rb = min(CW + row, n - 1);
+        st.ha[u] = st.hb[u] = st.la[u] = st.lb[u] = bf16x8{};
+        if (c8 < kn) {
+            st.ha[u] = *(const bf16x8 *)(p.hi + (int64_t)ra * dp + k0 + c8);
+            st.hb[u] = *(const bf16x8 *)(p.hi + (int64_t)rb * dp + k0 + c8);
+            if (SPLIT) {
+                st.la[u] = *(const bf16x8 *)(p.lo + (int64_t)ra * dp + k0 + c8);
+                st.lb[u] = *(const bf16x8 *)(p.lo + (int64_t)rb * dp + k0 + c8);
+            }
+        }
+    }
+}
+
+template <bool SPLIT>
+__device__ __forceinline__ void edm_stage_store(const EdmStage<SPLIT> &st, __bf16 *sAh, __bf16 *sBh,
+                                                __bf16 *sAl, __bf16 *sBl)
+{
+#pragma unroll
+    for (int u = 0; u < kVecPerThread; ++u) {
+        const int v = threadIdx.x + 256 * u;
+        const int row = v / (kKC / 8), c8 = (v % (kKC / 8)) * 8;
+        *(bf16x8 *)&sAh[row * kRS + c8] = st.ha[u];
+        *(bf16x8 *)&sBh[row * kRS + c8] = st.hb[u];
+        if (SPLIT) {
+            *(bf16x8 *)&sAl[row * kRS + c8] = st.la[u];
+            *(bf16x8 *)&sBl[row * kRS + c8] = st.lb[u];
+        }
+    }
+}
+
 template <int MAP, bool SPLIT>
 __global__ void __launch_bounds__(256) k_edm_mfma(EdmMfmaArgs p)
 {
+    constexpr int PLANES = SPLIT ? 4 : 2;
+    __shared__ __attribute__((aligned(16))) unsigned char lds[PLANES * kPlaneBytes];
+    __shared__ __attribute__((aligned(16))) float sN[2 * kEdmTile];
+    __bf16 *sAh = (__bf16 *)lds;
+    __bf16 *sBh = (__bf16 *)(lds + kPlaneBytes);
+    __bf16 *sAl = (__bf16 *)(lds + 2 * kPlaneBytes);  // split only
+    __bf16 *sBl = (__bf16 *)(lds + 3 * kPlaneBytes);
+
     int32_t bi, bj;
     if (!tile_of_block<MAP>(p.g, bi, bj)) return;
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int32_t n = p.n;
-    const int32_t R0 = 1 + bi * kEdmTile + 64 * (w >> 1);  // first row of this wave
-    const int32_t C0 = bj * kEdmTile + 64 * (w & 1);       // first column of this wave
-    // no barrier in this kernel: a wave with no pair j < i < n leaves early
-    if (R0 >= n || C0 >= R0 + 63) return;
+    const int t = threadIdx.x, w = t >> 6, l = t & 63;
+    const int32_t n = p.n, dp = p.dp;
+    const int32_t RW = 1 + bi * kEdmTile;  // first row point of the tile
+    const int32_t CW = bj * kEdmTile;      // first column point of the tile
 
-    const int lr = l & 31, lk = (l >> 5) * 8;
-    const int32_t dp = p.dp;
-    const __bf16 *ah[2], *bh[2];
-#pragma unroll
-    for (int a = 0; a < 2; ++a) {
-        const int32_t r = min(R0 + 32 * a + lr, n - 1);
-        const int32_t c = min(C0 + 32 * a + lr, n - 1);
-        ah[a] = p.hi + (int64_t)r * dp + lk;
-        bh[a] = p.hi + (int64_t)c * dp + lk;
+    EdmStage<SPLIT> st;
+    edm_stage_load<SPLIT>(p, RW, CW, 0, st);
+    // norms of the tile's row and column points
+    {
+        const int32_t q = t < kEdmTile ? RW + t : CW + (t - kEdmTile);
+        sN[t] = p.norms[min(q, n - 1)];
     }
-    const int64_t lo_off = p.lo - p.hi;
 
+    const int wr = w >> 1, wc = w & 1;
+    const int lr = l & 31, lk = (l >> 5) * 8;
     f32x16 acc[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -274,47 +285,97 @@ __global__ void __launch_bounds__(256) k_edm_mfma(EdmMfmaArgs p)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
 
-    for (int32_t k0 = 0; k0 < dp; k0 += 16) {
-        bf16x8 Ah[2], Bh[2], Al[2], Bl[2];
+    for (int32_t k0 = 0; k0 < dp; k0 += kKC) {
+        const int32_t kn = min(kKC, dp - k0);  // multiple of 16
+        edm_stage_store<SPLIT>(st, sAh, sBh, sAl, sBl);
+        lds_barrier();
+        if (k0 + kKC < dp) edm_stage_load<SPLIT>(p, RW, CW, k0 + kKC, st);  // in flight
+        for (int kk = 0; kk < kn; kk += 16) {
+            bf16x8 Ah[2], Bh[2], Al[2], Bl[2];
 #pragma unroll
-        for (int a = 0; a < 2; ++a) {
-            Ah[a] = *(const bf16x8 *)(ah[a] + k0);
-            Bh[a] = *(const bf16x8 *)(bh[a] + k0);
-            if (SPLIT) {
-                Al[a] = *(const bf16x8 *)(ah[a] + lo_off + k0);
-                Bl[a] = *(const bf16x8 *)(bh[a] + lo_off + k0);
-            }
-        }
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int b = 0; b < 2; ++b) {
-                acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah[a], Bh[b], acc[a][b], 0, 0, 0);
+            for (int a = 0; a < 2; ++a) {
+                const int ia = (64 * wr + 32 * a + lr) * kRS + kk + lk;
+                const int ib = (64 * wc + 32 * a + lr) * kRS + kk + lk;
+                Ah[a] = *(const bf16x8 *)&sAh[ia];
+                Bh[a] = *(const bf16x8 *)&sBh[ib];
                 if (SPLIT) {
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah[a], Bl[b], acc[a][b], 0, 0, 0);
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Al[a], Bh[b], acc[a][b], 0, 0, 0);
+                    Al[a] = *(const bf16x8 *)&sAl[ia];
+                    Bl[a] = *(const bf16x8 *)&sBl[ib];
                 }
             }
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah[a], Bh[b], acc[a][b], 0, 0, 0);
+                    if (SPLIT) {
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah[a], Bl[b], acc[a][b], 0, 0, 0);
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Al[a], Bh[b], acc[a][b], 0, 0, 0);
+                    }
+                }
+        }
+        lds_barrier();
     }
 
     // D[m][n] of a 32 x 32 block: lane l holds column n = l % 32 and, in
-    // register r, row m = 8 (r / 4) + 4 (l / 32) + r % 4
+    // register r, row m = 8 (r / 4) + 4 (l / 32) + r % 4.
+    const int32_t R0 = RW + 64 * wr, C0 = CW + 64 * wc;  // this wave's 64 x 64 block
+    if (R0 >= n || C0 >= R0 + 63) return;  // no pair j < i < n here (no barrier follows)
+    // d^2 = |x_i|^2 + |x_j|^2 - 2 x_i.x_j, in place
+    bool near = false;
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-        const int32_t j = C0 + 32 * b + lr;
-        const float nj = p.norms[min(j, n - 1)];
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float4 ni = *(const float4 *)&sN[64 * wr + 32 * a + 8 * q + 4 * (l >> 5)];
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const float nj = sN[kEdmTile + 64 * wc + 32 * b + lr];
+                f32x16 &v = acc[a][b];
+                v[4 * q + 0] = __builtin_fmaf(-2.f, v[4 * q + 0], ni.x + nj);
+                v[4 * q + 1] = __builtin_fmaf(-2.f, v[4 * q + 1], ni.y + nj);
+                v[4 * q + 2] = __builtin_fmaf(-2.f, v[4 * q + 2], ni.z + nj);
+                v[4 * q + 3] = __builtin_fmaf(-2.f, v[4 * q + 3], ni.w + nj);
+                near |= (v[4 * q + 0] < p.thr) | (v[4 * q + 1] < p.thr) |
+                        (v[4 * q + 2] < p.thr) | (v[4 * q + 3] < p.thr);
+            }
+        }
+    // near-duplicates (rare): recompute those squares directly in FP32
+    if (__any(near)) {
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int32_t i = R0 + 32 * a + 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
-                if (i >= n || j >= i) continue;
-                float d2 = p.norms[i] + nj - 2.f * acc[a][b][r];
-                if (d2 < p.thr) d2 = direct_d2(p.x, p.ldx, p.d, i, j);
-                __builtin_nontemporal_store(__builtin_sqrtf(fmaxf(d2, 0.f)),
-                                            p.out + (int64_t)i * (i - 1) / 2 + j);
-            }
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int32_t i = R0 + 32 * a + 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
+                    const int32_t j = C0 + 32 * b + lr;
+                    if (acc[a][b][r] < p.thr && i < n && j < i)
+                        acc[a][b][r] = direct_d2(p.x, p.ldx, p.d, i, j);
+                }
     }
+    // every pair of the wave's block is in the domain unless the block
+    // touches the diagonal or the last row
+    const bool full = (C0 + 63 < R0) && (R0 + 63 < n);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            int32_t i = R0 + 32 * a + 8 * q + 4 * (l >> 5);
+            uint64_t base = (uint64_t)i * (uint64_t)(i - 1) / 2;  // start of row i
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    const int32_t j = C0 + 32 * b + lr;
+                    const float d2 = acc[a][b][4 * q + u];
+                    if (full || (i < n && j < i))
+                        p.out[base + j] = __builtin_amdgcn_sqrtf(fmaxf(d2, 0.f));
+                }
+                base += (uint64_t)i;  // start of row i + 1
+                ++i;
+            }
+        }
 }
 
 template <int MAP>
@@ -334,6 +395,23 @@ static bool edm_mfma(const tri_plan *p, const EdmMfmaArgs &a, bool split, hipStr
     case TRI_MAP_RB: edm_mfma_launch<MAP_RB>(p, a, split, s); return true;
     case TRI_MAP_REC: edm_mfma_launch<MAP_REC>(p, a, split, s); return true;
     case TRI_MAP_LAMBDA: edm_mfma_launch<MAP_LAMBDA>(p, a, split, s); return true;
+    }
+    return false;
+}
+
+// One distance-map domain under lambda with the FP32 body (batched
+// per-instance mode); false for an unsupported tile.
+bool launch_edm_f32_lambda(int tile, const TileGrid &g, const EdmTile &t, hipStream_t s)
+{
+    EdmArgs a{g, t};
+    uint32_t gx, gy;
+    if (g.T <= (1ull << 24)) { gx = (uint32_t)g.T; gy = 1; }
+    else { gx = 1u << 16; gy = (uint32_t)((g.T + gx - 1) / gx); }
+    const dim3 grid(gx, gy);
+    switch (tile) {
+    case 16: k_edm_f32<MAP_LAMBDA, 16><<<grid, 256, 0, s>>>(a); return true;
+    case 32: k_edm_f32<MAP_LAMBDA, 32><<<grid, 256, 0, s>>>(a); return true;
+    case 64: k_edm_f32<MAP_LAMBDA, 64><<<grid, 256, 0, s>>>(a); return true;
     }
     return false;
 }
@@ -385,11 +463,13 @@ extern "C" tri_status tri_edm(const tri_plan *p, const float *x, int64_t d, int6
     if (((uintptr_t)x | (uintptr_t)out) & 3) return fail(TRI_E_INVAL, "tri_edm: unaligned buffer");
     hipStream_t s = (hipStream_t)stream;
     if (mode == TRI_EDM_FP32) {
-        EdmArgs a{plan_tile_grid(p), (int32_t)p->n, (int32_t)d, ldx, x, out};
+        EdmArgs a{plan_tile_grid(p), EdmTile{(int32_t)p->n, (int32_t)d, ldx, x, out}};
         if (!edm_f32(p, a, s)) return fail(TRI_E_UNSUPPORTED, "tri_edm: tile");
         TRI_HIP(hipGetLastError());
         return TRI_OK;
     }
+    if ((uintptr_t)out & 15)
+        return fail(TRI_E_INVAL, "tri_edm: the MFMA modes need a 16-byte aligned output");
     const EdmWs L = edm_ws_layout(p->n, d);
     if (!ws || ws_bytes < L.total)
         return fail(TRI_E_NOMEM, "tri_edm: workspace of %zu bytes needed", L.total);
@@ -402,7 +482,7 @@ extern "C" tri_status tri_edm(const tri_plan *p, const float *x, int64_t d, int6
     const int32_t n = (int32_t)p->n, dd = (int32_t)d, dp = (int32_t)L.dp;
     const bool split = (mode == TRI_EDM_BF16X3);
     k_edm_colsum<<<dim3((uint32_t)L.nb), 256, 0, s>>>(x, n, dd, ldx, dp, partial);
-    k_edm_mean<<<1, 256, 0, s>>>(partial, (int32_t)L.nb, n, dp, mean);
+    k_edm_mean<<<dim3((uint32_t)dp), 256, 0, s>>>(partial, (int32_t)L.nb, n, dp, mean);
     if (split)
         k_edm_split<true><<<dim3((uint32_t)n), 64, 0, s>>>(x, dd, ldx, dp, mean, hi, lo, norms);
     else

@@ -188,8 +188,13 @@ tri_status tri_map_plan(tri_plan **out, int64_t n, int tile, int map, int includ
     p.gy = (uint32_t)gy;
     p.blocks = (int64_t)(gx * gy);
 
+    p.graphs = new (std::nothrow) PlanGraphs();
+    if (!p.graphs) return fail(TRI_E_NOMEM, "tri_map_plan: out of host memory");
     tri_plan *h = new (std::nothrow) tri_plan(p);
-    if (!h) return fail(TRI_E_NOMEM, "tri_map_plan: out of host memory");
+    if (!h) {
+        delete p.graphs;
+        return fail(TRI_E_NOMEM, "tri_map_plan: out of host memory");
+    }
     *out = h;
     return TRI_OK;
 }
@@ -197,6 +202,11 @@ tri_status tri_map_plan(tri_plan **out, int64_t n, int tile, int map, int includ
 tri_status tri_plan_destroy(tri_plan *plan)
 {
     clear_error();
+    if (!plan) return TRI_OK;
+    if (plan->graphs) {
+        for (auto &kv : plan->graphs->execs) (void)hipGraphExecDestroy(kv.second);
+        delete plan->graphs;
+    }
     delete plan;
     return TRI_OK;
 }

@@ -2,13 +2,16 @@
 // neighbourhood case of the paper (Section 5, where lambda keeps the 2-D
 // thread block and therefore the tile with its halo).
 //
-// One workgroup per rho x rho tile.  The tile plus a one-cell halo is staged
-// in LDS as 32-bit words of four cells ((rho + 2) rows x (rho/4 + 2) words:
-// the halo columns come in as whole words).  Each thread then updates a
-// vertical strip of words with byte-sliced (SWAR) arithmetic: four cells per
-// 32-bit operation, neighbour sums never exceed 9 so no byte carries.
-// Cells outside the domain (j > i, outside the n x n square) are zeroed as
-// they are loaded and never stored, so the upper triangle is never touched.
+// One workgroup per rho x rho tile; the tile body (life_tile_body) stages the
+// tile plus a one-cell halo in LDS as 32-bit words of four cells ((rho + 2)
+// rows x (rho/4 + 2) words: the halo columns come in as whole words) and
+// updates it with byte-sliced (SWAR) arithmetic, four cells per 32-bit
+// operation.  Cells outside the domain (j > i, outside the n x n square) are
+// zeroed as they are loaded and never stored, so the upper triangle is never
+// touched.
+#include <mutex>
+
+#include "bodies.hpp"
 #include "common.hpp"
 #include "maps.hpp"
 
@@ -18,103 +21,21 @@ TileGrid plan_tile_grid(const tri_plan *p);
 
 struct LifeArgs {
     TileGrid g;
-    int32_t n;
-    int64_t ld;
-    const uint8_t *cur;
-    uint8_t *nxt;
+    LifeTile t;
 };
 
+// threads per workgroup of the one-launch-per-step kernel
 template <int TILE>
-struct LifeShape {
-    static constexpr int WPR = TILE / 4;                                  // words per row
-    static constexpr int NT = TILE == 8 ? 16 : (TILE == 64 ? 256 : 64);   // threads
-    static constexpr int STRIPS = NT / WPR;                               // strips per column
-    static constexpr int SH = TILE / STRIPS;                              // rows per strip
-    static constexpr int LW = WPR + 2;                                    // LDS words per row
-    static constexpr int LR = TILE + 2;                                   // LDS rows
-    static_assert(SH * STRIPS == TILE && SH >= 1, "life tile shape");
-};
-
-// bytes of the word at column j (4-aligned) of row i that lie in the domain
-// (j + b <= i); 0 when none does
-__device__ __forceinline__ uint32_t domain_mask(int32_t i, int32_t j)
-{
-    const int32_t k = i - j;  // number of in-domain bytes minus one
-    if (k >= 3) return 0xFFFFFFFFu;
-    if (k < 0) return 0u;
-    return 0xFFFFFFFFu >> (8 * (3 - k));
-}
-
-// one byte (0x01) per zero byte of t, for bytes below 0x80
-__device__ __forceinline__ uint32_t zero_bytes(uint32_t t)
-{
-    const uint32_t nz = (t + 0x7F7F7F7Fu) | t;
-    return (~nz & 0x80808080u) >> 7;
-}
-
-// horizontal 3-sums of a word given its west and east neighbour words
-__device__ __forceinline__ uint32_t hsum3(uint32_t west, uint32_t w, uint32_t east)
-{
-    const uint32_t wl = __builtin_amdgcn_alignbit(w, west, 24);  // (w << 8) | (west >> 24)
-    const uint32_t wr = __builtin_amdgcn_alignbit(east, w, 8);   // (w >> 8) | (east << 24)
-    return w + wl + wr;
-}
+constexpr int life_threads() { return TILE == 8 ? 16 : (TILE == 64 ? 256 : 64); }
 
 template <int MAP, int TILE>
-__global__ void __launch_bounds__(LifeShape<TILE>::NT) k_life(LifeArgs p)
+__global__ void __launch_bounds__(life_threads<TILE>()) k_life(LifeArgs p)
 {
-    using S = LifeShape<TILE>;
+    constexpr int NT = life_threads<TILE>();
     int32_t bi, bj;
     if (!tile_of_block<MAP>(p.g, bi, bj)) return;
-
-    __shared__ uint32_t L[S::LR][S::LW];
-    const int32_t n = p.n;
-    const int64_t ld = p.ld;
-    const int32_t i0 = bi * TILE, j0 = bj * TILE;
-    const bool interior = (bi != bj) && bj > 0 && (i0 + TILE < n) && (j0 + TILE + 3 < i0);
-
-    // stage rows i0-1 .. i0+TILE, words at columns j0-4 .. j0+TILE
-    for (int idx = threadIdx.x; idx < S::LR * S::LW; idx += S::NT) {
-        const int lr = idx / S::LW, lw = idx % S::LW;
-        const int32_t gi = i0 - 1 + lr;
-        const int32_t gj = j0 - 4 + 4 * lw;
-        uint32_t v = 0;
-        if (interior) {
-            v = *(const uint32_t *)(p.cur + (int64_t)gi * ld + gj);
-        } else if (gi >= 0 && gi < n && gj >= 0 && gj <= gi) {
-            v = *(const uint32_t *)(p.cur + (int64_t)gi * ld + gj) & domain_mask(gi, gj);
-        }
-        L[lr][lw] = v;
-    }
-    __syncthreads();
-
-    const int wc = threadIdx.x % S::WPR;  // word column inside the tile
-    const int st = threadIdx.x / S::WPR;  // strip
-    const int lw = wc + 1;
-    const int r0 = st * S::SH + 1;        // first LDS row of the strip
-
-    uint32_t hprev = hsum3(L[r0 - 1][lw - 1], L[r0 - 1][lw], L[r0 - 1][lw + 1]);
-    uint32_t hcur = hsum3(L[r0][lw - 1], L[r0][lw], L[r0][lw + 1]);
-#pragma unroll
-    for (int k = 0; k < S::SH; ++k) {
-        const int lr = r0 + k;
-        const uint32_t hnext = hsum3(L[lr + 1][lw - 1], L[lr + 1][lw], L[lr + 1][lw + 1]);
-        const uint32_t self = L[lr][lw];
-        const uint32_t s9 = hprev + hcur + hnext;  // 3x3 sum including the cell
-        // alive next: s9 == 3, or s9 == 4 and alive now
-        const uint32_t nv = zero_bytes(s9 ^ 0x03030303u) | (zero_bytes(s9 ^ 0x04040404u) & self);
-        hprev = hcur;
-        hcur = hnext;
-
-        const int32_t gi = i0 + lr - 1;
-        const int32_t gj = j0 + 4 * wc;
-        if (interior || (gi < n && gj + 3 <= gi)) {
-            *(uint32_t *)(p.nxt + (int64_t)gi * ld + gj) = nv;
-        } else if (gi < n && gj <= gi) {  // the word holding the diagonal cell
-            uint8_t *q = p.nxt + (int64_t)gi * ld + gj;
-            for (int b = 0; b <= gi - gj; ++b) q[b] = (uint8_t)(nv >> (8 * b));
-        }
-    }
+    __shared__ uint32_t L[LifeShape<TILE, NT>::LDS_WORDS];
+    life_tile_body<TILE, NT>(p.t, bi, bj, L);
 }
 
 template <int MAP>
@@ -122,10 +43,34 @@ static bool life_tile(const tri_plan *p, const LifeArgs &a, hipStream_t s)
 {
     const dim3 grid(p->gx, p->gy);
     switch (p->tile) {
-    case 8: k_life<MAP, 8><<<grid, LifeShape<8>::NT, 0, s>>>(a); return true;
-    case 16: k_life<MAP, 16><<<grid, LifeShape<16>::NT, 0, s>>>(a); return true;
-    case 32: k_life<MAP, 32><<<grid, LifeShape<32>::NT, 0, s>>>(a); return true;
-    case 64: k_life<MAP, 64><<<grid, LifeShape<64>::NT, 0, s>>>(a); return true;
+    case 8: k_life<MAP, 8><<<grid, life_threads<8>(), 0, s>>>(a); return true;
+    case 16: k_life<MAP, 16><<<grid, life_threads<16>(), 0, s>>>(a); return true;
+    case 32: k_life<MAP, 32><<<grid, life_threads<32>(), 0, s>>>(a); return true;
+    case 64: k_life<MAP, 64><<<grid, life_threads<64>(), 0, s>>>(a); return true;
+    }
+    return false;
+}
+
+// kernel address and block size of the one-step kernel of a plan
+template <int MAP>
+static bool life_kernel_tile(int tile, const void *&fn, int &threads)
+{
+    switch (tile) {
+    case 8: fn = (const void *)k_life<MAP, 8>; threads = life_threads<8>(); return true;
+    case 16: fn = (const void *)k_life<MAP, 16>; threads = life_threads<16>(); return true;
+    case 32: fn = (const void *)k_life<MAP, 32>; threads = life_threads<32>(); return true;
+    case 64: fn = (const void *)k_life<MAP, 64>; threads = life_threads<64>(); return true;
+    }
+    return false;
+}
+
+static bool life_kernel(const tri_plan *p, const void *&fn, int &threads)
+{
+    switch (p->map) {
+    case TRI_MAP_BB: return life_kernel_tile<MAP_BB>(p->tile, fn, threads);
+    case TRI_MAP_RB: return life_kernel_tile<MAP_RB>(p->tile, fn, threads);
+    case TRI_MAP_REC: return life_kernel_tile<MAP_REC>(p->tile, fn, threads);
+    case TRI_MAP_LAMBDA: return life_kernel_tile<MAP_LAMBDA>(p->tile, fn, threads);
     }
     return false;
 }
@@ -139,6 +84,67 @@ static bool life_step(const tri_plan *p, const LifeArgs &a, hipStream_t s)
     case TRI_MAP_LAMBDA: return life_tile<MAP_LAMBDA>(p, a, s);
     }
     return false;
+}
+
+// One Life generation of one domain under lambda (batched per-instance
+// mode); false for an unsupported tile.
+bool launch_life_lambda(int tile, const TileGrid &g, const LifeTile &t, hipStream_t s)
+{
+    LifeArgs a{g, t};
+    uint32_t gx, gy;
+    if (g.T <= (1ull << 24)) { gx = (uint32_t)g.T; gy = 1; }
+    else { gx = 1u << 16; gy = (uint32_t)((g.T + gx - 1) / gx); }
+    const dim3 grid(gx, gy);
+    switch (tile) {
+    case 8: k_life<MAP_LAMBDA, 8><<<grid, life_threads<8>(), 0, s>>>(a); return true;
+    case 16: k_life<MAP_LAMBDA, 16><<<grid, life_threads<16>(), 0, s>>>(a); return true;
+    case 32: k_life<MAP_LAMBDA, 32><<<grid, life_threads<32>(), 0, s>>>(a); return true;
+    case 64: k_life<MAP_LAMBDA, 64><<<grid, life_threads<64>(), 0, s>>>(a); return true;
+    }
+    return false;
+}
+
+// The generations of one (plan, buffers, steps) as an instantiated graph of
+// kernel nodes, built on first use and kept with the plan until
+// tri_plan_destroy.
+static tri_status life_graph(const tri_plan *p, const LifeArgs &a0, int steps,
+                             hipGraphExec_t &exec)
+{
+    const PlanGraphKey key{(const void *)a0.t.cur, (const void *)a0.t.nxt, a0.t.ld, steps};
+    std::lock_guard<std::mutex> lk(p->graphs->mu);
+    auto it = p->graphs->execs.find(key);
+    if (it != p->graphs->execs.end()) {
+        exec = it->second;
+        return TRI_OK;
+    }
+    const void *fn = nullptr;
+    int threads = 0;
+    if (!life_kernel(p, fn, threads)) return fail(TRI_E_UNSUPPORTED, "tri_launch_stencil: tile");
+    hipGraph_t g = nullptr;
+    TRI_HIP(hipGraphCreate(&g, 0));
+    hipGraphNode_t prev = nullptr;
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < steps && e == hipSuccess; ++k) {
+        LifeArgs a = a0;
+        a.t.cur = (k & 1) ? a0.t.nxt : a0.t.cur;
+        a.t.nxt = (k & 1) ? (uint8_t *)a0.t.cur : a0.t.nxt;
+        void *args[] = {&a};
+        hipKernelNodeParams np{};
+        np.func = (void *)fn;
+        np.gridDim = dim3(p->gx, p->gy);
+        np.blockDim = dim3(threads);
+        np.sharedMemBytes = 0;
+        np.kernelParams = args;
+        np.extra = nullptr;
+        hipGraphNode_t node;
+        e = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &np);
+        prev = node;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(e, "tri_launch_stencil: graph");
+    p->graphs->execs[key] = exec;
+    return TRI_OK;
 }
 
 }  // namespace trimap
@@ -160,13 +166,18 @@ extern "C" tri_status tri_launch_stencil(const tri_plan *p, uint8_t *cur, uint8_
     if (ld < p->n || ld % 4) return fail(TRI_E_INVAL, "tri_launch_stencil: ld must be >= n and a multiple of 4");
     if (((uintptr_t)cur | (uintptr_t)nxt) & 3)
         return fail(TRI_E_INVAL, "tri_launch_stencil: buffers must be 4-byte aligned");
-    if (use_graph) return fail(TRI_E_UNSUPPORTED, "tri_launch_stencil: graph replay not built yet");
-
     hipStream_t s = (hipStream_t)stream;
-    LifeArgs a{plan_tile_grid(p), (int32_t)p->n, ld, cur, nxt};
+    LifeArgs a{plan_tile_grid(p), LifeTile{(int32_t)p->n, ld, cur, nxt}};
+    if (use_graph) {
+        hipGraphExec_t exec = nullptr;
+        tri_status st = life_graph(p, a, steps, exec);
+        if (st != TRI_OK) return st;
+        TRI_HIP(hipGraphLaunch(exec, s));
+        return TRI_OK;
+    }
     for (int k = 0; k < steps; ++k) {
-        a.cur = (k & 1) ? nxt : cur;
-        a.nxt = (k & 1) ? cur : nxt;
+        a.t.cur = (k & 1) ? nxt : cur;
+        a.t.nxt = (k & 1) ? cur : nxt;
         if (!life_step(p, a, s)) return fail(TRI_E_UNSUPPORTED, "tri_launch_stencil: tile");
         TRI_HIP(hipGetLastError());
     }

@@ -22,6 +22,9 @@ MAP_NAMES = {v: k for k, v in MAPS.items()}
 FLAG_XCD_SWIZZLE, FLAG_SQRT_RSQ, FLAG_SQRT_F64 = 1, 2, 4
 OP_XORMUL_I32, OP_AXPYT_F32 = 0, 1
 EDM_FP32, EDM_BF16X3, EDM_BF16 = 0, 1, 2
+KIND_EDM, KIND_LIFE = 0, 1
+TUNE_ELEMENTWISE_F32, TUNE_ELEMENTWISE_I32, TUNE_LIFE, TUNE_EDM_FP32, TUNE_EDM_BF16X3 = range(5)
+BATCH_GRAPH, BATCH_STREAM, BATCH_PER_INSTANCE = 0, 1, 2
 
 OK, E_INVAL, E_RANGE, E_NOMEM, E_HIP, E_UNSUPPORTED = range(6)
 
@@ -38,6 +41,18 @@ class tri_plan_info(ctypes.Structure):
         "elements", "dump_entries")] + [
         ("map", ctypes.c_int32), ("include_diag", ctypes.c_int32),
         ("flags", ctypes.c_uint32), ("reserved", ctypes.c_int32)]
+
+
+class tri_batch_info(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int32) for name in (
+        "count", "life_instances", "edm_tile", "life_tile", "life_steps",
+        "persistent_workgroups")] + [
+        ("items_generation0", ctypes.c_int64), ("items_per_later_generation", ctypes.c_int64)]
+
+
+class tri_tune_choice(ctypes.Structure):
+    _fields_ = [("tile", ctypes.c_int32), ("map", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("ms", ctypes.c_float)]
 
 
 def _load() -> ctypes.CDLL:
@@ -69,6 +84,26 @@ def _load() -> ctypes.CDLL:
     L.tri_edm_workspace_size.argtypes = [vp, i64, i32, ctypes.POINTER(ctypes.c_size_t)]
     L.tri_edm.restype = st
     L.tri_edm.argtypes = [vp, vp, i64, i64, vp, i32, ctypes.c_float, vp, ctypes.c_size_t, vp]
+    L.tri_batch_plan.restype = st
+    L.tri_batch_plan.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, vp, vp, vp, i32, i32, i32]
+    L.tri_batch_bind.restype = st
+    L.tri_batch_bind.argtypes = [vp, vp, vp, vp]
+    L.tri_batch_launch.restype = st
+    L.tri_batch_launch.argtypes = [vp, i32, vp]
+    L.tri_batch_query.restype = st
+    L.tri_batch_query.argtypes = [vp, ctypes.POINTER(tri_batch_info)]
+    L.tri_batch_destroy.restype = st
+    L.tri_batch_destroy.argtypes = [vp]
+    L.tri_autotune.restype = st
+    L.tri_autotune.argtypes = [i32, i64, i64, i32, i32, vp, ctypes.POINTER(tri_tune_choice),
+                               ctypes.POINTER(tri_tune_choice), ctypes.c_int32,
+                               ctypes.POINTER(ctypes.c_int32)]
+    L.tri_tune_cache_save.restype = st
+    L.tri_tune_cache_save.argtypes = [ctypes.c_char_p]
+    L.tri_tune_cache_load.restype = st
+    L.tri_tune_cache_load.argtypes = [ctypes.c_char_p]
+    L.tri_tune_cache_clear.restype = st
+    L.tri_tune_cache_clear.argtypes = []
     L.tri_status_str.restype = ctypes.c_char_p
     L.tri_status_str.argtypes = [st]
     L.tri_last_error.restype = ctypes.c_char_p
@@ -195,3 +230,80 @@ def lambda_eval(omega, include_diag: bool = True, flags: int = 0, stream=None):
     _check(lib.tri_lambda_eval(_dptr(omega), int(omega.numel()), 1 if include_diag else 0,
                                int(flags), _dptr(out), _stream(stream)))
     return out
+
+
+class Batch:
+    """Uneven triangular domains in one persistent launch per generation
+    (tri_batch_plan / tri_batch_bind / tri_batch_launch).
+
+    kinds: KIND_EDM or KIND_LIFE per instance; ns: sides; ds: dimensions
+    (distance maps).  bind() takes per-instance device tensors: distance map
+    (x, out), Life (grid holding generation 0, the other grid)."""
+
+    def __init__(self, kinds, ns, ds, edm_tile: int = 32, life_tile: int = 32,
+                 life_steps: int = 20):
+        import numpy as np
+        self.kinds = np.ascontiguousarray(kinds, dtype=np.int32)
+        self.ns = np.ascontiguousarray(ns, dtype=np.int64)
+        self.ds = np.ascontiguousarray(ds, dtype=np.int64)
+        h = ctypes.c_void_p()
+        _check(lib.tri_batch_plan(ctypes.byref(h), int(self.kinds.size),
+                                  self.kinds.ctypes.data, self.ns.ctypes.data,
+                                  self.ds.ctypes.data, int(edm_tile), int(life_tile),
+                                  int(life_steps)))
+        self._h = h
+        info = tri_batch_info()
+        _check(lib.tri_batch_query(h, ctypes.byref(info)))
+        self.info = {f: getattr(info, f) for f, _ in tri_batch_info._fields_}
+        self._keep = None
+
+    def bind(self, a_list, b_list):
+        import numpy as np
+        n = self.kinds.size
+        assert len(a_list) == n and len(b_list) == n
+        A = (ctypes.c_void_p * n)(*[_dptr(t) for t in a_list])
+        B = (ctypes.c_void_p * n)(*[_dptr(t) for t in b_list])
+        ld = np.ascontiguousarray([t.stride(0) for t in a_list], dtype=np.int64)
+        _check(lib.tri_batch_bind(self._h, A, B, ld.ctypes.data))
+        self._keep = (list(a_list), list(b_list))  # the buffers must outlive the plan's use
+
+    def launch(self, how: int = BATCH_GRAPH, stream=None):
+        _check(lib.tri_batch_launch(self._h, int(how), _stream(stream)))
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            lib.tri_batch_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune(workload: int, n: int, d: int = 0, reps: int = 3, use_cache: bool = True,
+             stream=None):
+    """Time the tile/map candidates (tri_autotune); returns (best, all) with
+    each choice a dict(tile, map, flags, ms)."""
+    best = tri_tune_choice()
+    cap = 64
+    arr = (tri_tune_choice * cap)()
+    cnt = ctypes.c_int32()
+    _check(lib.tri_autotune(int(workload), int(n), int(d), int(reps), 1 if use_cache else 0,
+                            _stream(stream), ctypes.byref(best), arr, cap, ctypes.byref(cnt)))
+    conv = lambda c: {"tile": c.tile, "map": MAP_NAMES.get(c.map, c.map), "flags": c.flags,
+                      "ms": c.ms}
+    return conv(best), [conv(arr[k]) for k in range(cnt.value)]
+
+
+def tune_cache_save(path: str):
+    _check(lib.tri_tune_cache_save(path.encode()))
+
+
+def tune_cache_load(path: str):
+    _check(lib.tri_tune_cache_load(path.encode()))
+
+
+def tune_cache_clear():
+    _check(lib.tri_tune_cache_clear())

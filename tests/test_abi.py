@@ -75,3 +75,28 @@ def test_edm_argument_checks_on_host():
     with pytest.raises(tm.TrimapError) as ei:
         q.edm_workspace_size(0, tm.EDM_FP32)
     assert ei.value.status == tm.E_RANGE
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libtrimap.so not built")
+def test_tune_cache_file_round_trip(tmp_path):
+    """The tuning cache parser reads back exactly what its writer writes
+    (host-only: no GPU is needed to save or load)."""
+    from paper_1609_01490_amd import trimap as tm
+    src = tmp_path / "in.json"
+    src.write_text(
+        '{\n  "entries": [\n'
+        '    {"arch": "gfx950", "cus": 256, "workload": 0, "bucket": 15, "d": 0, '
+        '"tile": 64, "map": 1, "flags": 0, "ms": 1.15},\n'
+        '    {"arch": "gfx950", "cus": 256, "workload": 2, "bucket": 14, "d": 0, '
+        '"tile": 64, "map": 4, "flags": 1, "ms": 0.088}\n  ]\n}\n')
+    tm.tune_cache_clear()
+    tm.tune_cache_load(str(src))
+    out = tmp_path / "out.json"
+    tm.tune_cache_save(str(out))
+    txt = out.read_text()
+    assert txt.count('"arch": "gfx950"') == 2
+    assert '"bucket": 15' in txt and '"tile": 64, "map": 1' in txt
+    assert '"flags": 1, "ms": 0.088' in txt
+    tm.tune_cache_clear()
+    with pytest.raises(tm.TrimapError):
+        tm.tune_cache_load(str(tmp_path / "missing.json"))

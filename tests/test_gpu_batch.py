@@ -1,0 +1,131 @@
+"""GPU parity of the batched persistent queue: every instance of a batch
+equals the oracle (Life bit-exact; distance map within the FP32 bound), and
+the graph, stream and per-instance launch modes give identical bits."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import dev, host, note, padded_ld
+from paper_1609_01490_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+U = 2.0 ** -24
+
+
+def _tm():
+    from paper_1609_01490_amd import trimap
+    return trimap
+
+
+def _make(tm, spec, d, steps, edm_tile, life_tile, seed):
+    import torch
+    kinds, ns, ds, host_in, A, B = [], [], [], [], [], []
+    for k, (kind, n) in enumerate(spec):
+        if kind == "edm":
+            X, _ = inputs.points(n, d, dup_frac=0.0, seed=seed + k)
+            host_in.append(X)
+            A.append(dev(X))
+            B.append(torch.full((n * (n - 1) // 2,), -1.0, dtype=torch.float32, device="cuda"))
+            kinds.append(tm.KIND_EDM)
+        else:
+            ld = padded_ld(n)
+            g = inputs.life(n, 0.3, seed=seed + k, ld=ld)
+            host_in.append(g)
+            A.append(dev(g))
+            B.append(torch.zeros_like(A[-1]))
+            kinds.append(tm.KIND_LIFE)
+        ns.append(n)
+        ds.append(d)
+    b = tm.Batch(kinds, ns, ds, edm_tile=edm_tile, life_tile=life_tile, life_steps=steps)
+    b.bind(A, B)
+    return b, host_in, A, B
+
+
+def _results(spec, A, B, steps):
+    out = []
+    for (kind, n), a, b in zip(spec, A, B):
+        if kind == "edm":
+            out.append(host(b))
+        else:
+            out.append(host(a if steps % 2 == 0 else b)[:, :n])
+    return out
+
+
+def _check_oracle(spec, host_in, res, d, steps):
+    for (kind, n), x, r in zip(spec, host_in, res):
+        if kind == "edm":
+            if n < 2:
+                continue
+            e = oracle.edm_condensed(x)
+            nz = e > 0
+            rel = np.abs(r.astype(np.float64)[nz] - e[nz]) / e[nz]
+            assert rel.max() <= (d + 2) * U / 2 + U, (n, rel.max())
+        else:
+            exp = oracle.gol(x, n, steps)
+            low = np.tril(np.ones((n, n), dtype=bool))
+            assert (r[low] == exp[low]).all(), n
+
+
+@pytest.mark.parametrize("edm_tile,life_tile", [(16, 8), (32, 16), (32, 32), (64, 64)])
+def test_batch_matches_oracle_and_modes(edm_tile, life_tile):
+    tm = _tm()
+    rng = np.random.default_rng(edm_tile + life_tile)
+    spec = [("edm" if k % 2 == 0 else "life", int(n)) for k, n in
+            enumerate(rng.integers(2, 260, size=14))] + [("edm", 2), ("life", 1), ("life", 3)]
+    d, steps = 32, 5
+    outs = {}
+    for how in (tm.BATCH_GRAPH, tm.BATCH_STREAM, tm.BATCH_PER_INSTANCE):
+        note("batch", edm_tile, life_tile, how)
+        b, host_in, A, B = _make(tm, spec, d, steps, edm_tile, life_tile, seed=70)
+        b.launch(how)
+        outs[how] = _results(spec, A, B, steps)
+        if how == tm.BATCH_GRAPH:
+            _check_oracle(spec, host_in, outs[how], d, steps)
+    for how in (tm.BATCH_STREAM, tm.BATCH_PER_INSTANCE):
+        for x, y in zip(outs[tm.BATCH_GRAPH], outs[how]):
+            assert (x.view(np.uint8) == y.view(np.uint8)).all()
+
+
+def test_batch_graph_replays():
+    """The graph is replayed several times with eager work in between; every
+    replay must give the same (oracle-checked) result."""
+    import torch
+    tm = _tm()
+    spec = [("life", 100), ("edm", 90), ("life", 37), ("edm", 300), ("life", 250)]
+    d, steps = 16, 4  # even: a Life grid holds the result and is re-run from there
+    b, host_in, A, B = _make(tm, spec, d, steps, 32, 32, seed=90)
+    ref = None
+    state = [x.copy() for x in host_in]
+    for rep in range(3):
+        note("batch replay", rep)
+        b.launch(tm.BATCH_GRAPH)
+        torch.cuda.synchronize()
+        _ = torch.ones(1000, device="cuda").sum().item()  # eager work between replays
+        res = _results(spec, A, B, steps)
+        # Life continues from where it stopped, distance maps are recomputed
+        for k, (kind, n) in enumerate(spec):
+            if kind == "life":
+                state[k] = np.pad(oracle.gol(state[k], n, steps), ((0, 0), (0, state[k].shape[1] - n)))
+        for (kind, n), x, s, r in zip(spec, host_in, state, res):
+            if kind == "life":
+                low = np.tril(np.ones((n, n), dtype=bool))
+                assert (r[low] == s[:, :n][low]).all(), (rep, n)
+        if ref is None:
+            ref = [r for r, (kind, _) in zip(res, spec) if kind == "edm"]
+        else:
+            for x, y in zip(ref, [r for r, (kind, _) in zip(res, spec) if kind == "edm"]):
+                assert (x == y).all()
+
+
+def test_batch_plan_errors():
+    tm = _tm()
+    with pytest.raises(tm.TrimapError):
+        tm.Batch([0, 1], [10, 10], [4, 4], edm_tile=8)
+    with pytest.raises(tm.TrimapError):
+        tm.Batch([0, 5], [10, 10], [4, 4])
+    with pytest.raises(tm.TrimapError):
+        tm.Batch([0], [10], [0])
+    b = tm.Batch([0, 1], [10, 10], [4, 4])
+    with pytest.raises(tm.TrimapError):
+        b.launch(tm.BATCH_GRAPH)   # not bound

@@ -135,3 +135,29 @@ def test_life_full_size_windows(map_name, tile):
         assert not got[~dom].any(), (r, c)
     del cur, nxt
     torch.cuda.empty_cache()
+
+
+def test_life_graph_mode_matches_eager_and_replays():
+    """use_graph builds the generations into a hipGraph once per (buffers,
+    steps) and replays it; every replay, with eager work in between, equals
+    the eager launches and the oracle."""
+    import torch
+    tm = _tm()
+    n, steps = 200, 6
+    ld = padded_ld(n)
+    g = inputs.life(n, 0.3, seed=5, ld=ld)
+    p = tm.Plan(n, 32, "lambda")
+    eager = _run(tm, p, g, steps)
+    cur, nxt = dev(g), torch.zeros((n, ld), dtype=torch.uint8, device="cuda")
+    state = g.copy()
+    low = np.tril(np.ones((n, n), dtype=bool))
+    for rep in range(3):
+        note("life graph replay", rep)
+        p.stencil(cur, nxt, steps, ld=ld, use_graph=True)   # even steps: result in cur
+        torch.cuda.synchronize()
+        _ = torch.ones(100, device="cuda").sum().item()
+        got = host(cur)[:, :n]
+        state = np.pad(oracle.gol(state, n, steps), ((0, 0), (0, ld - n)))
+        assert (got[low] == state[:, :n][low]).all(), rep
+        if rep == 0:
+            assert (got[low] == eager[:, :n][low]).all()

@@ -10,7 +10,7 @@ The same line carries, under "extra", the other workloads measured on the
 same run: lambda vs bounding box at n = 2048 (int32), the triangular Game of
 Life (n = 16384, 100 steps), and the distance map (n = 65536, d = 128).
 
-    python bench.py [--steps K] [--warmup W] [--tile 32] [--map lambda]
+    python bench.py [--steps K] [--warmup W] [--tile 0=autotuned] [--map lambda]
                     [--no-extra] [--no-cpu] [--gpus 1]
 """
 from __future__ import annotations
@@ -107,6 +107,18 @@ def cpu_baseline_elementwise(a, X, Y, budget_s=12.0):
                       f"elementwise workload, {dt:.1f} s"}
 
 
+def tune_table(tm, workload, n, d=0, reps=3):
+    """Every tile x map candidate timed by the library's autotuner."""
+    tm.tune_cache_clear()
+    best, allc = tm.autotune(workload, n, d, reps=reps, use_cache=False)
+    return best, allc
+
+
+def best_of(table, map_name):
+    c = [x for x in table if x["map"] == map_name]
+    return min(c, key=lambda x: x["ms"]) if c else None
+
+
 def bench_elementwise(tm, torch, args, timer):
     from paper_1609_01490_amd import inputs
     n = 32768
@@ -116,52 +128,82 @@ def bench_elementwise(tm, torch, args, timer):
     yd = torch.from_numpy(Y).cuda()
     c = torch.empty((n, n), dtype=torch.float32, device="cuda")
     E = n * (n + 1) // 2
+    # tile and swizzle of each map from the autotuner (all maps x tiles timed)
+    _, table = tune_table(tm, tm.TUNE_ELEMENTWISE_F32, n)
+    lam = best_of(table, args.map)
+    bb = best_of(table, "bb")
+    tile = args.tile or lam["tile"]
+    flags = args.flags if args.tile else lam["flags"]
     res = {}
-    for map_name in (args.map, "bb"):
-        p = tm.Plan(n, args.tile, map_name, flags=args.flags)
+    for map_name, t_, f_ in ((args.map, tile, flags), ("bb", args.tile or bb["tile"], 0)):
+        p = tm.Plan(n, t_, map_name, flags=f_)
         ms = timer.run(lambda: p.elementwise(tm.OP_AXPYT_F32, xd, yd, c, ld=n, a=float(a)),
                        args.steps, args.warmup)
-        res[map_name] = ms
-        log(f"elementwise {map_name} tile {args.tile}: {ms:.4f} ms")
+        res[map_name] = (ms, t_, f_)
+        log(f"elementwise {map_name} tile {t_} flags {f_}: {ms:.4f} ms")
     cpu = None if args.no_cpu else cpu_baseline_elementwise(a, X, Y)
     del xd, yd, c
     torch.cuda.empty_cache()
-    return n, E, res, cpu
+    return n, E, res, cpu, table
 
 
-def bench_int_elementwise(tm, torch, timer, tile=16):
+def bench_int_elementwise(tm, torch, timer, tile=16, launches=200):
+    """n = 2048 int32, lambda vs BB (and the other maps): GPU time per launch
+    from a captured graph of `launches` back-to-back launches (a single
+    launch is a few microseconds, below the host's launch rate)."""
     from paper_1609_01490_amd import inputs
     n = 2048
     A, B, C0 = inputs.int_elementwise(n)
     ad, bd, cd = (torch.from_numpy(v).cuda() for v in (A, B, C0))
     out = {}
-    for map_name in ("lambda", "bb", "rb", "rec", "utm"):
-        p = tm.Plan(n, tile, map_name)
-        ms = timer.run(lambda: p.elementwise(tm.OP_XORMUL_I32, ad, bd, cd, ld=n), 2000, 50)
-        out[map_name] = round(ms * 1e3, 3)
-    return {"n": n, "tile": tile, "us_per_launch": out,
-            "I_lambda_vs_bb": round(out["bb"] / out["lambda"], 4)}
+    for t_ in (8, 16, 32):
+        for map_name in ("lambda", "bb", "rb", "rec", "utm"):
+            if map_name == "utm" and t_ != tile:
+                continue
+            p = tm.Plan(n, t_, map_name)
+            fn = lambda: p.elementwise(tm.OP_XORMUL_I32, ad, bd, cd, ld=n)
+            fn()
+            torch.cuda.synchronize()
+            g = torch.cuda.CUDAGraph()
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                with torch.cuda.graph(g, stream=s):
+                    for _ in range(launches):
+                        fn()
+            torch.cuda.synchronize()
+            ms = timer.run(lambda: g.replay(), 5, 1) / launches
+            out[f"{map_name}/t{t_}"] = round(ms * 1e3, 3)
+            del g
+    return {"n": n, "tile": tile, "us_per_launch_graph": out,
+            "I_lambda_vs_bb": round(out[f"bb/t{tile}"] / out[f"lambda/t{tile}"], 4)}
 
 
-def bench_life(tm, torch, timer, tile=32, steps=100):
+def bench_life(tm, torch, timer, steps=100):
+    """Life n = 16384, 100 generations: lambda and BB each at the tile (and,
+    for lambda, swizzle) the autotuner finds fastest; the per-generation
+    table of every map x tile is reported too."""
     from paper_1609_01490_amd import inputs
     n = 16384
+    _, table = tune_table(tm, tm.TUNE_LIFE, n, reps=2)
     g = inputs.life(n, 0.3)
     cur = torch.from_numpy(g).cuda()
     nxt = torch.zeros_like(cur)
     out = {}
     for map_name in ("lambda", "bb"):
-        p = tm.Plan(n, tile, map_name)
+        ch = best_of(table, map_name)
+        p = tm.Plan(n, ch["tile"], map_name, flags=ch["flags"])
         ms = timer.run(lambda: p.stencil(cur, nxt, steps), 3, 1)
-        out[map_name] = ms
+        out[map_name] = {"ms": round(ms, 4), "tile": ch["tile"], "flags": ch["flags"]}
     cells = n * (n + 1) // 2
     del cur, nxt
     torch.cuda.empty_cache()
-    return {"n": n, "tile": tile, "steps": steps,
-            "ms_100_steps": {k: round(v, 4) for k, v in out.items()},
-            "cell_updates_per_s": round(cells * steps / (out["lambda"] * 1e-3), 1),
-            "GBps_algorithmic": round(2 * cells * steps / (out["lambda"] * 1e-3) / 1e9, 1),
-            "I_lambda_vs_bb": round(out["bb"] / out["lambda"], 4)}
+    lam = out["lambda"]["ms"]
+    return {"n": n, "steps": steps, "ms_100_steps": out,
+            "cell_updates_per_s": round(cells * steps / (lam * 1e-3), 1),
+            "GBps_algorithmic": round(2 * cells * steps / (lam * 1e-3) / 1e9, 1),
+            "I_lambda_vs_bb": round(out["bb"]["ms"] / lam, 4),
+            "per_generation_ms_by_map_tile": {f"{c['map']}/t{c['tile']}/f{c['flags']}":
+                                              round(c["ms"], 4) for c in table}}
 
 
 def bench_edm(tm, torch, timer):
@@ -190,13 +232,14 @@ def bench_edm(tm, torch, timer):
     return {"n": n, "d": d, **res}
 
 
-def bench_batch(tm, torch, timer, edm_tile=32, life_tile=32, steps=20, d=32):
+def bench_batch(tm, torch, timer, steps=20, d=32, tiles=None):
     """512 uneven instances (n log-uniform in [64, 8192]), even index distance
-    map (d = 32), odd index Life (20 generations): one hipGraph launch of the
-    persistent queue vs the same bodies launched per instance."""
+    map (d = 32), odd index Life (20 generations).  Tiles from the batch
+    autotuner (tri_batch_autotune) unless given; then one hipGraph launch of
+    the persistent queue vs the same bodies launched per instance."""
     from paper_1609_01490_amd import inputs
     spec = inputs.batch_instances()
-    kinds, ns, A, B = [], [], [], []
+    kinds, ns, A, B, init = [], [], [], [], []
     pairs = cells = 0
     for k, (kind, n) in enumerate(spec):
         if kind == "edm":
@@ -205,6 +248,7 @@ def bench_batch(tm, torch, timer, edm_tile=32, life_tile=32, steps=20, d=32):
             B.append(torch.empty((n * (n - 1) // 2,), dtype=torch.float32, device="cuda"))
             kinds.append(tm.KIND_EDM)
             pairs += n * (n - 1) // 2
+            init.append(None)
         else:
             ld = (n + 3) // 4 * 4
             g = inputs.life(n, 0.3, seed=inputs.seed_for(4) * 1000 + k, ld=ld)
@@ -212,16 +256,26 @@ def bench_batch(tm, torch, timer, edm_tile=32, life_tile=32, steps=20, d=32):
             B.append(torch.zeros_like(A[-1]))
             kinds.append(tm.KIND_LIFE)
             cells += n * (n + 1) // 2
+            init.append(g)
         ns.append(n)
-    b = tm.Batch(kinds, ns, [d] * len(ns), edm_tile=edm_tile, life_tile=life_tile,
-                 life_steps=steps)
+    ds = [d] * len(ns)
+    tune_ms = None
+    if tiles is None:
+        te, tl, tune_ms = tm.batch_autotune(kinds, ns, ds, steps, A, B, reps=1)
+        for a, g in zip(A, init):  # back to generation 0
+            if g is not None:
+                a.copy_(torch.from_numpy(g))
+    else:
+        te, tl = tiles
+    b = tm.Batch(kinds, ns, ds, edm_tile=te, life_tile=tl, life_steps=steps)
     b.bind(A, B)
     res = {}
     for how, name in ((tm.BATCH_GRAPH, "graph"), (tm.BATCH_STREAM, "stream"),
                       (tm.BATCH_PER_INSTANCE, "per_instance")):
         res[name] = round(timer.run(lambda: b.launch(how), 3, 1), 4)
     alg_bytes = 4 * pairs + 2 * cells * steps
-    out = {"instances": len(spec), "edm_tile": edm_tile, "life_tile": life_tile,
+    out = {"instances": len(spec), "edm_tile": te, "life_tile": tl, "tiles_from": (
+               "tri_batch_autotune" if tiles is None else "given"),
            "life_steps": steps, "d": d, "edm_pairs": pairs, "life_cells": cells,
            "launches_per_instance_mode": sum(1 if k == tm.KIND_EDM else steps for k in kinds),
            "ms": res, "speedup_graph_vs_per_instance": round(res["per_instance"] / res["graph"], 3),
@@ -249,7 +303,7 @@ def profile_target(tm, torch, args):
         a, X, Y, _ = inputs.f32_elementwise(n, with_fill=False)
         xd, yd = torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda()
         c = torch.empty((n, n), dtype=torch.float32, device="cuda")
-        p = tm.Plan(n, args.tile, args.map, flags=args.flags)
+        p = tm.Plan(n, args.tile or 64, args.map, flags=args.flags)
         for _ in range(reps):
             p.elementwise(tm.OP_AXPYT_F32, xd, yd, c, ld=n, a=float(a))
     elif t == "edm":
@@ -266,7 +320,7 @@ def profile_target(tm, torch, args):
         n = 16384
         cur = torch.from_numpy(inputs.life(n, 0.3)).cuda()
         nxt = torch.zeros_like(cur)
-        p = tm.Plan(n, args.tile, args.map, flags=args.flags)
+        p = tm.Plan(n, args.tile or 64, args.map, flags=args.flags)
         p.stencil(cur, nxt, reps)
     elif t == "int":
         n = 2048
@@ -284,7 +338,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--tile", type=int, default=32)
+    ap.add_argument("--tile", type=int, default=0, help="0: the autotuner's choice")
     ap.add_argument("--map", default="lambda")
     ap.add_argument("--flags", type=int, default=0)
     ap.add_argument("--no-extra", action="store_true")
@@ -308,15 +362,17 @@ def main():
         profile_target(tm, torch, args)
         return
 
-    n, E, res, cpu = bench_elementwise(tm, torch, args, timer)
-    ms = res[args.map]
+    n, E, res, cpu, table = bench_elementwise(tm, torch, args, timer)
+    ms, tile, flags = res[args.map]
     bytes_per_launch = 12 * E
     achieved = bytes_per_launch / (ms * 1e-3) / 1e9
     digest = src_digest("elementwise.hip", "maps.hpp")
-    traffic = traffic_from_profiles(f"axpyt_f32_n{n}_{args.map}_t{args.tile}", digest)
+    traffic = traffic_from_profiles(f"axpyt_f32_n{n}_{args.map}_t{tile}_f{flags}", digest)
 
-    extra = {"I_lambda_vs_bb_elementwise": round(res["bb"] / ms, 4),
-             "bb_ms": round(res["bb"], 4), "src_digest": digest}
+    extra = {"I_lambda_vs_bb_elementwise": round(res["bb"][0] / ms, 4),
+             "bb_ms": round(res["bb"][0], 4), "bb_tile": res["bb"][1], "src_digest": digest,
+             "elementwise_ms_by_map_tile": {f"{c['map']}/t{c['tile']}/f{c['flags']}":
+                                            round(c["ms"], 4) for c in table}}
     if not args.no_extra:
         for name, fn in (("int32_n2048", lambda: bench_int_elementwise(tm, torch, timer)),
                          ("life_n16384", lambda: bench_life(tm, torch, timer)),
@@ -344,8 +400,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"triangular elementwise C=a*X+Y^T, n={n} fp32 full storage, "
                                f"lower triangle incl. diagonal ({E} cells), map {args.map}, "
-                               f"tile {args.tile}x{args.tile}",
-                   "n": n, "tile": args.tile, "map": args.map},
+                               f"tile {tile}x{tile} (autotuned), flags {flags}",
+                   "n": n, "tile": tile, "map": args.map, "flags": flags},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
         "cpu_baseline": cpu,

@@ -206,7 +206,7 @@ typedef struct {
 /* Plan a batch from host arrays kind[count], n[count], d[count] (d ignored
  * for Life).  Needs the device that will run it to be current: it queries
  * the CU count and occupancy and allocates the plan's own device arrays
- * (prefix sums, instance descriptors, counters).  n_k < 2^20; at most 2^32
+ * (prefix sums, instance descriptors, counters).  n_k < 2^20; at most 2^31
  * tiles per generation. */
 tri_status tri_batch_plan(tri_batch **out, int32_t count, const int32_t *host_kind,
                           const int64_t *host_n, const int64_t *host_d, int edm_tile,
@@ -228,6 +228,18 @@ tri_status tri_batch_bind(tri_batch *b, void *const *host_a, void *const *host_b
 tri_status tri_batch_launch(tri_batch *b, int how, void *stream);
 tri_status tri_batch_query(const tri_batch *b, tri_batch_info *info);
 tri_status tri_batch_destroy(tri_batch *b);
+
+/* Autotune the tiles of a batch: plans, binds and times (one warm-up, then
+ * `reps` graph launches with HIP events on `stream`) every pair of
+ * edm_tile in {16, 32, 64} and life_tile in {8, 16, 32, 64} on the given
+ * instances and buffers (arguments as for tri_batch_plan and tri_batch_bind)
+ * and returns the fastest pair and its time per launch.  The buffers are
+ * used for real: distance-map outputs are rewritten and the Life grids
+ * advance by (reps + 1) * life_steps generations per candidate. */
+tri_status tri_batch_autotune(int32_t count, const int32_t *host_kind, const int64_t *host_n,
+                              const int64_t *host_d, int life_steps, void *const *host_a,
+                              void *const *host_b, const int64_t *host_ld, int reps, void *stream,
+                              int *best_edm_tile, int *best_life_tile, float *best_ms);
 
 /* ------------------------------------------------------------------------
  * Autotuner: tile size and map for a workload and problem size.

@@ -61,6 +61,12 @@ struct BatchLds {
     static constexpr int BYTES = EDM_BYTES > LIFE_BYTES ? EDM_BYTES : LIFE_BYTES;
 };
 
+// Items are taken kChunk at a time (one atomic per chunk) and the next
+// chunk is claimed as soon as the current one starts, so the atomic's
+// round trip overlaps the work.  Consecutive items usually belong to the
+// same instance: its range and descriptor are kept until an item leaves it.
+constexpr int kChunk = 4;
+
 template <int TE, int TL>
 __global__ void __launch_bounds__(kBatchThreads) k_batch_step(BatchStepArgs a)
 {
@@ -71,35 +77,48 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch_step(BatchStepArgs a)
     const bool in_lds = a.count + 1 <= kPrefixLds;
     if (in_lds)
         for (int k = threadIdx.x; k <= a.count; k += kBatchThreads) pfx[k] = a.prefix[k];
+    uint32_t next = 0;  // thread 0: first item of the chunk claimed ahead
+    if (threadIdx.x == 0) next = atomicAdd(a.head, (uint32_t)kChunk);
 
+    int64_t lo_g = 0, hi_g = 0;  // item range of the cached instance
+    BatchDesc D{};
     for (;;) {
         __syncthreads();  // the previous item is done with the LDS and with slot
-        if (threadIdx.x == 0) slot = (int64_t)atomicAdd(a.head, 1u);
-        __syncthreads();
-        const int64_t g = slot;
-        if (g >= a.total) return;  // uniform over the workgroup
-
-        // instance: the largest q with prefix[q] <= g
-        int lo = 0, hi = a.count;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            const int64_t pm = in_lds ? pfx[mid] : a.prefix[mid];
-            if (pm <= g) lo = mid;
-            else hi = mid;
+        if (threadIdx.x == 0) {
+            slot = (int64_t)next;
+            if ((int64_t)next < a.total) next = atomicAdd(a.head, (uint32_t)kChunk);
         }
-        const int64_t base = in_lds ? pfx[lo] : a.prefix[lo];
-        const int k = a.idx ? a.idx[lo] : lo;
-        const BatchDesc D = a.desc[k];
-        int32_t bi, bj;
-        lambda_tile((uint64_t)(g - base), 0u, bi, bj);
-        if (D.kind == TRI_KIND_EDM) {
-            const EdmTile t{D.n, D.d, D.ld, (const float *)D.a, (float *)D.b};
-            edm_f32_tile_body<TE>(t, bi, bj, (float *)body_lds);
-        } else {
-            const bool even = (a.step & 1) == 0;
-            const LifeTile t{D.n, D.ld, (const uint8_t *)(even ? D.a : D.b),
-                             (uint8_t *)(even ? D.b : D.a)};
-            life_tile_body<TL, kBatchThreads>(t, bi, bj, (uint32_t *)body_lds);
+        __syncthreads();
+        const int64_t g0 = slot;
+        if (g0 >= a.total) return;  // uniform over the workgroup
+        for (int c = 0; c < kChunk; ++c) {
+            const int64_t g = g0 + c;
+            if (g >= a.total) break;
+            if (g < lo_g || g >= hi_g) {
+                // instance: the largest q with prefix[q] <= g
+                int lo = 0, hi = a.count;
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    const int64_t pm = in_lds ? pfx[mid] : a.prefix[mid];
+                    if (pm <= g) lo = mid;
+                    else hi = mid;
+                }
+                lo_g = in_lds ? pfx[lo] : a.prefix[lo];
+                hi_g = in_lds ? pfx[lo + 1] : a.prefix[lo + 1];
+                D = a.desc[a.idx ? a.idx[lo] : lo];
+            }
+            if (c > 0) __syncthreads();  // LDS reuse between items of a chunk
+            int32_t bi, bj;
+            lambda_tile((uint64_t)(g - lo_g), 0u, bi, bj);
+            if (D.kind == TRI_KIND_EDM) {
+                const EdmTile t{D.n, D.d, D.ld, (const float *)D.a, (float *)D.b};
+                edm_f32_tile_body<TE>(t, bi, bj, (float *)body_lds);
+            } else {
+                const bool even = (a.step & 1) == 0;
+                const LifeTile t{D.n, D.ld, (const uint8_t *)(even ? D.a : D.b),
+                                 (uint8_t *)(even ? D.b : D.a)};
+                life_tile_body<TL, kBatchThreads>(t, bi, bj, (uint32_t *)body_lds);
+            }
         }
     }
 }
@@ -304,9 +323,9 @@ tri_status tri_batch_plan(tri_batch **out, int32_t count, const int32_t *host_ki
             b->idx1.push_back(k);
         }
     }
-    if (b->prefix0.back() >= (1ll << 32)) {
+    if (b->prefix0.back() >= (1ll << 31)) {
         batch_free(b);
-        return fail(TRI_E_RANGE, "tri_batch_plan: more than 2^32 tiles in one generation");
+        return fail(TRI_E_RANGE, "tri_batch_plan: more than 2^31 tiles in one generation");
     }
 
     hipError_t e = hipGetDevice(&b->device);
@@ -434,6 +453,58 @@ tri_status tri_batch_query(const tri_batch *b, tri_batch_info *info)
     info->persistent_workgroups = (int32_t)b->grid;
     info->items_generation0 = b->prefix0.back();
     info->items_per_later_generation = b->prefix1.back();
+    return TRI_OK;
+}
+
+tri_status tri_batch_autotune(int32_t count, const int32_t *host_kind, const int64_t *host_n,
+                              const int64_t *host_d, int life_steps, void *const *host_a,
+                              void *const *host_b, const int64_t *host_ld, int reps, void *stream,
+                              int *best_edm_tile, int *best_life_tile, float *best_ms)
+{
+    clear_error();
+    if (!best_edm_tile || !best_life_tile) return fail(TRI_E_INVAL, "tri_batch_autotune: NULL output");
+    if (reps < 1) reps = 1;
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    TRI_HIP(hipEventCreate(&e0));
+    hipError_t he = hipEventCreate(&e1);
+    if (he != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_fail(he, "tri_batch_autotune: event");
+    }
+    const int edm_tiles[] = {16, 32, 64}, life_tiles[] = {8, 16, 32, 64};
+    float best = -1.f;
+    tri_status st = TRI_OK;
+    for (int te : edm_tiles) {
+        for (int tl : life_tiles) {
+            tri_batch *b = nullptr;
+            st = tri_batch_plan(&b, count, host_kind, host_n, host_d, te, tl, life_steps);
+            if (st != TRI_OK) break;
+            st = tri_batch_bind(b, host_a, host_b, host_ld);
+            if (st == TRI_OK) st = tri_batch_launch(b, TRI_BATCH_GRAPH, stream);  // warm-up
+            if (st == TRI_OK) he = hipEventRecord(e0, s);
+            for (int r = 0; r < reps && st == TRI_OK && he == hipSuccess; ++r)
+                st = tri_batch_launch(b, TRI_BATCH_GRAPH, stream);
+            if (st == TRI_OK && he == hipSuccess) he = hipEventRecord(e1, s);
+            if (st == TRI_OK && he == hipSuccess) he = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (st == TRI_OK && he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+            tri_batch_destroy(b);
+            if (he != hipSuccess) st = hip_fail(he, "tri_batch_autotune: timing");
+            if (st != TRI_OK) break;
+            ms /= (float)reps;
+            if (best < 0.f || ms < best) {
+                best = ms;
+                *best_edm_tile = te;
+                *best_life_tile = tl;
+            }
+        }
+        if (st != TRI_OK) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != TRI_OK) return st;
+    if (best_ms) *best_ms = best;
     return TRI_OK;
 }
 

@@ -92,6 +92,10 @@ def _load() -> ctypes.CDLL:
     L.tri_batch_launch.argtypes = [vp, i32, vp]
     L.tri_batch_query.restype = st
     L.tri_batch_query.argtypes = [vp, ctypes.POINTER(tri_batch_info)]
+    L.tri_batch_autotune.restype = st
+    L.tri_batch_autotune.argtypes = [ctypes.c_int32, vp, vp, vp, i32, vp, vp, vp, i32, vp,
+                                     ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                     ctypes.POINTER(ctypes.c_float)]
     L.tri_batch_destroy.restype = st
     L.tri_batch_destroy.argtypes = [vp]
     L.tri_autotune.restype = st
@@ -307,3 +311,22 @@ def tune_cache_load(path: str):
 
 def tune_cache_clear():
     _check(lib.tri_tune_cache_clear())
+
+
+def batch_autotune(kinds, ns, ds, life_steps, a_list, b_list, reps: int = 2, stream=None):
+    """Fastest (edm_tile, life_tile, ms) for a batch (tri_batch_autotune).
+    Runs the batch on the given buffers (Life grids advance)."""
+    import numpy as np
+    kinds = np.ascontiguousarray(kinds, dtype=np.int32)
+    ns = np.ascontiguousarray(ns, dtype=np.int64)
+    ds = np.ascontiguousarray(ds, dtype=np.int64)
+    n = kinds.size
+    A = (ctypes.c_void_p * n)(*[_dptr(t) for t in a_list])
+    B = (ctypes.c_void_p * n)(*[_dptr(t) for t in b_list])
+    ld = np.ascontiguousarray([t.stride(0) for t in a_list], dtype=np.int64)
+    te, tl, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_float()
+    _check(lib.tri_batch_autotune(n, kinds.ctypes.data, ns.ctypes.data, ds.ctypes.data,
+                                  int(life_steps), A, B, ld.ctypes.data, int(reps),
+                                  _stream(stream), ctypes.byref(te), ctypes.byref(tl),
+                                  ctypes.byref(ms)))
+    return te.value, tl.value, ms.value

@@ -129,3 +129,31 @@ def test_batch_plan_errors():
     b = tm.Batch([0, 1], [10, 10], [4, 4])
     with pytest.raises(tm.TrimapError):
         b.launch(tm.BATCH_GRAPH)   # not bound
+
+
+def test_batch_autotune_choice_is_valid_and_exact():
+    tm = _tm()
+    spec = [("edm", 120), ("life", 200), ("edm", 33), ("life", 64), ("life", 9)]
+    d, steps = 16, 3
+    import torch
+    kinds, ns, ds, A, B = [], [], [], [], []
+    for k, (kind, n) in enumerate(spec):
+        if kind == "edm":
+            X, _ = inputs.points(n, d, dup_frac=0.0, seed=200 + k)
+            A.append(dev(X))
+            B.append(torch.empty((n * (n - 1) // 2,), dtype=torch.float32, device="cuda"))
+            kinds.append(tm.KIND_EDM)
+        else:
+            ld = padded_ld(n)
+            A.append(dev(inputs.life(n, 0.3, seed=200 + k, ld=ld)))
+            B.append(torch.zeros_like(A[-1]))
+            kinds.append(tm.KIND_LIFE)
+        ns.append(n)
+        ds.append(d)
+    note("batch autotune")
+    te, tl, ms = tm.batch_autotune(kinds, ns, ds, steps, A, B, reps=1)
+    assert te in (16, 32, 64) and tl in (8, 16, 32, 64) and ms > 0
+    # the chosen tiles give the oracle's results
+    b, host_in, A2, B2 = _make(tm, spec, d, steps, te, tl, seed=300)
+    b.launch(tm.BATCH_GRAPH)
+    _check_oracle(spec, host_in, _results(spec, A2, B2, steps), d, steps)

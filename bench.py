@@ -218,7 +218,10 @@ def bench_edm(tm, torch, timer):
     ms = timer.run(lambda: p.edm(xd, out, mode=tm.EDM_FP32), 3, 1)
     res["fp32_ms"] = round(ms, 4)
     res["fp32_pairs_per_s"] = round(pairs / (ms * 1e-3), 1)
-    q = tm.Plan(n, 128, "lambda", include_diag=False)
+    best, _ = tune_table(tm, tm.TUNE_EDM_BF16X3, n, d, reps=2)  # lambda with or without swizzle
+    q = tm.Plan(n, 128, best["map"], include_diag=False, flags=best["flags"])
+    res["mfma_map"] = best["map"]
+    res["mfma_flags"] = best["flags"]
     for mode, name in ((tm.EDM_BF16X3, "bf16x3"), (tm.EDM_BF16, "bf16")):
         ws = torch.empty(q.edm_workspace_size(d, mode), dtype=torch.uint8, device="cuda")
         ms = timer.run(lambda: q.edm(xd, out, mode=mode, fixup_thr=1e-2, ws=ws), 5, 2)

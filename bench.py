@@ -141,6 +141,12 @@ def bench_elementwise(tm, torch, args, timer):
                        args.steps, args.warmup)
         res[map_name] = (ms, t_, f_)
         log(f"elementwise {map_name} tile {t_} flags {f_}: {ms:.4f} ms")
+    # streaming ceiling: c = x + y over the same 3 x 4 GiB buffers
+    flat = [t.view(-1) for t in (c, xd, yd)]
+    ms_add = timer.run(lambda: tm.stream_add(*flat), args.steps, args.warmup)
+    res["stream_add_GBps"] = 12 * n * n / (ms_add * 1e-3) / 1e9
+    log(f"stream add (12 B per element over {n}x{n}): {ms_add:.4f} ms, "
+        f"{res['stream_add_GBps']:.0f} GB/s")
     cpu = None if args.no_cpu else cpu_baseline_elementwise(a, X, Y)
     del xd, yd, c
     torch.cuda.empty_cache()
@@ -372,7 +378,9 @@ def main():
     digest = src_digest("elementwise.hip", "maps.hpp")
     traffic = traffic_from_profiles(f"axpyt_f32_n{n}_{args.map}_t{tile}_f{flags}", digest)
 
-    extra = {"I_lambda_vs_bb_elementwise": round(res["bb"][0] / ms, 4),
+    extra = {"stream_add_ceiling_GBps": round(res["stream_add_GBps"], 1),
+             "frac_of_stream_add": round(achieved / res["stream_add_GBps"], 4),
+             "I_lambda_vs_bb_elementwise": round(res["bb"][0] / ms, 4),
              "bb_ms": round(res["bb"][0], 4), "bb_tile": res["bb"][1], "src_digest": digest,
              "elementwise_ms_by_map_tile": {f"{c['map']}/t{c['tile']}/f{c['flags']}":
                                             round(c["ms"], 4) for c in table}}

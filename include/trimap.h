@@ -54,7 +54,9 @@ typedef enum {
 enum {
     TRI_FLAG_XCD_SWIZZLE = 1u, /* lambda: give each XCD a contiguous range of omega   */
     TRI_FLAG_SQRT_RSQ = 2u,    /* lambda: sqrt(x) as x * rsq(x) (the paper's lambda_R) */
-    TRI_FLAG_SQRT_F64 = 4u     /* lambda: FP64 square root                             */
+    TRI_FLAG_SQRT_F64 = 4u,    /* lambda: FP64 square root                             */
+    TRI_FLAG_ORDER_REVERSE = 8u, /* lambda: dispatch omega from T-1 down to 0            */
+    TRI_FLAG_ORDER_PAIRS = 16u   /* lambda: alternate omega from the front and the back  */
 };
 
 /* Elementwise bodies. */
@@ -246,8 +248,9 @@ tri_status tri_batch_autotune(int32_t count, const int32_t *host_kind, const int
  *
  * tri_autotune times every candidate (tiles 8/16/32/64 — 16/32/64 for the
  * FP32 distance map, 128 for the MFMA one — times maps BB, RB, REC (when m is
- * a power of two), lambda and lambda with TRI_FLAG_XCD_SWIZZLE, plus UTM for
- * the elementwise bodies) on this GPU: one warm-up and `reps` timed calls
+ * a power of two) and lambda, the latter plain, with TRI_FLAG_XCD_SWIZZLE,
+ * TRI_FLAG_ORDER_REVERSE, TRI_FLAG_ORDER_PAIRS and swizzle + pairs, plus UTM
+ * for the elementwise bodies) on this GPU: one warm-up and `reps` timed calls
  * with HIP events on `stream`, on zeroed scratch buffers of the problem's
  * size that it allocates and frees itself (so it is not for graph capture).
  * Life is timed over two generations and reported per generation.  The
@@ -280,6 +283,13 @@ tri_status tri_autotune(int workload, int64_t n, int64_t d, int reps, int use_ca
 tri_status tri_tune_cache_save(const char *path);
 tri_status tri_tune_cache_load(const char *path);
 tri_status tri_tune_cache_clear(void);
+
+/* Measurement probe: c[k] = a[k] + b[k] for k < count (FP32, count a
+ * multiple of 4, 16-byte aligned device buffers), streamed with 16-byte
+ * non-temporal loads and stores by a grid-stride kernel: the bandwidth a
+ * plain kernel with the elementwise body's mix (two reads, one write)
+ * reaches on this GPU. */
+tri_status tri_stream_add(float *c, const float *a, const float *b, int64_t count, void *stream);
 
 /* Human-readable name of a status, and the last error message of the
  * calling thread ("" if none). */

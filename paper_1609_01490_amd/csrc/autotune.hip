@@ -93,7 +93,12 @@ static std::vector<Candidate> candidates(int workload, int64_t n)
     for (int t : tiles)
         for (int m : maps) {
             c.push_back({t, m, 0u});
-            if (m == TRI_MAP_LAMBDA) c.push_back({t, m, (uint32_t)TRI_FLAG_XCD_SWIZZLE});
+            if (m == TRI_MAP_LAMBDA) {
+                c.push_back({t, m, (uint32_t)TRI_FLAG_XCD_SWIZZLE});
+                c.push_back({t, m, (uint32_t)TRI_FLAG_ORDER_REVERSE});
+                c.push_back({t, m, (uint32_t)TRI_FLAG_ORDER_PAIRS});
+                c.push_back({t, m, (uint32_t)(TRI_FLAG_XCD_SWIZZLE | TRI_FLAG_ORDER_PAIRS)});
+            }
         }
     if (utm) c.push_back({32, TRI_MAP_UTM, 0u});
     (void)n;

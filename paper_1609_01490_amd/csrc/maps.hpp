@@ -69,6 +69,17 @@ __device__ __forceinline__ uint64_t xcd_swizzle(uint64_t L, uint64_t G)
     return x * q + (x < r ? x : r) + l;
 }
 
+// Order in which the workgroups of a lambda grid visit omega: a bijection
+// of [0, T) applied to the (possibly swizzled) block number L < T.  Reverse
+// starts with the longest tile rows; pairs alternates a block from the front
+// with one from the back, so short and long tile rows run together.
+__device__ __forceinline__ uint64_t dispatch_order(uint64_t L, uint64_t T, uint32_t flags)
+{
+    if (flags & TRI_FLAG_ORDER_REVERSE) return T - 1 - L;
+    if (flags & TRI_FLAG_ORDER_PAIRS) return (L & 1) ? T - 1 - (L >> 1) : (L >> 1);
+    return L;
+}
+
 enum { MAP_BB = TRI_MAP_BB, MAP_RB = TRI_MAP_RB, MAP_REC = TRI_MAP_REC,
        MAP_UTM = TRI_MAP_UTM, MAP_LAMBDA = TRI_MAP_LAMBDA };
 
@@ -115,7 +126,7 @@ __device__ __forceinline__ bool tile_of_block_raw(const TileGrid &g, int32_t &bi
         if (g.flags & TRI_FLAG_XCD_SWIZZLE)
             L = xcd_swizzle(L, (uint64_t)gridDim.x * gridDim.y);
         if (L >= g.T) return false;
-        lambda_tile(L, g.flags, bi, bj);
+        lambda_tile(dispatch_order(L, g.T, g.flags), g.flags, bi, bj);
         return true;
     }
 }

@@ -20,6 +20,7 @@ MAPS = {"bb": BB, "rb": RB, "rec": REC, "utm": UTM, "lambda": LAMBDA}
 MAP_NAMES = {v: k for k, v in MAPS.items()}
 
 FLAG_XCD_SWIZZLE, FLAG_SQRT_RSQ, FLAG_SQRT_F64 = 1, 2, 4
+FLAG_ORDER_REVERSE, FLAG_ORDER_PAIRS = 8, 16
 OP_XORMUL_I32, OP_AXPYT_F32 = 0, 1
 EDM_FP32, EDM_BF16X3, EDM_BF16 = 0, 1, 2
 KIND_EDM, KIND_LIFE = 0, 1
@@ -108,6 +109,8 @@ def _load() -> ctypes.CDLL:
     L.tri_tune_cache_load.argtypes = [ctypes.c_char_p]
     L.tri_tune_cache_clear.restype = st
     L.tri_tune_cache_clear.argtypes = []
+    L.tri_stream_add.restype = st
+    L.tri_stream_add.argtypes = [vp, vp, vp, i64, vp]
     L.tri_status_str.restype = ctypes.c_char_p
     L.tri_status_str.argtypes = [st]
     L.tri_last_error.restype = ctypes.c_char_p
@@ -330,3 +333,8 @@ def batch_autotune(kinds, ns, ds, life_steps, a_list, b_list, reps: int = 2, str
                                   _stream(stream), ctypes.byref(te), ctypes.byref(tl),
                                   ctypes.byref(ms)))
     return te.value, tl.value, ms.value
+
+
+def stream_add(c, a, b, stream=None):
+    """c = a + b with the library's streaming probe kernel (tri_stream_add)."""
+    _check(lib.tri_stream_add(_dptr(c), _dptr(a), _dptr(b), int(c.numel()), _stream(stream)))

@@ -138,3 +138,16 @@ def test_axpyt_full_size_sampled_rows(full_inputs, map_name, tile):
         assert bool((blk[upper] == float(fill)).all())
     del c
     torch.cuda.empty_cache()
+
+
+def test_stream_add_probe_is_exact():
+    import torch
+    tm = _tm()
+    a = torch.rand(1 << 20, device="cuda")
+    b = torch.rand(1 << 20, device="cuda")
+    c = torch.empty_like(a)
+    note("stream add")
+    tm.stream_add(c, a, b)
+    assert torch.equal(c, a + b)
+    with pytest.raises(tm.TrimapError):
+        tm.stream_add(c[:5], a[:5], b[:5])

@@ -39,6 +39,23 @@ def test_tile_map_dump_equals_oracle(map_name, tile):
             assert (got == exp).all(), (map_name, tile, n, diag)
 
 
+@pytest.mark.parametrize("flags", [8, 16, 17, 9])
+def test_lambda_dispatch_orders_are_permutations(flags):
+    tm = _tm()
+    for n in (1, 100, 257, 2048, 5000):
+        p = tm.Plan(n, 16, "lambda", flags=flags)
+        note("order dump", flags, n)
+        got = host(p.dump())
+        exp = oracle.map_dump(oracle.LAMBDA, p.info.m)
+        assert sorted(map(tuple, got.tolist())) == sorted(map(tuple, exp.tolist()))
+        if flags == 8:       # reverse
+            assert (got == exp[::-1]).all()
+        if flags == 16:      # front, back, front + 1, back - 1, ...
+            T = exp.shape[0]
+            order = [(L // 2) if L % 2 == 0 else T - 1 - L // 2 for L in range(T)]
+            assert (got == exp[order]).all()
+
+
 @pytest.mark.parametrize("tile", [16, 32])
 def test_lambda_xcd_swizzle_is_a_permutation(tile):
     tm = _tm()

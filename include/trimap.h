@@ -56,7 +56,8 @@ enum {
     TRI_FLAG_SQRT_RSQ = 2u,    /* lambda: sqrt(x) as x * rsq(x) (the paper's lambda_R) */
     TRI_FLAG_SQRT_F64 = 4u,    /* lambda: FP64 square root                             */
     TRI_FLAG_ORDER_REVERSE = 8u, /* lambda: dispatch omega from T-1 down to 0            */
-    TRI_FLAG_ORDER_PAIRS = 16u   /* lambda: alternate omega from the front and the back  */
+    TRI_FLAG_ORDER_PAIRS = 16u,  /* lambda: alternate omega from the front and the back  */
+    TRI_FLAG_LIFE_TEMPORAL = 32u /* stencil: up to 4 generations per launch (4-cell halo) */
 };
 
 /* Elementwise bodies. */
@@ -141,7 +142,10 @@ tri_status tri_launch_elementwise(const tri_plan *plan, int op, const void *x, c
  * Runs `steps` synchronous generations, reading cur and writing nxt, then
  * the other way round: the result is in cur when steps is even, in nxt when
  * odd.  Requires ld % 4 == 0, ld >= n, 4-byte aligned pointers, steps >= 0.
- * Each generation is one kernel launch; when use_graph is non-zero the
+ * With TRI_FLAG_LIFE_TEMPORAL in the plan (tiles 16, 32, 64; no graph) one
+ * launch advances up to four generations from a tile staged with a 4-cell
+ * halo, the number of launches keeping the parity of `steps`.  Otherwise
+ * each generation is one kernel launch; when use_graph is non-zero the
  * generations are built once into a hipGraph of kernel nodes for this
  * (cur, nxt, ld, steps), kept with the plan and replayed by every later call
  * with the same arguments (the graph is freed by tri_plan_destroy, which must
@@ -253,7 +257,8 @@ tri_status tri_batch_autotune(int32_t count, const int32_t *host_kind, const int
  * for the elementwise bodies) on this GPU: one warm-up and `reps` timed calls
  * with HIP events on `stream`, on zeroed scratch buffers of the problem's
  * size that it allocates and frees itself (so it is not for graph capture).
- * Life is timed over two generations and reported per generation.  The
+ * Life is timed over four generations (also with TRI_FLAG_LIFE_TEMPORAL
+ * for BB and lambda at tiles 16..64) and reported per generation.  The
  * fastest candidate goes to *best and into a process-wide cache keyed by GPU
  * architecture, CU count, workload, floor(log2 n) and d (distance maps); with
  * use_cache non-zero a cached entry is returned without timing.  When `all`

@@ -101,6 +101,12 @@ static std::vector<Candidate> candidates(int workload, int64_t n)
             }
         }
     if (utm) c.push_back({32, TRI_MAP_UTM, 0u});
+    if (workload == TRI_TUNE_LIFE)  // temporal blocking (tiles 16..64)
+        for (int t : {16, 32, 64}) {
+            c.push_back({t, TRI_MAP_BB, (uint32_t)TRI_FLAG_LIFE_TEMPORAL});
+            c.push_back({t, TRI_MAP_LAMBDA, (uint32_t)TRI_FLAG_LIFE_TEMPORAL});
+            c.push_back({t, TRI_MAP_LAMBDA, (uint32_t)(TRI_FLAG_LIFE_TEMPORAL | TRI_FLAG_XCD_SWIZZLE)});
+        }
     (void)n;
     return c;
 }
@@ -201,7 +207,7 @@ tri_status tri_autotune(int workload, int64_t n, int64_t d, int reps, int use_ca
             case TRI_TUNE_ELEMENTWISE_I32:
                 return tri_launch_elementwise(p, TRI_OP_XORMUL_I32, x, y, c, ld, 0.f, s);
             case TRI_TUNE_LIFE:
-                return tri_launch_stencil(p, (uint8_t *)x, (uint8_t *)y, ld, 2, 0, s);
+                return tri_launch_stencil(p, (uint8_t *)x, (uint8_t *)y, ld, 4, 0, s);
             case TRI_TUNE_EDM_FP32:
                 return tri_edm(p, (const float *)x, d, d, (float *)c, TRI_EDM_FP32, 1e-2f, nullptr, 0, s);
             default:
@@ -227,7 +233,7 @@ tri_status tri_autotune(int workload, int64_t n, int64_t d, int reps, int use_ca
         float ms = 0.f;
         (void)hipEventElapsedTime(&ms, e0, e1);
         ms /= (float)reps;
-        if (workload == TRI_TUNE_LIFE) ms *= 0.5f;  // per generation
+        if (workload == TRI_TUNE_LIFE) ms *= 0.25f;  // per generation
         const tri_tune_choice ch{cd.tile, cd.map, cd.flags, ms};
         if (all && nall < all_cap) all[nall] = ch;
         ++nall;

@@ -129,7 +129,8 @@ tri_status tri_map_plan(tri_plan **out, int64_t n, int tile, int map, int includ
     if (include_diag != 0 && include_diag != 1)
         return fail(TRI_E_INVAL, "tri_map_plan: include_diag = %d", include_diag);
     if (flags & ~(uint32_t)(TRI_FLAG_XCD_SWIZZLE | TRI_FLAG_SQRT_RSQ | TRI_FLAG_SQRT_F64 |
-                            TRI_FLAG_ORDER_REVERSE | TRI_FLAG_ORDER_PAIRS))
+                            TRI_FLAG_ORDER_REVERSE | TRI_FLAG_ORDER_PAIRS |
+                            TRI_FLAG_LIFE_TEMPORAL))
         return fail(TRI_E_INVAL, "tri_map_plan: unknown flags 0x%x", flags);
 
     tri_plan p{};

@@ -161,3 +161,43 @@ def test_life_graph_mode_matches_eager_and_replays():
         assert (got[low] == state[:, :n][low]).all(), rep
         if rep == 0:
             assert (got[low] == eager[:, :n][low]).all()
+
+
+@pytest.mark.parametrize("map_name", ["lambda", "bb", "rb"])
+@pytest.mark.parametrize("tile", [16, 32, 64])
+def test_life_temporal_blocking_bit_exact(map_name, tile):
+    """Up to four generations per launch from a tile staged with a 4-cell
+    halo: bit-exact against the oracle, upper triangle untouched, result in
+    the buffer the one-step path uses (parity of the step count)."""
+    tm = _tm()
+    for n in (1, 5, 33, 100, 257):
+        ld = padded_ld(n)
+        g = inputs.life(n, 0.3, seed=6000 + n, ld=ld)
+        p = tm.Plan(n, tile, map_name, flags=tm.FLAG_LIFE_TEMPORAL)
+        for steps in (1, 2, 3, 4, 5, 7, 12):
+            note("life temporal", map_name, tile, n, steps)
+            got = _run(tm, p, g, steps, garbage_seed=n * 31 + steps)
+            exp = oracle.gol(g, n, steps)
+            low = np.tril(np.ones((n, n), dtype=bool))
+            assert (got[:, :n][low] == exp[low]).all(), (map_name, tile, n, steps)
+
+
+@pytest.mark.slow
+def test_life_temporal_full_size_windows():
+    import torch
+    tm = _tm()
+    n, steps = 16384, 100
+    g = inputs.life(n, 0.3)
+    note("life temporal full", n, steps)
+    cur = dev(g)
+    nxt = torch.zeros_like(cur)
+    p = tm.Plan(n, 64, "lambda", flags=tm.FLAG_LIFE_TEMPORAL | tm.FLAG_XCD_SWIZZLE)
+    p.stencil(cur, nxt, steps)
+    torch.cuda.synchronize()
+    for (r, c) in [(8000, 7970), (n - 64, 5000), (9000, 0), (n - 64, n - 64), (64, 0)]:
+        win = oracle.gol(g, n, steps, r - steps, c - steps, 64 + 2 * steps, 64 + 2 * steps)
+        exp = win[steps:steps + 64, steps:steps + 64]
+        got = cur[r:r + 64, c:c + 64].cpu().numpy()
+        dom = np.arange(c, c + 64)[None, :] <= np.arange(r, r + 64)[:, None]
+        assert (got[dom] == exp[dom]).all(), (r, c)
+        assert not got[~dom].any(), (r, c)

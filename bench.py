@@ -270,20 +270,21 @@ def bench_batch(tm, torch, timer, steps=20, d=32, tiles=None):
     ds = [d] * len(ns)
     tune_ms = None
     if tiles is None:
-        te, tl, tune_ms = tm.batch_autotune(kinds, ns, ds, steps, A, B, reps=1)
+        te, tl, fl, tune_ms = tm.batch_autotune(kinds, ns, ds, steps, A, B, reps=1)
         for a, g in zip(A, init):  # back to generation 0
             if g is not None:
                 a.copy_(torch.from_numpy(g))
     else:
-        te, tl = tiles
-    b = tm.Batch(kinds, ns, ds, edm_tile=te, life_tile=tl, life_steps=steps)
+        te, tl, fl = tiles
+    b = tm.Batch(kinds, ns, ds, edm_tile=te, life_tile=tl, life_steps=steps, flags=fl)
     b.bind(A, B)
     res = {}
     for how, name in ((tm.BATCH_GRAPH, "graph"), (tm.BATCH_STREAM, "stream"),
                       (tm.BATCH_PER_INSTANCE, "per_instance")):
         res[name] = round(timer.run(lambda: b.launch(how), 3, 1), 4)
     alg_bytes = 4 * pairs + 2 * cells * steps
-    out = {"instances": len(spec), "edm_tile": te, "life_tile": tl, "tiles_from": (
+    out = {"instances": len(spec), "edm_tile": te, "life_tile": tl, "flags": fl,
+           "graph_nodes": b.info["graph_nodes"], "tiles_from": (
                "tri_batch_autotune" if tiles is None else "given"),
            "life_steps": steps, "d": d, "edm_pairs": pairs, "life_cells": cells,
            "launches_per_instance_mode": sum(1 if k == tm.KIND_EDM else steps for k in kinds),

@@ -205,18 +205,23 @@ typedef struct {
     int32_t life_tile;
     int32_t life_steps;
     int32_t persistent_workgroups;
+    int32_t graph_nodes;                 /* kernel nodes after the counter reset   */
+    int32_t reserved;
     int64_t items_generation0;          /* tiles in generation 0                  */
     int64_t items_per_later_generation; /* Life tiles in each later generation    */
 } tri_batch_info;
 
 /* Plan a batch from host arrays kind[count], n[count], d[count] (d ignored
- * for Life).  Needs the device that will run it to be current: it queries
- * the CU count and occupancy and allocates the plan's own device arrays
- * (prefix sums, instance descriptors, counters).  n_k < 2^20; at most 2^31
- * tiles per generation. */
+ * for Life).  flags: 0 or TRI_FLAG_LIFE_TEMPORAL (life_tile >= 16: each node
+ * advances the Life instances by up to four generations, as in
+ * tri_launch_stencil; the number of nodes keeps the parity of life_steps).
+ * Needs the device that will run it to be current: it queries the CU count
+ * and occupancy and allocates the plan's own device arrays (prefix sums,
+ * instance descriptors, counters).  n_k < 2^20; at most 2^31 tiles per
+ * generation. */
 tri_status tri_batch_plan(tri_batch **out, int32_t count, const int32_t *host_kind,
                           const int64_t *host_n, const int64_t *host_d, int edm_tile,
-                          int life_tile, int life_steps);
+                          int life_tile, int life_steps, uint32_t flags);
 
 /* Bind the instances' device buffers (host arrays of device pointers):
  * distance map k: a[k] = x (n_k x d_k FP32, leading dimension ld[k] >= d_k),
@@ -236,16 +241,19 @@ tri_status tri_batch_query(const tri_batch *b, tri_batch_info *info);
 tri_status tri_batch_destroy(tri_batch *b);
 
 /* Autotune the tiles of a batch: plans, binds and times (one warm-up, then
- * `reps` graph launches with HIP events on `stream`) every pair of
- * edm_tile in {16, 32, 64} and life_tile in {8, 16, 32, 64} on the given
- * instances and buffers (arguments as for tri_batch_plan and tri_batch_bind)
- * and returns the fastest pair and its time per launch.  The buffers are
- * used for real: distance-map outputs are rewritten and the Life grids
- * advance by (reps + 1) * life_steps generations per candidate. */
+ * `reps` graph launches with HIP events on `stream`) every edm_tile in
+ * {16, 32, 64} with every life_tile in {8, 16, 32, 64} (one generation per
+ * node) and in {16, 32, 64} with TRI_FLAG_LIFE_TEMPORAL, on the given
+ * instances and buffers (arguments as for tri_batch_plan and tri_batch_bind),
+ * and returns the fastest choice (best_flags may be NULL) and its time per
+ * launch.  The buffers are used for real: distance-map outputs are
+ * rewritten and the Life grids advance by (reps + 1) * life_steps
+ * generations per candidate. */
 tri_status tri_batch_autotune(int32_t count, const int32_t *host_kind, const int64_t *host_n,
                               const int64_t *host_d, int life_steps, void *const *host_a,
                               void *const *host_b, const int64_t *host_ld, int reps, void *stream,
-                              int *best_edm_tile, int *best_life_tile, float *best_ms);
+                              int *best_edm_tile, int *best_life_tile, uint32_t *best_flags,
+                              float *best_ms);
 
 /* ------------------------------------------------------------------------
  * Autotuner: tile size and map for a workload and problem size.

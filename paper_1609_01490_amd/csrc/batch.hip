@@ -30,6 +30,9 @@ namespace trimap {
 
 bool launch_edm_f32_lambda(int tile, const TileGrid &g, const EdmTile &t, hipStream_t s);
 bool launch_life_lambda(int tile, const TileGrid &g, const LifeTile &t, hipStream_t s);
+bool launch_life_multi_lambda(int tile, const TileGrid &g, const LifeTile &t, int gens,
+                              hipStream_t s);
+std::vector<int> life_multi_schedule(int steps);
 
 struct BatchDesc {
     int32_t kind;  // TRI_KIND_*
@@ -46,7 +49,8 @@ struct BatchStepArgs {
     const int64_t *prefix;  // count + 1 entries, prefix[0] = 0, prefix[count] = total
     const int32_t *idx;     // queue position -> instance (Life-only queues); null = identity
     int32_t count;
-    int32_t step;           // generation
+    int32_t step;           // node of the graph (Life buffers alternate per node)
+    int32_t gens;           // Life generations in this node (0: the one-step body)
     int64_t total;
     uint32_t *head;         // this generation's counter
 };
@@ -54,11 +58,16 @@ struct BatchStepArgs {
 constexpr int kBatchThreads = 256;
 constexpr int kPrefixLds = 1024;  // prefix entries kept in LDS (else searched in memory)
 
+template <int TL>
+constexpr int life_multi_bytes() { return TL >= 16 ? 2 * LifeMultiShape<(TL >= 16 ? TL : 16)>::WORDS * 4 : 0; }
+
 template <int TE, int TL>
 struct BatchLds {
     static constexpr int EDM_BYTES = EdmF32Shape<TE>::LDS_FLOATS * 4;
     static constexpr int LIFE_BYTES = LifeShape<TL, kBatchThreads>::LDS_WORDS * 4;
-    static constexpr int BYTES = EDM_BYTES > LIFE_BYTES ? EDM_BYTES : LIFE_BYTES;
+    static constexpr int MULTI_BYTES = life_multi_bytes<TL>();
+    static constexpr int B1 = EDM_BYTES > LIFE_BYTES ? EDM_BYTES : LIFE_BYTES;
+    static constexpr int BYTES = B1 > MULTI_BYTES ? B1 : MULTI_BYTES;
 };
 
 // Items are taken kChunk at a time (one atomic per chunk) and the next
@@ -117,7 +126,14 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch_step(BatchStepArgs a)
                 const bool even = (a.step & 1) == 0;
                 const LifeTile t{D.n, D.ld, (const uint8_t *)(even ? D.a : D.b),
                                  (uint8_t *)(even ? D.b : D.a)};
-                life_tile_body<TL, kBatchThreads>(t, bi, bj, (uint32_t *)body_lds);
+                bool done = false;
+                if constexpr (TL >= 16) {
+                    if (a.gens > 0) {
+                        life_multi_tile_body<TL>(t, bi, bj, a.gens, (uint32_t *)body_lds);
+                        done = true;
+                    }
+                }
+                if (!done) life_tile_body<TL, kBatchThreads>(t, bi, bj, (uint32_t *)body_lds);
             }
         }
     }
@@ -161,6 +177,8 @@ using namespace trimap;
 
 struct tri_batch {
     int32_t count = 0, edm_tile = 0, life_tile = 0, steps = 0;
+    bool temporal = false;
+    std::vector<int> sched;             // Life generations per node (temporal)
     std::vector<int32_t> kind;
     std::vector<int64_t> n, d, tiles;   // tiles: lambda blocks of each instance
     std::vector<int64_t> prefix0;       // every instance (generation 0)
@@ -193,11 +211,17 @@ static void batch_free(tri_batch *b)
     delete b;
 }
 
+static int batch_nodes(const tri_batch *b)
+{
+    return b->temporal ? std::max<int>(1, (int)b->sched.size()) : std::max(1, b->steps);
+}
+
 static BatchStepArgs step_args(const tri_batch *b, int s)
 {
     BatchStepArgs a{};
     a.desc = b->d_desc;
     a.step = s;
+    a.gens = (b->temporal && s < (int)b->sched.size()) ? b->sched[s] : 0;
     a.head = b->d_heads + s;
     if (s == 0) {
         a.prefix = b->d_prefix0;
@@ -216,7 +240,7 @@ static BatchStepArgs step_args(const tri_batch *b, int s)
 // the persistent launches: counter reset, then one kernel per generation
 static tri_status batch_enqueue(const tri_batch *b, hipStream_t s)
 {
-    const int S = std::max(1, b->steps);
+    const int S = batch_nodes(b);
     k_batch_reset<<<1, 256, 0, s>>>(b->d_heads, S);
     TRI_HIP(hipGetLastError());
     for (int k = 0; k < S; ++k) {
@@ -230,7 +254,7 @@ static tri_status batch_enqueue(const tri_batch *b, hipStream_t s)
 
 static tri_status batch_build_graph(tri_batch *b)
 {
-    const int S = std::max(1, b->steps);
+    const int S = batch_nodes(b);
     TRI_HIP(hipGraphCreate(&b->graph, 0));
     hipGraphNode_t prev = nullptr;
     {
@@ -269,7 +293,7 @@ extern "C" {
 
 tri_status tri_batch_plan(tri_batch **out, int32_t count, const int32_t *host_kind,
                           const int64_t *host_n, const int64_t *host_d, int edm_tile,
-                          int life_tile, int life_steps)
+                          int life_tile, int life_steps, uint32_t flags)
 {
     clear_error();
     if (!out) return fail(TRI_E_INVAL, "tri_batch_plan: out is NULL");
@@ -282,6 +306,10 @@ tri_status tri_batch_plan(tri_batch **out, int32_t count, const int32_t *host_ki
         return fail(TRI_E_INVAL, "tri_batch_plan: life_tile %d not in {8,16,32,64}", life_tile);
     if (life_steps < 0 || life_steps > 4096)
         return fail(TRI_E_INVAL, "tri_batch_plan: life_steps %d not in [0, 4096]", life_steps);
+    if (flags & ~(uint32_t)TRI_FLAG_LIFE_TEMPORAL)
+        return fail(TRI_E_INVAL, "tri_batch_plan: unknown flags 0x%x", flags);
+    if ((flags & TRI_FLAG_LIFE_TEMPORAL) && life_tile < 16)
+        return fail(TRI_E_UNSUPPORTED, "tri_batch_plan: temporal blocking needs life_tile >= 16");
 
     tri_batch *b = new (std::nothrow) tri_batch();
     if (!b) return fail(TRI_E_NOMEM, "tri_batch_plan: out of host memory");
@@ -289,6 +317,8 @@ tri_status tri_batch_plan(tri_batch **out, int32_t count, const int32_t *host_ki
     b->edm_tile = edm_tile;
     b->life_tile = life_tile;
     b->steps = life_steps;
+    b->temporal = (flags & TRI_FLAG_LIFE_TEMPORAL) != 0;
+    if (b->temporal && life_steps > 0) b->sched = life_multi_schedule(life_steps);
     b->kernel = step_kernel(edm_tile, life_tile);
     b->prefix0.push_back(0);
     b->prefix1.push_back(0);
@@ -341,7 +371,7 @@ tri_status tri_batch_plan(tri_batch **out, int32_t count, const int32_t *host_ki
     b->grid = (uint32_t)std::max(1, cus * std::max(1, per_cu));
 
     const size_t nl = b->idx1.size();
-    const int S = std::max(1, life_steps);
+    const int S = batch_nodes(b);
     e = hipMalloc(&b->d_desc, sizeof(BatchDesc) * count);
     if (e == hipSuccess) e = hipMalloc(&b->d_prefix0, sizeof(int64_t) * (count + 1));
     if (e == hipSuccess) e = hipMalloc(&b->d_prefix1, sizeof(int64_t) * (nl + 1));
@@ -426,11 +456,13 @@ tri_status tri_batch_launch(tri_batch *b, int how, void *stream)
                 launch_edm_f32_lambda(tile, g, t, s);
                 TRI_HIP(hipGetLastError());
             } else {
-                for (int st = 0; st < b->steps; ++st) {
+                const int nodes = b->temporal ? (int)b->sched.size() : b->steps;
+                for (int st = 0; st < nodes; ++st) {
                     const bool even = (st & 1) == 0;
                     const LifeTile t{D.n, D.ld, (const uint8_t *)(even ? D.a : D.b),
                                      (uint8_t *)(even ? D.b : D.a)};
-                    launch_life_lambda(tile, g, t, s);
+                    if (b->temporal) launch_life_multi_lambda(tile, g, t, b->sched[st], s);
+                    else launch_life_lambda(tile, g, t, s);
                     TRI_HIP(hipGetLastError());
                 }
             }
@@ -450,6 +482,7 @@ tri_status tri_batch_query(const tri_batch *b, tri_batch_info *info)
     info->edm_tile = b->edm_tile;
     info->life_tile = b->life_tile;
     info->life_steps = b->steps;
+    info->graph_nodes = batch_nodes(b);
     info->persistent_workgroups = (int32_t)b->grid;
     info->items_generation0 = b->prefix0.back();
     info->items_per_later_generation = b->prefix1.back();
@@ -459,7 +492,8 @@ tri_status tri_batch_query(const tri_batch *b, tri_batch_info *info)
 tri_status tri_batch_autotune(int32_t count, const int32_t *host_kind, const int64_t *host_n,
                               const int64_t *host_d, int life_steps, void *const *host_a,
                               void *const *host_b, const int64_t *host_ld, int reps, void *stream,
-                              int *best_edm_tile, int *best_life_tile, float *best_ms)
+                              int *best_edm_tile, int *best_life_tile, uint32_t *best_flags,
+                              float *best_ms)
 {
     clear_error();
     if (!best_edm_tile || !best_life_tile) return fail(TRI_E_INVAL, "tri_batch_autotune: NULL output");
@@ -476,9 +510,12 @@ tri_status tri_batch_autotune(int32_t count, const int32_t *host_kind, const int
     float best = -1.f;
     tri_status st = TRI_OK;
     for (int te : edm_tiles) {
-        for (int tl : life_tiles) {
+        for (int cand = 0; cand < 7; ++cand) {
+            // life tiles 8..64 one generation per node, then 16..64 temporal
+            const int tl = cand < 4 ? life_tiles[cand] : life_tiles[cand - 3];
+            const uint32_t fl = cand < 4 ? 0u : (uint32_t)TRI_FLAG_LIFE_TEMPORAL;
             tri_batch *b = nullptr;
-            st = tri_batch_plan(&b, count, host_kind, host_n, host_d, te, tl, life_steps);
+            st = tri_batch_plan(&b, count, host_kind, host_n, host_d, te, tl, life_steps, fl);
             if (st != TRI_OK) break;
             st = tri_batch_bind(b, host_a, host_b, host_ld);
             if (st == TRI_OK) st = tri_batch_launch(b, TRI_BATCH_GRAPH, stream);  // warm-up
@@ -497,6 +534,7 @@ tri_status tri_batch_autotune(int32_t count, const int32_t *host_kind, const int
                 best = ms;
                 *best_edm_tile = te;
                 *best_life_tile = tl;
+                if (best_flags) *best_flags = fl;
             }
         }
         if (st != TRI_OK) break;

@@ -52,111 +52,13 @@ static bool life_tile(const tri_plan *p, const LifeArgs &a, hipStream_t s)
     return false;
 }
 
-// ---------------------------------------------------------------------------
-// Temporal blocking (TRI_FLAG_LIFE_TEMPORAL): one launch advances up to
-// kLifeMaxGen generations.  The workgroup stages its tile with a halo of
-// kLifeMaxGen cells (rows) and one word (4 cells) on each side, runs the
-// generations in LDS, and writes only the tile: after g generations every
-// cell at least g cells inside the staged window is exact (the light cone of
-// a cell grows by one per generation), so the tile is exact after up to four.
-// Cells outside the domain are forced dead after every generation, as the
-// rule requires.  HBM traffic per generation falls from one read and one
-// write of the tile to (1 + halo) / g reads and 1 / g writes.
-// ---------------------------------------------------------------------------
-constexpr int kLifeMaxGen = 4;
-
-template <int TILE>
-struct LifeMultiShape {
-    static constexpr int NT = 256;
-    static constexpr int W = TILE / 4 + 2;        // words per staged row
-    static constexpr int R = TILE + 2 * kLifeMaxGen;  // staged rows
-    static constexpr int PW = W + 2;              // padded LDS row (zero border)
-    static constexpr int PR = R + 2;
-    static constexpr int STRIPS = NT / W;         // strips of rows per word column
-    static constexpr int SH = (R + STRIPS - 1) / STRIPS;
-    static constexpr int WORDS = PR * PW;
-};
-
-// domain mask of the staged word at row gi, column gj (4-aligned): bytes of
-// cells 0 <= gj + b <= gi < n
-__device__ __forceinline__ uint32_t life_window_mask(int32_t gi, int32_t gj, int32_t n)
-{
-    if (gi < 0 || gi >= n || gj < 0) return 0u;
-    return life_domain_mask(gi, gj);
-}
-
 template <int MAP, int TILE>
 __global__ void __launch_bounds__(256) k_life_multi(LifeArgs p, int gens)
 {
-    using S = LifeMultiShape<TILE>;
     int32_t bi, bj;
     if (!tile_of_block<MAP>(p.g, bi, bj)) return;
-    __shared__ uint32_t buf[2][S::WORDS];
-    const int32_t n = p.t.n;
-    const int64_t ld = p.t.ld;
-    const int32_t i0 = bi * TILE, j0 = bj * TILE;
-    const int K = kLifeMaxGen;
-
-    // stage rows i0-K .. i0+TILE+K-1, words at columns j0-4 .. j0+TILE, with
-    // a zero border around the window
-    for (int idx = threadIdx.x; idx < S::WORDS; idx += S::NT) {
-        const int pr = idx / S::PW, pw = idx % S::PW;
-        uint32_t v = 0;
-        if (pr >= 1 && pr <= S::R && pw >= 1 && pw <= S::W) {
-            const int32_t gi = i0 - K + (pr - 1);
-            const int32_t gj = j0 - 4 + 4 * (pw - 1);
-            const uint32_t m = life_window_mask(gi, gj, n);
-            if (m) v = *(const uint32_t *)(p.t.cur + (int64_t)gi * ld + gj) & m;
-        }
-        buf[0][idx] = v;
-        buf[1][idx] = 0;
-    }
-    __syncthreads();
-
-    const int w = threadIdx.x % S::W;      // word column of this thread
-    const int st = threadIdx.x / S::W;     // strip
-    const bool active = st < S::STRIPS;
-    const int r0 = st * S::SH;             // first staged row of the strip
-    const int32_t gj = j0 - 4 + 4 * w;
-    int cur = 0;
-    for (int g = 0; g < gens; ++g) {
-        const uint32_t *A = buf[cur];
-        uint32_t *B = buf[cur ^ 1];
-        if (active) {
-            auto L = [A](int r, int c) { return A[(r + 1) * S::PW + (c + 1)]; };
-            uint32_t hprev = life_hsum3(L(r0 - 1, w - 1), L(r0 - 1, w), L(r0 - 1, w + 1));
-            uint32_t hcur = life_hsum3(L(r0, w - 1), L(r0, w), L(r0, w + 1));
-            for (int k = 0; k < S::SH; ++k) {
-                const int r = r0 + k;
-                if (r >= S::R) break;
-                const uint32_t hnext = life_hsum3(L(r + 1, w - 1), L(r + 1, w), L(r + 1, w + 1));
-                const uint32_t self = L(r, w);
-                const uint32_t s9 = hprev + hcur + hnext;
-                uint32_t nv = life_zero_bytes(s9 ^ 0x03030303u) |
-                              (life_zero_bytes(s9 ^ 0x04040404u) & self);
-                nv &= life_window_mask(i0 - K + r, gj, n);  // dead outside the domain
-                B[(r + 1) * S::PW + (w + 1)] = nv;
-                hprev = hcur;
-                hcur = hnext;
-            }
-        }
-        __syncthreads();
-        cur ^= 1;
-    }
-
-    // the tile: staged rows K .. K+TILE-1, words 1 .. TILE/4
-    const uint32_t *A = buf[cur];
-    for (int idx = threadIdx.x; idx < TILE * (TILE / 4); idx += S::NT) {
-        const int tr = idx / (TILE / 4), tw = idx % (TILE / 4);
-        const int32_t gi = i0 + tr, gjw = j0 + 4 * tw;
-        const uint32_t v = A[(K + tr + 1) * S::PW + (tw + 1 + 1)];
-        if (gi < n && gjw + 3 <= gi) {
-            *(uint32_t *)(p.t.nxt + (int64_t)gi * ld + gjw) = v;
-        } else if (gi < n && gjw <= gi) {  // the word holding the diagonal cell
-            uint8_t *q = p.t.nxt + (int64_t)gi * ld + gjw;
-            for (int b = 0; b <= gi - gjw; ++b) q[b] = (uint8_t)(v >> (8 * b));
-        }
-    }
+    __shared__ uint32_t buf[2 * LifeMultiShape<TILE>::WORDS];
+    life_multi_tile_body<TILE>(p.t, bi, bj, gens, buf);
 }
 
 template <int MAP>
@@ -181,16 +83,31 @@ static bool life_multi_kernel(const tri_plan *p, const void *&fn)
     return false;
 }
 
-// Generations per launch for a run of `steps` generations, at most
-// kLifeMaxGen each, with a number of launches of the same parity as steps
-// (the result then lands in the buffer the one-step path would leave it in).
-static std::vector<int> life_multi_schedule(int steps)
+std::vector<int> life_multi_schedule(int steps)
 {
     int L = (steps + kLifeMaxGen - 1) / kLifeMaxGen;
     if ((L & 1) != (steps & 1)) ++L;
     std::vector<int> g(L, steps / L);
     for (int k = 0; k < steps % L; ++k) ++g[k];
     return g;
+}
+
+// One temporal-blocking launch of one domain under lambda (batched
+// per-instance mode); false for an unsupported tile.
+bool launch_life_multi_lambda(int tile, const TileGrid &g, const LifeTile &t, int gens,
+                              hipStream_t s)
+{
+    LifeArgs a{g, t};
+    uint32_t gx, gy;
+    if (g.T <= (1ull << 24)) { gx = (uint32_t)g.T; gy = 1; }
+    else { gx = 1u << 16; gy = (uint32_t)((g.T + gx - 1) / gx); }
+    const dim3 grid(gx, gy);
+    switch (tile) {
+    case 16: k_life_multi<MAP_LAMBDA, 16><<<grid, 256, 0, s>>>(a, gens); return true;
+    case 32: k_life_multi<MAP_LAMBDA, 32><<<grid, 256, 0, s>>>(a, gens); return true;
+    case 64: k_life_multi<MAP_LAMBDA, 64><<<grid, 256, 0, s>>>(a, gens); return true;
+    }
+    return false;
 }
 
 // kernel address and block size of the one-step kernel of a plan

@@ -47,7 +47,7 @@ class tri_plan_info(ctypes.Structure):
 class tri_batch_info(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int32) for name in (
         "count", "life_instances", "edm_tile", "life_tile", "life_steps",
-        "persistent_workgroups")] + [
+        "persistent_workgroups", "graph_nodes", "reserved")] + [
         ("items_generation0", ctypes.c_int64), ("items_per_later_generation", ctypes.c_int64)]
 
 
@@ -86,7 +86,7 @@ def _load() -> ctypes.CDLL:
     L.tri_edm.restype = st
     L.tri_edm.argtypes = [vp, vp, i64, i64, vp, i32, ctypes.c_float, vp, ctypes.c_size_t, vp]
     L.tri_batch_plan.restype = st
-    L.tri_batch_plan.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, vp, vp, vp, i32, i32, i32]
+    L.tri_batch_plan.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, vp, vp, vp, i32, i32, i32, u32]
     L.tri_batch_bind.restype = st
     L.tri_batch_bind.argtypes = [vp, vp, vp, vp]
     L.tri_batch_launch.restype = st
@@ -96,7 +96,7 @@ def _load() -> ctypes.CDLL:
     L.tri_batch_autotune.restype = st
     L.tri_batch_autotune.argtypes = [ctypes.c_int32, vp, vp, vp, i32, vp, vp, vp, i32, vp,
                                      ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
-                                     ctypes.POINTER(ctypes.c_float)]
+                                     ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_float)]
     L.tri_batch_destroy.restype = st
     L.tri_batch_destroy.argtypes = [vp]
     L.tri_autotune.restype = st
@@ -248,7 +248,7 @@ class Batch:
     (x, out), Life (grid holding generation 0, the other grid)."""
 
     def __init__(self, kinds, ns, ds, edm_tile: int = 32, life_tile: int = 32,
-                 life_steps: int = 20):
+                 life_steps: int = 20, flags: int = 0):
         import numpy as np
         self.kinds = np.ascontiguousarray(kinds, dtype=np.int32)
         self.ns = np.ascontiguousarray(ns, dtype=np.int64)
@@ -257,7 +257,7 @@ class Batch:
         _check(lib.tri_batch_plan(ctypes.byref(h), int(self.kinds.size),
                                   self.kinds.ctypes.data, self.ns.ctypes.data,
                                   self.ds.ctypes.data, int(edm_tile), int(life_tile),
-                                  int(life_steps)))
+                                  int(life_steps), int(flags)))
         self._h = h
         info = tri_batch_info()
         _check(lib.tri_batch_query(h, ctypes.byref(info)))
@@ -317,8 +317,9 @@ def tune_cache_clear():
 
 
 def batch_autotune(kinds, ns, ds, life_steps, a_list, b_list, reps: int = 2, stream=None):
-    """Fastest (edm_tile, life_tile, ms) for a batch (tri_batch_autotune).
-    Runs the batch on the given buffers (Life grids advance)."""
+    """Fastest (edm_tile, life_tile, flags, ms) for a batch
+    (tri_batch_autotune).  Runs the batch on the given buffers (Life grids
+    advance)."""
     import numpy as np
     kinds = np.ascontiguousarray(kinds, dtype=np.int32)
     ns = np.ascontiguousarray(ns, dtype=np.int64)
@@ -327,12 +328,12 @@ def batch_autotune(kinds, ns, ds, life_steps, a_list, b_list, reps: int = 2, str
     A = (ctypes.c_void_p * n)(*[_dptr(t) for t in a_list])
     B = (ctypes.c_void_p * n)(*[_dptr(t) for t in b_list])
     ld = np.ascontiguousarray([t.stride(0) for t in a_list], dtype=np.int64)
-    te, tl, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_float()
+    te, tl, fl, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_uint32(), ctypes.c_float()
     _check(lib.tri_batch_autotune(n, kinds.ctypes.data, ns.ctypes.data, ds.ctypes.data,
                                   int(life_steps), A, B, ld.ctypes.data, int(reps),
                                   _stream(stream), ctypes.byref(te), ctypes.byref(tl),
-                                  ctypes.byref(ms)))
-    return te.value, tl.value, ms.value
+                                  ctypes.byref(fl), ctypes.byref(ms)))
+    return te.value, tl.value, fl.value, ms.value
 
 
 def stream_add(c, a, b, stream=None):

@@ -18,7 +18,7 @@ def _tm():
     return trimap
 
 
-def _make(tm, spec, d, steps, edm_tile, life_tile, seed):
+def _make(tm, spec, d, steps, edm_tile, life_tile, seed, flags=0):
     import torch
     kinds, ns, ds, host_in, A, B = [], [], [], [], [], []
     for k, (kind, n) in enumerate(spec):
@@ -37,7 +37,8 @@ def _make(tm, spec, d, steps, edm_tile, life_tile, seed):
             kinds.append(tm.KIND_LIFE)
         ns.append(n)
         ds.append(d)
-    b = tm.Batch(kinds, ns, ds, edm_tile=edm_tile, life_tile=life_tile, life_steps=steps)
+    b = tm.Batch(kinds, ns, ds, edm_tile=edm_tile, life_tile=life_tile, life_steps=steps,
+                 flags=flags)
     b.bind(A, B)
     return b, host_in, A, B
 
@@ -67,8 +68,9 @@ def _check_oracle(spec, host_in, res, d, steps):
             assert (r[low] == exp[low]).all(), n
 
 
-@pytest.mark.parametrize("edm_tile,life_tile", [(16, 8), (32, 16), (32, 32), (64, 64)])
-def test_batch_matches_oracle_and_modes(edm_tile, life_tile):
+@pytest.mark.parametrize("edm_tile,life_tile,flags", [(16, 8, 0), (32, 16, 0), (32, 32, 0),
+                                                       (64, 64, 0), (32, 16, 32), (64, 64, 32)])
+def test_batch_matches_oracle_and_modes(edm_tile, life_tile, flags):
     tm = _tm()
     rng = np.random.default_rng(edm_tile + life_tile)
     spec = [("edm" if k % 2 == 0 else "life", int(n)) for k, n in
@@ -76,8 +78,8 @@ def test_batch_matches_oracle_and_modes(edm_tile, life_tile):
     d, steps = 32, 5
     outs = {}
     for how in (tm.BATCH_GRAPH, tm.BATCH_STREAM, tm.BATCH_PER_INSTANCE):
-        note("batch", edm_tile, life_tile, how)
-        b, host_in, A, B = _make(tm, spec, d, steps, edm_tile, life_tile, seed=70)
+        note("batch", edm_tile, life_tile, flags, how)
+        b, host_in, A, B = _make(tm, spec, d, steps, edm_tile, life_tile, seed=70, flags=flags)
         b.launch(how)
         outs[how] = _results(spec, A, B, steps)
         if how == tm.BATCH_GRAPH:
@@ -151,9 +153,9 @@ def test_batch_autotune_choice_is_valid_and_exact():
         ns.append(n)
         ds.append(d)
     note("batch autotune")
-    te, tl, ms = tm.batch_autotune(kinds, ns, ds, steps, A, B, reps=1)
-    assert te in (16, 32, 64) and tl in (8, 16, 32, 64) and ms > 0
+    te, tl, fl, ms = tm.batch_autotune(kinds, ns, ds, steps, A, B, reps=1)
+    assert te in (16, 32, 64) and tl in (8, 16, 32, 64) and fl in (0, 32) and ms > 0
     # the chosen tiles give the oracle's results
-    b, host_in, A2, B2 = _make(tm, spec, d, steps, te, tl, seed=300)
+    b, host_in, A2, B2 = _make(tm, spec, d, steps, te, tl, seed=300, flags=fl)
     b.launch(tm.BATCH_GRAPH)
     _check_oracle(spec, host_in, _results(spec, A2, B2, steps), d, steps)

@@ -241,6 +241,35 @@ def bench_edm(tm, torch, timer):
     return {"n": n, "d": d, **res}
 
 
+def bench_edm4(tm, torch, timer, n=32768):
+    """Four-feature distances (the global-memory distance test of Section
+    4.1) written to the n x n lower triangle: every map at tiles 16, 32, 64
+    (UTM has no tile), with the improvement factor I = t_BB / t_map at each
+    tile.  HBM-bound: 4 B written per cell; the points (16 B each) stay in
+    cache."""
+    from paper_1609_01490_amd import inputs
+    P = torch.from_numpy(inputs.points4(n)).cuda()
+    c = torch.empty((n, n), dtype=torch.float32, device="cuda")
+    E = n * (n + 1) // 2
+    ms = {}
+    for t_ in (16, 32, 64):
+        for map_name in ("bb", "rb", "rec", "lambda", "utm"):
+            if map_name == "utm" and t_ != 16:
+                continue
+            p = tm.Plan(n, t_, map_name)
+            key = "utm" if map_name == "utm" else f"{map_name}/t{t_}"
+            ms[key] = round(timer.run(lambda: p.elementwise(tm.OP_EDM4_F32, P, None, c, ld=n),
+                                      5, 2), 4)
+    del P, c
+    torch.cuda.empty_cache()
+    best = min(ms, key=ms.get)
+    I = {k: round(ms[f"bb/t{k.split('/t')[1]}"] / v, 4) for k, v in ms.items() if "/t" in k}
+    I["utm"] = round(min(v for k, v in ms.items() if k.startswith("bb/")) / ms["utm"], 4)
+    return {"n": n, "cells": E, "ms_by_map_tile": ms, "best": best,
+            "best_GBps_written": round(4 * E / (ms[best] * 1e-3) / 1e9, 1),
+            "I_vs_bb_same_tile": I}
+
+
 def bench_batch(tm, torch, timer, steps=20, d=32, tiles=None):
     """512 uneven instances (n log-uniform in [64, 8192]), even index distance
     map (d = 32), odd index Life (20 generations).  Tiles from the batch
@@ -389,6 +418,7 @@ def main():
         for name, fn in (("int32_n2048", lambda: bench_int_elementwise(tm, torch, timer)),
                          ("life_n16384", lambda: bench_life(tm, torch, timer)),
                          ("edm_n65536_d128", lambda: bench_edm(tm, torch, timer)),
+                         ("edm4_n32768", lambda: bench_edm4(tm, torch, timer)),
                          ("batch_512", lambda: bench_batch(tm, torch, timer))):
             log("extra", name)
             try:

@@ -67,7 +67,14 @@ enum {
     TRI_OP_XORMUL_I32 = 0,
     /* C[i][j] = fl(fl(a * X[i][j]) + Y[j][i]), two binary32 roundings, no
      * fused multiply-add; x = X, y = Y, c = C (float n x ld each). */
-    TRI_OP_AXPYT_F32 = 1
+    TRI_OP_AXPYT_F32 = 1,
+    /* Euclidean distance of four features, the global-memory distance test
+     * of Section 4.1: x = P (float[n][4], 16-byte aligned), y unused (may be
+     * NULL), c = C (float n x ld).  With p = P[i], q = P[j] and every step
+     * rounded to binary32 (no fused multiply-add):
+     * C[i][j] = sqrt(((dx*dx + dy*dy) + dz*dz) + dw*dw), d. = p. - q.,
+     * with a correctly rounded square root; C[i][i] = 0. */
+    TRI_OP_EDM4_F32 = 2
 };
 
 /* Distance-map arithmetic. */
@@ -128,7 +135,8 @@ tri_status tri_lambda_eval(const uint64_t *dev_omega, int64_t count, int include
 /* Apply an elementwise body to every cell of the plan's domain
  * (include_diag must be 1).  Cells j > i and rows >= n are never written.
  * Requirements: ld >= n; for TRI_OP_AXPYT_F32 x, y, c all n x ld with the
- * same ld; for TRI_OP_XORMUL_I32 x, y hold n uint32 and c is n x ld int32.
+ * same ld; for TRI_OP_XORMUL_I32 x, y hold n uint32 and c is n x ld int32;
+ * for TRI_OP_EDM4_F32 x holds n 16-byte-aligned points of four floats.
  * Rows are accessed 16 bytes at a time when ld % 4 == 0 and the matrix
  * pointers are 16-byte aligned, one element at a time otherwise.
  * `a` is used by TRI_OP_AXPYT_F32 only. */

@@ -62,6 +62,7 @@ def lib() -> ctypes.CDLL:
         L.orc_gol.restype = ctypes.c_int
         L.orc_gol.argtypes = [i64, vp, i64, i64, i64, i64, i64, ctypes.c_int, vp, i64]
         L.orc_edm_rows.argtypes = [i64, i64, vp, i64, vp, i64, vp]
+        L.orc_edm4.argtypes = [i64, vp, i64, i64, vp, i64]
         L.orc_queue_locate.restype = ctypes.c_int
         L.orc_queue_locate.argtypes = [i64, vp, i64, p64, p64]
         _lib = L
@@ -135,6 +136,21 @@ def c1(a: float, X: np.ndarray, Y: np.ndarray, out: np.ndarray, r0: int = 0,
     assert X.strides == Y.strides and X.strides[1] == 4 and out.strides[1] == 4
     lib().orc_c1(n, float(a), _ptr(X), _ptr(Y), X.strides[0] // 4, r0, r1, _ptr(out),
                  out.strides[0] // 4)
+    return out
+
+
+def edm4(P: np.ndarray, out: np.ndarray | None = None, r0: int = 0,
+         r1: int | None = None) -> np.ndarray:
+    """Four-feature binary32 distances |P_i - P_j| for rows r0..r1-1, j <= i
+    (cells j > i of out untouched; a new out starts at zero)."""
+    n = P.shape[0]
+    r1 = n if r1 is None else min(r1, n)
+    P = np.ascontiguousarray(P, dtype=np.float32)
+    assert P.shape == (n, 4)
+    if out is None:
+        out = np.zeros((r1 - r0, n), dtype=np.float32)
+    assert out.dtype == np.float32 and out.strides[1] == 4 and out.shape[0] >= r1 - r0
+    lib().orc_edm4(n, _ptr(P), r0, r1, _ptr(out), out.strides[0] // 4)
     return out
 
 

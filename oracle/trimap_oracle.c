@@ -379,6 +379,31 @@ void orc_edm_rows(int64_t n, int64_t d, const float *X, int64_t ldx, const int64
     }
 }
 
+/* Four-feature distance map, the global-memory test of Section 4.1: every
+ * point carries (x, y, z, w).  The paper gives the formula (Section 5, the
+ * EDM paragraph) without fixing a precision; here it is one binary32
+ * expression with a fixed order, so that any conforming evaluation is
+ * bit-identical: d. = p. - q. rounded, squares rounded, the sum
+ * ((dx^2 + dy^2) + dz^2) + dw^2 rounded left to right, then the correctly
+ * rounded sqrtf.  P is n x 4 (row-major, no padding).  Rows r0..r1-1 of the
+ * lower triangle with diagonal (j <= i) are written to out, leading
+ * dimension ldo; cells j > i of out are left as they are. */
+void orc_edm4(int64_t n, const float *P, int64_t r0, int64_t r1, float *out, int64_t ldo)
+{
+    for (int64_t i = r0; i < r1 && i < n; ++i)
+        for (int64_t j = 0; j <= i; ++j) {
+            float dx = P[4 * i + 0] - P[4 * j + 0];
+            float dy = P[4 * i + 1] - P[4 * j + 1];
+            float dz = P[4 * i + 2] - P[4 * j + 2];
+            float dw = P[4 * i + 3] - P[4 * j + 3];
+            float sx = dx * dx, sy = dy * dy, sz = dz * dz, sw = dw * dw;
+            float s = sx + sy;
+            s = s + sz;
+            s = s + sw;
+            out[(i - r0) * ldo + j] = sqrtf(s);
+        }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Batched work queue over per-instance lambda numberings                    */
 /* ------------------------------------------------------------------------ */

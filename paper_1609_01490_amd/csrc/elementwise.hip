@@ -6,9 +6,12 @@
 //    tile of Y is read row-major (coalesced) and transposed through LDS.
 //  * XORMUL_I32: C[i][j] = (A[i] xor B[j]) + i j (mod 2^32), the dummy
 //    kernel of Section 4.1 with a real per-cell store.
+//  * EDM4_F32: C[i][j] = |P_i - P_j| for four features per point, the
+//    global-memory distance test of Section 4.1: both points come straight
+//    from global memory (they stay in L1/L2), nothing is staged in LDS.
 //
-// Both are HBM-bound: 12 B (fp32) or 4 B (int32) of algorithmic traffic per
-// cell.  Rows move as 16-byte vectors; stores are non-temporal (the output
+// All are HBM-bound: 12 B (axpyt) or 4 B (xormul, edm4) of algorithmic
+// traffic per cell.  Rows move as 16-byte vectors; stores are non-temporal (the output
 // is not re-read).  UTM (thread space) has no tile and gets its own scalar
 // kernel, reading Y[j][i] straight from memory as the map implies.
 #include <type_traits>
@@ -177,6 +180,68 @@ __global__ void __launch_bounds__((ElemShape<TILE, VECTOR>::NT)) k_xormul(ElemAr
     }
 }
 
+// |P_i - P_j| with a fixed operation order: differences, squares, the sum
+// ((dx^2 + dy^2) + dz^2) + dw^2, each rounded to binary32, then a correctly
+// rounded square root.
+__device__ __forceinline__ float dist4(f4 a, f4 b)
+{
+    const float dx = __fsub_rn(a.x, b.x), dy = __fsub_rn(a.y, b.y);
+    const float dz = __fsub_rn(a.z, b.z), dw = __fsub_rn(a.w, b.w);
+    float s = __fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy));
+    s = __fadd_rn(s, __fmul_rn(dz, dz));
+    s = __fadd_rn(s, __fmul_rn(dw, dw));
+    return __fsqrt_rn(s);
+}
+
+template <int MAP, int TILE, bool VECTOR>
+__global__ void __launch_bounds__((ElemShape<TILE, VECTOR>::NT)) k_edm4(ElemArgs p)
+{
+    using S = ElemShape<TILE, VECTOR>;
+    int32_t bi, bj;
+    if (!tile_of_block<MAP>(p.g, bi, bj)) return;
+
+    const int tr = threadIdx.x / S::VPR;
+    const int tc = (threadIdx.x % S::VPR) * S::VEC;
+    const int32_t n = p.n;
+    const int64_t ld = p.ld;
+    const int32_t i0 = bi * TILE, j0 = bj * TILE;
+    const f4 *P = (const f4 *)p.x;
+    float *C = (float *)p.c;
+    const bool full = (bj < bi) && (i0 + TILE <= n);
+
+#pragma unroll
+    for (int ps = 0; ps < S::PASSES; ++ps) {
+        const int r = tr + ps * S::RPP;
+        const int32_t i = i0 + r, jc = j0 + tc;
+        if (!full && (i >= n || jc > i)) continue;
+        const f4 pi = P[i];
+        float *crow = C + (int64_t)i * ld + jc;
+        if constexpr (S::VEC == 4) {
+            // jc + 1 .. jc + 3 may lie past the diagonal (and past n - 1 on
+            // the last tile row): those lanes reuse P[jc] and are not stored
+            const f4 p0 = P[jc];
+            const bool all = full || jc + 3 <= i;
+            const f4 p1 = (all || jc + 1 <= i) ? P[jc + 1] : p0;
+            const f4 p2 = (all || jc + 2 <= i) ? P[jc + 2] : p0;
+            const f4 p3 = all ? P[jc + 3] : p0;
+            f4 o;
+            o.x = dist4(pi, p0);
+            o.y = dist4(pi, p1);
+            o.z = dist4(pi, p2);
+            o.w = dist4(pi, p3);
+            if (all) {
+                __builtin_nontemporal_store(o, (f4 *)crow);
+            } else {
+                crow[0] = o.x;
+                if (jc + 1 <= i) crow[1] = o.y;
+                if (jc + 2 <= i) crow[2] = o.z;
+            }
+        } else {
+            __builtin_nontemporal_store(dist4(pi, P[jc]), crow);
+        }
+    }
+}
+
 // UTM: thread k owns cell utm_cell(k); no tile, no LDS.
 template <int OP>
 __global__ void __launch_bounds__(kUtmThreads) k_elem_utm(ElemArgs p, int64_t elements)
@@ -192,6 +257,9 @@ __global__ void __launch_bounds__(kUtmThreads) k_elem_utm(ElemArgs p, int64_t el
         const float *Y = (const float *)p.y;
         ((float *)p.c)[(int64_t)i * ld + j] =
             __fadd_rn(__fmul_rn(p.a, X[(int64_t)i * ld + j]), Y[(int64_t)j * ld + i]);
+    } else if constexpr (OP == TRI_OP_EDM4_F32) {
+        const f4 *P = (const f4 *)p.x;
+        ((float *)p.c)[(int64_t)i * ld + j] = dist4(P[i], P[j]);
     } else {
         const uint32_t *A = (const uint32_t *)p.x;
         const uint32_t *B = (const uint32_t *)p.y;
@@ -207,6 +275,8 @@ static void launch_tile(const tri_plan *p, const ElemArgs &args, hipStream_t s)
     constexpr int NT = ElemShape<TILE, VECTOR>::NT;
     if constexpr (OP == TRI_OP_AXPYT_F32)
         k_axpyt<MAP, TILE, VECTOR><<<grid, NT, 0, s>>>(args);
+    else if constexpr (OP == TRI_OP_EDM4_F32)
+        k_edm4<MAP, TILE, VECTOR><<<grid, NT, 0, s>>>(args);
     else
         k_xormul<MAP, TILE, VECTOR><<<grid, NT, 0, s>>>(args);
 }
@@ -248,18 +318,21 @@ extern "C" tri_status tri_launch_elementwise(const tri_plan *p, int op, const vo
 {
     clear_error();
     if (!p) return fail(TRI_E_INVAL, "tri_launch_elementwise: plan is NULL");
-    if (op != TRI_OP_XORMUL_I32 && op != TRI_OP_AXPYT_F32)
+    if (op != TRI_OP_XORMUL_I32 && op != TRI_OP_AXPYT_F32 && op != TRI_OP_EDM4_F32)
         return fail(TRI_E_INVAL, "tri_launch_elementwise: op = %d", op);
     if (!p->diag)
         return fail(TRI_E_UNSUPPORTED, "tri_launch_elementwise: needs include_diag = 1");
     if (p->tile > 64)
         return fail(TRI_E_UNSUPPORTED, "tri_launch_elementwise: tile %d > 64", p->tile);
     if (p->n == 0) return TRI_OK;
-    if (!x || !y || !c) return fail(TRI_E_INVAL, "tri_launch_elementwise: NULL buffer");
+    if (!x || (!y && op != TRI_OP_EDM4_F32) || !c)
+        return fail(TRI_E_INVAL, "tri_launch_elementwise: NULL buffer");
     if (ld < p->n) return fail(TRI_E_INVAL, "tri_launch_elementwise: ld %lld < n %lld",
                                (long long)ld, (long long)p->n);
     const uintptr_t cx = (uintptr_t)c, xx = (uintptr_t)x, yx = (uintptr_t)y;
     if ((cx | xx | yx) & 3) return fail(TRI_E_INVAL, "tri_launch_elementwise: unaligned buffer");
+    if (op == TRI_OP_EDM4_F32 && (xx & 15))
+        return fail(TRI_E_INVAL, "tri_launch_elementwise: EDM4 points need 16-byte alignment");
     bool vector = (ld % 4 == 0) && ((cx & 15) == 0);
     if (op == TRI_OP_AXPYT_F32) vector = vector && ((xx & 15) == 0) && ((yx & 15) == 0);
 
@@ -269,6 +342,9 @@ extern "C" tri_status tri_launch_elementwise(const tri_plan *p, int op, const vo
     if (op == TRI_OP_AXPYT_F32)
         ok = vector ? dispatch_map<TRI_OP_AXPYT_F32, true>(p, args, s)
                     : dispatch_map<TRI_OP_AXPYT_F32, false>(p, args, s);
+    else if (op == TRI_OP_EDM4_F32)
+        ok = vector ? dispatch_map<TRI_OP_EDM4_F32, true>(p, args, s)
+                    : dispatch_map<TRI_OP_EDM4_F32, false>(p, args, s);
     else
         ok = vector ? dispatch_map<TRI_OP_XORMUL_I32, true>(p, args, s)
                     : dispatch_map<TRI_OP_XORMUL_I32, false>(p, args, s);

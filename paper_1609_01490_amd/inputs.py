@@ -12,6 +12,7 @@ Workloads (sizes of the defaults):
   * Game of Life:      n = 16384 uint8, lower triangle Bernoulli(0.3), upper 0.
   * distance map:      n = 65536 points in d = 128, uniform [0, 1), 1 % of the
                        rows replaced by near-duplicates (copy + U[-1e-4, 1e-4)).
+  * four-feature distances: n = 32768 points (x, y, z, w) uniform in [0, 1)^4.
   * batched:           512 instances, n log-uniform in [64, 8192]; even
                        instance index = distance map (d = 32), odd = Life
                        (density 0.3, 20 steps).
@@ -149,6 +150,14 @@ def points(n: int = 65536, d: int = 128, dup_frac: float = 0.01, jitter: float =
     jit = g.random((k, d), dtype=np.float32) * np.float32(2 * jitter) - np.float32(jitter)
     X[targets] = X[sources] + jit
     return X, np.stack([targets, sources], axis=1).astype(np.int64)
+
+
+def points4(n: int = 32768, seed: int | None = None) -> np.ndarray:
+    """P float32[n, 4]: points (x, y, z, w) uniform in the unit box [0, 1)^4
+    (the four-feature distance test)."""
+    seed = seed_for(5) if seed is None else seed
+    (sp,) = _streams(seed, 1)
+    return uniform_f32((n, 4), sp, 0.0, 1.0)
 
 
 def batch_instances(count: int = 512, n_lo: int = 64, n_hi: int = 8192,

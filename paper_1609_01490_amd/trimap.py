@@ -21,7 +21,7 @@ MAP_NAMES = {v: k for k, v in MAPS.items()}
 
 FLAG_XCD_SWIZZLE, FLAG_SQRT_RSQ, FLAG_SQRT_F64 = 1, 2, 4
 FLAG_ORDER_REVERSE, FLAG_ORDER_PAIRS, FLAG_LIFE_TEMPORAL = 8, 16, 32
-OP_XORMUL_I32, OP_AXPYT_F32 = 0, 1
+OP_XORMUL_I32, OP_AXPYT_F32, OP_EDM4_F32 = 0, 1, 2
 EDM_FP32, EDM_BF16X3, EDM_BF16 = 0, 1, 2
 KIND_EDM, KIND_LIFE = 0, 1
 TUNE_ELEMENTWISE_F32, TUNE_ELEMENTWISE_I32, TUNE_LIFE, TUNE_EDM_FP32, TUNE_EDM_BF16X3 = range(5)

@@ -270,6 +270,47 @@ def bench_edm4(tm, torch, timer, n=32768):
             "I_vs_bb_same_tile": I}
 
 
+# vector ALU issue rate: 256 CUs x 128 FP32 lanes per clock x 2.4 GHz (the
+# published 157.3 TFLOP/s FP32 vector peak counts a fused multiply-add as 2)
+VALU_LANE_OPS = 256 * 128 * 2.4e9
+
+
+def bench_collide(tm, torch, timer, n=131072):
+    """Sphere collision counts (the shared-memory test of Section 4.1), 1-D
+    and 3-D, every map at tiles 16, 32, 64, 128 (UTM: thread space), with the
+    improvement factor over BB at the same tile.  Vector-ALU-bound: 11 VALU
+    operations per pair test in 3-D, 5 in 1-D, against 256 CUs x 128 FP32
+    lanes x 2.4 GHz."""
+    from paper_1609_01490_amd import inputs
+    pairs = n * (n - 1) // 2
+    out = {"n": n, "pairs": pairs}
+    counts = torch.empty(n, dtype=torch.int32, device="cuda")
+    for dim, ops in ((3, 11), (1, 5)):
+        S = torch.from_numpy(inputs.spheres(n, dim)).cuda()
+        ms = {}
+        for t_ in (16, 32, 64, 128):
+            for map_name in ("bb", "rb", "rec", "lambda", "utm"):
+                if map_name == "utm" and t_ != 16:
+                    continue
+                p = tm.Plan(n, t_, map_name, include_diag=False)
+                key = "utm" if map_name == "utm" else f"{map_name}/t{t_}"
+                ms[key] = round(timer.run(lambda: p.collide(S, counts, dim=dim), 5, 2), 4)
+        best = min(ms, key=ms.get)
+        rate = pairs / (ms[best] * 1e-3)
+        peak = VALU_LANE_OPS / ops
+        I = {k: round(ms[f"bb/t{k.split('/t')[1]}"] / v, 4) for k, v in ms.items() if "/t" in k}
+        I["utm"] = round(min(v for k, v in ms.items() if k.startswith("bb/")) / ms["utm"], 4)
+        out[f"dim{dim}"] = {"ms_by_map_tile": ms, "best": best, "pairs_per_s": round(rate, 1),
+                            "alu_bound_pairs_per_s": round(peak, 1),
+                            "frac_of_alu_bound": round(rate / peak, 4),
+                            "mean_overlaps_per_sphere": round(float(counts.float().mean()), 3),
+                            "I_vs_bb_same_tile": I}
+        del S
+    del counts
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_batch(tm, torch, timer, steps=20, d=32, tiles=None):
     """512 uneven instances (n log-uniform in [64, 8192]), even index distance
     map (d = 32), odd index Life (20 generations).  Tiles from the batch
@@ -419,6 +460,7 @@ def main():
                          ("life_n16384", lambda: bench_life(tm, torch, timer)),
                          ("edm_n65536_d128", lambda: bench_edm(tm, torch, timer)),
                          ("edm4_n32768", lambda: bench_edm4(tm, torch, timer)),
+                         ("collide_n131072", lambda: bench_collide(tm, torch, timer)),
                          ("batch_512", lambda: bench_batch(tm, torch, timer))):
             log("extra", name)
             try:

@@ -180,6 +180,20 @@ tri_status tri_edm_workspace_size(const tri_plan *plan, int64_t d, int mode, siz
 tri_status tri_edm(const tri_plan *plan, const float *x, int64_t d, int64_t ldx, float *out,
                    int mode, float fixup_thr, void *ws, size_t ws_bytes, void *stream);
 
+/* Collision detection of n spheres (the shared-memory test of Section 4.1).
+ * The plan covers the strict lower triangle (include_diag must be 0); any
+ * map, tile 8, 16, 32, 64 or 128 (tile maps stage both blocks of spheres in
+ * LDS; UTM reads them from global memory per pair).  spheres is n x 4 FP32
+ * rows (x, y, z, r), 16-byte aligned; dim is 3, or 1 (only x and r are
+ * read).  Spheres a and b overlap when, in binary32 without fused
+ * multiply-add, s < (r_a + r_b)^2 with s = dx^2 (+ dy^2) (+ dz^2) summed left
+ * to right (d. = a. - b.); touching spheres (equality) and NaN coordinates
+ * do not overlap.  counts (int32[n], device, 4-byte aligned) is cleared by
+ * the call and then receives, for every sphere, the number of other spheres
+ * it overlaps.  Stream-ordered, no host synchronisation, no allocation. */
+tri_status tri_collide(const tri_plan *plan, const float *spheres, int dim, int32_t *counts,
+                       void *stream);
+
 /* ------------------------------------------------------------------------
  * Batched uneven domains in one persistent launch per generation.
  *

@@ -63,6 +63,9 @@ def lib() -> ctypes.CDLL:
         L.orc_gol.argtypes = [i64, vp, i64, i64, i64, i64, i64, ctypes.c_int, vp, i64]
         L.orc_edm_rows.argtypes = [i64, i64, vp, i64, vp, i64, vp]
         L.orc_edm4.argtypes = [i64, vp, i64, i64, vp, i64]
+        L.orc_collide.argtypes = [i64, ctypes.c_int, vp, vp]
+        L.orc_collide_one.restype = ctypes.c_int32
+        L.orc_collide_one.argtypes = [i64, ctypes.c_int, vp, i64]
         L.orc_queue_locate.restype = ctypes.c_int
         L.orc_queue_locate.argtypes = [i64, vp, i64, p64, p64]
         _lib = L
@@ -152,6 +155,21 @@ def edm4(P: np.ndarray, out: np.ndarray | None = None, r0: int = 0,
     assert out.dtype == np.float32 and out.strides[1] == 4 and out.shape[0] >= r1 - r0
     lib().orc_edm4(n, _ptr(P), r0, r1, _ptr(out), out.strides[0] // 4)
     return out
+
+
+def collide(S: np.ndarray, dim: int) -> np.ndarray:
+    """Per-sphere overlap counts (int32[n]) for spheres S = (x, y, z, r)."""
+    S = np.ascontiguousarray(S, dtype=np.float32)
+    assert S.ndim == 2 and S.shape[1] == 4 and dim in (1, 3)
+    out = np.zeros(S.shape[0], dtype=np.int32)
+    lib().orc_collide(S.shape[0], dim, _ptr(S), _ptr(out))
+    return out
+
+
+def collide_one(S: np.ndarray, dim: int, k: int) -> int:
+    """Overlap count of sphere k alone."""
+    S = np.ascontiguousarray(S, dtype=np.float32)
+    return int(lib().orc_collide_one(S.shape[0], dim, _ptr(S), int(k)))
 
 
 def gol(grid: np.ndarray, n: int, steps: int, r0: int = 0, c0_: int = 0,

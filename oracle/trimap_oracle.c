@@ -405,6 +405,61 @@ void orc_edm4(int64_t n, const float *P, int64_t r0, int64_t r1, float *out, int
 }
 
 /* ------------------------------------------------------------------------ */
+/* Collision detection of spheres (Section 4.1, the shared-memory test)       */
+/* ------------------------------------------------------------------------ */
+
+/* Spheres k = 0..n-1 are rows (x, y, z, r) of S (n x 4).  In dim = 3 two
+ * spheres overlap when the squared distance of their centres is below the
+ * square of the sum of their radii; in dim = 1 only x is a coordinate.  The
+ * paper does not fix the arithmetic; here it is binary32 with a fixed order
+ * (differences, squares, sum left to right, r_a + r_b, its square) and a
+ * strict comparison, so that touching spheres do not count.  The test is
+ * symmetric in (a, b): a - b is exactly -(b - a). */
+static int orc_overlap(int dim, const float *a, const float *b)
+{
+    float dx = a[0] - b[0];
+    float s = dx * dx;
+    if (dim == 3) {
+        float dy = a[1] - b[1];
+        float dz = a[2] - b[2];
+        float sy = dy * dy, sz = dz * dz;
+        s = s + sy;
+        s = s + sz;
+    }
+    float rr = a[3] + b[3];
+    float t = rr * rr;
+    return s < t;
+}
+
+/* counts[k] = number of spheres other than k that overlap sphere k: every
+ * pair j < i of the strict lower triangle is tested once and counted for
+ * both spheres. */
+void orc_collide(int64_t n, int dim, const float *S, int32_t *counts)
+{
+    for (int64_t k = 0; k < n; ++k)
+        counts[k] = 0;
+    for (int64_t i = 1; i < n; ++i)
+        for (int64_t j = 0; j < i; ++j)
+            if (orc_overlap(dim, S + 4 * i, S + 4 * j)) {
+                counts[i]++;
+                counts[j]++;
+            }
+}
+
+/* The count of one sphere k alone (same pairs, same test). */
+int32_t orc_collide_one(int64_t n, int dim, const float *S, int64_t k)
+{
+    int32_t c = 0;
+    for (int64_t j = 0; j < n; ++j) {
+        if (j == k)
+            continue;
+        const int64_t hi = j > k ? j : k, lo = j > k ? k : j;
+        c += orc_overlap(dim, S + 4 * hi, S + 4 * lo);
+    }
+    return c;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Batched work queue over per-instance lambda numberings                    */
 /* ------------------------------------------------------------------------ */
 

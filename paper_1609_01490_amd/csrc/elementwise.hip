@@ -190,7 +190,7 @@ __device__ __forceinline__ float dist4(f4 a, f4 b)
     float s = __fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy));
     s = __fadd_rn(s, __fmul_rn(dz, dz));
     s = __fadd_rn(s, __fmul_rn(dw, dw));
-    return __fsqrt_rn(s);
+    return __builtin_sqrtf(s);
 }
 
 template <int MAP, int TILE, bool VECTOR>

@@ -13,6 +13,9 @@ Workloads (sizes of the defaults):
   * distance map:      n = 65536 points in d = 128, uniform [0, 1), 1 % of the
                        rows replaced by near-duplicates (copy + U[-1e-4, 1e-4)).
   * four-feature distances: n = 32768 points (x, y, z, w) uniform in [0, 1)^4.
+  * collision detection: n = 131072 spheres, centres uniform in the unit
+                       box (3-D, or 1-D on x), radii uniform in [0, r_max)
+                       with r_max set for about 4 overlaps per sphere.
   * batched:           512 instances, n log-uniform in [64, 8192]; even
                        instance index = distance map (d = 32), odd = Life
                        (density 0.3, 20 steps).
@@ -158,6 +161,30 @@ def points4(n: int = 32768, seed: int | None = None) -> np.ndarray:
     seed = seed_for(5) if seed is None else seed
     (sp,) = _streams(seed, 1)
     return uniform_f32((n, 4), sp, 0.0, 1.0)
+
+
+def spheres(n: int = 131072, dim: int = 3, mean_degree: float = 4.0,
+            seed: int | None = None) -> np.ndarray:
+    """S float32[n, 4] = (x, y, z, r): centres uniform in the unit box (in
+    dim = 1 only x is drawn, y = z = 0) and radii uniform in [0, r_max).
+    r_max sets the expected number of overlaps per sphere to about
+    mean_degree, away from the box walls: two radii uniform in [0, R) have
+    E[(r_a + r_b)^k] = R^k E[(u + v)^k], which is 1 for k = 1 and 3/2 for
+    k = 3, so the pair probability is 2 R in 1-D and (4/3) pi (3/2) R^3 =
+    2 pi R^3 in 3-D."""
+    assert dim in (1, 3)
+    seed = seed_for(6 if dim == 3 else 7) if seed is None else seed
+    sc, sr = _streams(seed, 2)
+    S = np.zeros((n, 4), dtype=np.float32)
+    pairs_per = max(n - 1, 1)
+    if dim == 3:
+        S[:, :3] = uniform_f32((n, 3), sc, 0.0, 1.0)
+        r_max = (mean_degree / (2.0 * np.pi * pairs_per)) ** (1.0 / 3.0)
+    else:
+        S[:, 0] = uniform_f32((n,), sc, 0.0, 1.0)
+        r_max = mean_degree / (2.0 * pairs_per)
+    S[:, 3] = uniform_f32((n,), sr, 0.0, float(r_max))
+    return S
 
 
 def batch_instances(count: int = 512, n_lo: int = 64, n_hi: int = 8192,

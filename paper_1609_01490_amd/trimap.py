@@ -85,6 +85,8 @@ def _load() -> ctypes.CDLL:
     L.tri_edm_workspace_size.argtypes = [vp, i64, i32, ctypes.POINTER(ctypes.c_size_t)]
     L.tri_edm.restype = st
     L.tri_edm.argtypes = [vp, vp, i64, i64, vp, i32, ctypes.c_float, vp, ctypes.c_size_t, vp]
+    L.tri_collide.restype = st
+    L.tri_collide.argtypes = [vp, vp, i32, vp, vp]
     L.tri_batch_plan.restype = st
     L.tri_batch_plan.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, vp, vp, vp, i32, i32, i32, u32]
     L.tri_batch_bind.restype = st
@@ -228,6 +230,12 @@ class Plan:
         wsb = 0 if ws is None else ws.numel() * ws.element_size()
         _check(lib.tri_edm(self._h, _dptr(x), int(d), int(x.stride(0)), _dptr(out), int(mode),
                            float(fixup_thr), _dptr(ws), int(wsb), _stream(stream)))
+
+    def collide(self, spheres, counts, dim: int = 3, stream=None):
+        """Per-sphere overlap counts (tri_collide); spheres is a float32
+        device tensor n x 4 (x, y, z, r), counts an int32 device tensor."""
+        _check(lib.tri_collide(self._h, _dptr(spheres), int(dim), _dptr(counts),
+                               _stream(stream)))
 
 
 def lambda_eval(omega, include_diag: bool = True, flags: int = 0, stream=None):

@@ -1,0 +1,88 @@
+"""GPU parity of sphere collision detection (tri_collide, the shared-memory
+test of Section 4.1) against the oracle: per-sphere overlap counts
+bit-exact, for every map and tile size, 1-D and 3-D, ragged sizes, exact
+ties on lattice spheres, and sampled spheres at the full size
+n = 131072."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import dev, host, note
+from paper_1609_01490_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+MAPS = ["bb", "rb", "rec", "utm", "lambda"]
+SIZES = [1, 2, 3, 17, 64, 100, 257, 300, 1000]
+
+
+def _tm():
+    from paper_1609_01490_amd import trimap
+    return trimap
+
+
+def _lattice(n, seed):
+    """Centres k / 64, radii m / 128: exact binary32 arithmetic with many
+    exact ties (touching spheres, which do not count)."""
+    rng = np.random.default_rng(seed)
+    S = np.zeros((n, 4), dtype=np.float32)
+    S[:, :3] = rng.integers(0, 64, (n, 3)) / 64.0
+    S[:, 3] = rng.integers(0, 16, n) / 128.0
+    return S
+
+
+@pytest.mark.parametrize("map_name", MAPS)
+@pytest.mark.parametrize("tile", [8, 16, 32, 64, 128])
+def test_collide_bit_exact(map_name, tile):
+    import torch
+    tm = _tm()
+    for n in SIZES:
+        m = -(-max(n - 1, 0) // tile)
+        if map_name == "rec" and m and (m & (m - 1)):
+            continue
+        p = tm.Plan(n, tile, map_name, include_diag=False)
+        for dim in (1, 3):
+            S = inputs.spheres(n, dim, mean_degree=6.0, seed=5000 + n + dim)
+            for case, arr in (("random", S), ("lattice", _lattice(n, n + dim))):
+                exp = oracle.collide(arr, dim)
+                note("collide", map_name, tile, n, dim, case)
+                counts = torch.full((n,), -7, dtype=torch.int32, device="cuda")
+                p.collide(dev(arr), counts, dim=dim)
+                got = host(counts)
+                assert (got == exp).all(), (map_name, tile, n, dim, case)
+
+
+def test_collide_errors():
+    import torch
+    tm = _tm()
+    S = torch.zeros((8, 4), device="cuda")
+    c = torch.zeros(8, dtype=torch.int32, device="cuda")
+    with pytest.raises(tm.TrimapError):
+        tm.Plan(8, 8, "lambda").collide(S, c)                      # needs the strict plan
+    with pytest.raises(tm.TrimapError):
+        tm.Plan(8, 8, "lambda", include_diag=False).collide(S, c, dim=2)
+    with pytest.raises(tm.TrimapError):
+        flat = torch.zeros(8 * 4 + 1, device="cuda")
+        tm.Plan(8, 8, "lambda", include_diag=False).collide(flat[1:], c)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("dim", [1, 3])
+@pytest.mark.parametrize("map_name,tile", [("lambda", 64), ("bb", 64), ("rb", 128), ("utm", 16)])
+def test_collide_full_size_sampled(dim, map_name, tile):
+    """n = 131072, about 4 overlaps per sphere: counts of sampled spheres
+    (ends, tile borders, random) from the oracle one by one, and the total
+    is even (every overlap is counted twice)."""
+    import torch
+    tm = _tm()
+    n = 131072
+    S = inputs.spheres(n, dim)
+    note("collide full", map_name, tile, dim, n)
+    counts = torch.zeros(n, dtype=torch.int32, device="cuda")
+    tm.Plan(n, tile, map_name, include_diag=False).collide(dev(S), counts, dim=dim)
+    got = host(counts)
+    assert got.sum() % 2 == 0 and 2.0 < got.mean() < 6.0
+    rng = np.random.default_rng(dim)
+    ks = sorted({0, 1, 63, 64, 65, n // 2, n - 2, n - 1, *rng.integers(0, n, 40).tolist()})
+    for k in ks:
+        assert got[k] == oracle.collide_one(S, dim, k), k

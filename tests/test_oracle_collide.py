@@ -1,0 +1,83 @@
+"""Pins of the oracle's sphere collision counts (the shared-memory test of
+Section 4.1): an exact integer brute force on lattice spheres (every
+binary32 step exact there, ties included), SciPy's binary64 distances away
+from ties, a 1-D chain with a closed-form answer, and the count of one
+sphere against the whole array."""
+import numpy as np
+import pytest
+from scipy.spatial.distance import pdist, squareform
+
+import oracle
+from paper_1609_01490_amd import inputs
+
+
+def _lattice(n, dim, seed):
+    """Centres k / 64 (k < 64), radii m / 128 (m < 16): differences, squares,
+    sums and (r_a + r_b)^2 are all exact in binary32, so the binary32 test is
+    the exact one: 4 sum (dk)^2 < (m_a + m_b)^2 in integers."""
+    rng = np.random.default_rng(seed)
+    K = rng.integers(0, 64 if dim == 3 else 2048, (n, 3))
+    if dim == 1:
+        K[:, 1:] = 0
+    M = rng.integers(0, 16 if dim == 3 else 200, n)
+    S = np.zeros((n, 4), dtype=np.float32)
+    S[:, :3] = K / (64.0 if dim == 3 else 2048.0)
+    S[:, 3] = M / (128.0 if dim == 3 else 4096.0)
+    return S, K.astype(np.int64), M.astype(np.int64)
+
+
+@pytest.mark.parametrize("dim", [1, 3])
+def test_collide_lattice_exact_integer_brute_force(dim):
+    n = 400
+    S, K, M = _lattice(n, dim, seed=dim)
+    got = oracle.collide(S, dim)
+    d2 = ((K[:, None, :] - K[None, :, :]) ** 2).sum(-1)
+    rr = (M[:, None] + M[None, :]) ** 2
+    hit = 4 * d2 < rr                  # both sides scaled by 128^2 (3-D) or 4096^2 (1-D)
+    np.fill_diagonal(hit, False)
+    exp = hit.sum(1).astype(np.int32)
+    assert (got == exp).all()
+    ties = (4 * d2 == rr)
+    np.fill_diagonal(ties, False)
+    assert ties.any()                  # touching spheres are present and do not count
+    assert got.sum() % 2 == 0 and got.sum() > 0
+
+
+@pytest.mark.parametrize("dim", [1, 3])
+def test_collide_matches_scipy_away_from_ties(dim):
+    n = 500
+    S = inputs.spheres(n, dim, mean_degree=6.0, seed=21)
+    got = oracle.collide(S, dim)
+    X = S[:, :3].astype(np.float64) if dim == 3 else S[:, :1].astype(np.float64)
+    d = squareform(pdist(X))
+    rr = S[:, 3].astype(np.float64)[:, None] + S[:, 3].astype(np.float64)[None, :]
+    near = np.abs(d - rr) <= 1e-5 * rr
+    np.fill_diagonal(near, False)
+    assert not near.any()              # no borderline pair in this seed
+    hit = d < rr
+    np.fill_diagonal(hit, False)
+    assert (got == hit.sum(1)).all()
+    assert got.mean() > 1.0
+
+
+def test_collide_chain_1d():
+    """Centres at k/8 with radius 1/16: neighbours touch (no overlap); with
+    radius 1/16 + 2^-10 each overlaps exactly its two neighbours."""
+    n = 8
+    S = np.zeros((n, 4), dtype=np.float32)
+    S[:, 0] = np.arange(n) / 8.0
+    S[:, 3] = 1 / 16
+    assert (oracle.collide(S, 1) == 0).all()
+    S[:, 3] = 1 / 16 + 2.0 ** -10
+    assert (oracle.collide(S, 1) == [1, 2, 2, 2, 2, 2, 2, 1]).all()
+    # the same spheres in 3-D, moved off the x axis equally, count the same
+    S[:, 1] = 0.25
+    S[:, 2] = 0.5
+    assert (oracle.collide(S, 3) == [1, 2, 2, 2, 2, 2, 2, 1]).all()
+
+
+def test_collide_one_equals_full():
+    S = inputs.spheres(300, 3, mean_degree=8.0, seed=4)
+    full = oracle.collide(S, 3)
+    for k in (0, 1, 150, 299):
+        assert oracle.collide_one(S, 3, k) == full[k]

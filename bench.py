@@ -153,6 +153,23 @@ def bench_elementwise(tm, torch, args, timer):
     return n, E, res, cpu, table
 
 
+def graph_time(torch, timer, fn, launches):
+    """GPU time per call of fn (ms) from a captured graph of `launches`
+    back-to-back calls, so that short launches are not host-bound."""
+    fn()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            for _ in range(launches):
+                fn()
+    torch.cuda.synchronize()
+    ms = timer.run(lambda: g.replay(), 5, 1) / launches
+    del g
+    return ms
+
+
 def bench_int_elementwise(tm, torch, timer, tile=16, launches=200):
     """n = 2048 int32, lambda vs BB (and the other maps): GPU time per launch
     from a captured graph of `launches` back-to-back launches (a single
@@ -275,6 +292,29 @@ def bench_edm4(tm, torch, timer, n=32768):
 VALU_LANE_OPS = 256 * 128 * 2.4e9
 
 
+def bench_map_study(tm, torch, timer, sizes=(4096, 32768), tile=16):
+    """The square-root study of Section 5.1 on the dummy kernel (the map, the
+    per-cell test, no stores): BB, RB, REC, UTM and lambda with each square
+    root (FP32 root / x rsq / bit-trick + 3 Newton steps / FP64, all with the
+    integer correction, and the paper's +1e-4 forms without it), as
+    I = t_BB / t_map."""
+    sink = torch.zeros(1, dtype=torch.int32, device="cuda")
+    variants = {"X": 0, "R": tm.FLAG_SQRT_RSQ, "N": tm.FLAG_SQRT_NEWTON, "F64": tm.FLAG_SQRT_F64,
+                "X_eps": tm.FLAG_SQRT_EPS, "R_eps": tm.FLAG_SQRT_EPS | tm.FLAG_SQRT_RSQ,
+                "N_eps": tm.FLAG_SQRT_EPS | tm.FLAG_SQRT_NEWTON}
+    out = {"tile": tile}
+    for n in sizes:
+        us = {}
+        for name, mp, fl in ([("bb", "bb", 0), ("rb", "rb", 0), ("rec", "rec", 0),
+                              ("utm", "utm", 0)] +
+                             [(f"lambda_{k}", "lambda", v) for k, v in variants.items()]):
+            p = tm.Plan(n, tile, mp, flags=fl)
+            us[name] = round(graph_time(torch, timer, lambda: p.dummy(-1, sink), 50) * 1e3, 3)
+        out[f"n{n}"] = {"us_per_launch": us,
+                        "I_vs_bb": {k: round(us["bb"] / v, 4) for k, v in us.items()}}
+    return out
+
+
 def bench_collide(tm, torch, timer, n=131072):
     """Sphere collision counts (the shared-memory test of Section 4.1), 1-D
     and 3-D, every map at tiles 16, 32, 64, 128 (UTM: thread space), with the
@@ -309,6 +349,42 @@ def bench_collide(tm, torch, timer, n=131072):
     del counts
     torch.cuda.empty_cache()
     return out
+
+
+def bench_tetra(tm, torch, timer, n=8192):
+    """The tetrahedral extension (Section 6): triangle counts of the
+    neighbour graph of n points (a triplet kernel over the strict
+    tetrahedron) and the map-only dummy kernel, 3-D lambda (FP32 / FP64 cube
+    root) vs the 3-D bounding box, I = t_BB / t_lambda."""
+    from paper_1609_01490_amd import inputs
+    P, r2 = inputs.points3(n)
+    Pd = torch.from_numpy(P).cuda()
+    counts = torch.empty(n, dtype=torch.int32, device="cuda")
+    total = torch.zeros(1, dtype=torch.int64, device="cuda")
+    sink = torch.zeros(1, dtype=torch.int32, device="cuda")
+    tri_ms, dummy_us = {}, {}
+    for t_ in (8, 16, 32):
+        for name, mp, fl in (("bb", "bb", 0), ("lambda", "lambda", 0),
+                             ("lambda_f64", "lambda", tm.FLAG_SQRT_F64)):
+            p = tm.TetPlan(n, t_, mp, strict=True, flags=fl)
+            tri_ms[f"{name}/t{t_}"] = round(
+                timer.run(lambda: p.triangles(Pd, float(r2), counts, total), 5, 2), 4)
+            if t_ <= 16:
+                q = tm.TetPlan(2048, t_, mp, strict=True, flags=fl)
+                dummy_us[f"{name}/t{t_}"] = round(
+                    graph_time(torch, timer, lambda: q.dummy(-1, sink), 10) * 1e3, 2)
+    tri_total = int(total.cpu()[0])
+    del Pd, counts, total, sink
+    torch.cuda.empty_cache()
+    best = min(tri_ms, key=tri_ms.get)
+    triples = n * (n - 1) * (n - 2) // 6
+    I = {k: round(tri_ms["bb/" + k.split("/")[1]] / v, 4) for k, v in tri_ms.items()}
+    Id = {k: round(dummy_us["bb/" + k.split("/")[1]] / v, 4) for k, v in dummy_us.items()}
+    return {"n": n, "triples": triples, "triangles": tri_total,
+            "triangles_ms_by_map_tile": tri_ms, "best": best,
+            "triples_per_s": round(triples / (tri_ms[best] * 1e-3), 1),
+            "I_vs_bb_same_tile": I,
+            "dummy_n2048_us_by_map_tile": dummy_us, "dummy_I_vs_bb": Id}
 
 
 def bench_batch(tm, torch, timer, steps=20, d=32, tiles=None):
@@ -461,6 +537,8 @@ def main():
                          ("edm_n65536_d128", lambda: bench_edm(tm, torch, timer)),
                          ("edm4_n32768", lambda: bench_edm4(tm, torch, timer)),
                          ("collide_n131072", lambda: bench_collide(tm, torch, timer)),
+                         ("map_study_dummy", lambda: bench_map_study(tm, torch, timer)),
+                         ("tetra_n8192", lambda: bench_tetra(tm, torch, timer)),
                          ("batch_512", lambda: bench_batch(tm, torch, timer))):
             log("extra", name)
             try:

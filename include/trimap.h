@@ -57,7 +57,13 @@ enum {
     TRI_FLAG_SQRT_F64 = 4u,    /* lambda: FP64 square root                             */
     TRI_FLAG_ORDER_REVERSE = 8u, /* lambda: dispatch omega from T-1 down to 0            */
     TRI_FLAG_ORDER_PAIRS = 16u,  /* lambda: alternate omega from the front and the back  */
-    TRI_FLAG_LIFE_TEMPORAL = 32u /* stencil: up to 4 generations per launch (4-cell halo) */
+    TRI_FLAG_LIFE_TEMPORAL = 32u, /* stencil: up to 4 generations per launch (4-cell halo) */
+    TRI_FLAG_SQRT_NEWTON = 64u,  /* lambda: bit-trick rsqrt + 3 Newton steps (lambda_N)  */
+    /* lambda, for the square-root study only: the paper's inexact row
+     * floor(sqrt(1/4 + 2 omega) + 1e-4 - 1/2) without the integer
+     * correction, with the square root the other SQRT flags select.  Wrong
+     * for some omega (tiles missed or repeated; never outside the domain). */
+    TRI_FLAG_SQRT_EPS = 128u
 };
 
 /* Elementwise bodies. */
@@ -142,6 +148,59 @@ tri_status tri_lambda_eval(const uint64_t *dev_omega, int64_t count, int include
  * `a` is used by TRI_OP_AXPYT_F32 only. */
 tri_status tri_launch_elementwise(const tri_plan *plan, int op, const void *x, const void *y,
                                   void *c, int64_t ld, float a, void *stream);
+
+/* The dummy kernel of the square-root study (Section 5.1): every cell
+ * (i, j) of the plan's domain (any map, tile 8 to 64, with or without the
+ * diagonal) forms its coordinates through the map and computes i + j; cells
+ * with i + j == target store that sum to sink[0] (device int32).  A target
+ * no cell reaches (e.g. -1) writes nothing, so the launch costs the
+ * dispatch, the map (TRI_FLAG_SQRT_* variants included) and the per-cell
+ * test alone. */
+tri_status tri_launch_dummy(const tri_plan *plan, int32_t target, int32_t *sink, void *stream);
+
+/* ---- Tetrahedral domains (Section 6) ------------------------------------- */
+
+/* A plan for the tetrahedron of n points tiled in rho^3 tiles (rho in {8,
+ * 16, 32}): tiles (i, j, k), 0 <= i <= j <= k < m, m = ceil(n_eff / rho),
+ * Tet(m) = m(m+1)(m+2)/6 of them.  strict = 1 covers the triples
+ * a > b > c of n points (the non-strict tetrahedron of side n_eff = n - 2,
+ * shifted: (a, b, c) = (k + 2, j + 1, i) per point), strict = 0 the triples
+ * a >= b >= c (n_eff = n).  map: TRI_MAP_LAMBDA (1-D grid of Tet(m) blocks;
+ * block omega's layer k is the largest with Tet(k) <= omega, from a cube
+ * root and an exact integer correction, the rest of omega through the 2-D
+ * lambda) or TRI_MAP_BB (m x m x m grid, blocks with i <= j <= k kept;
+ * m <= 65535).  flags: 0 (FP32 roots below 2^32) or TRI_FLAG_SQRT_F64 (FP64
+ * roots).  n < 2^21.  Freed by tri_tet_destroy. */
+typedef struct tri_tet tri_tet;
+tri_status tri_tet_plan(tri_tet **out, int64_t n, int tile, int map, int strict, uint32_t flags);
+tri_status tri_tet_destroy(tri_tet *plan);
+/* Tiles Tet(m), launched grid blocks, and triples in the domain (any
+ * pointer may be NULL). */
+tri_status tri_tet_query(const tri_tet *plan, int64_t *tiles, int64_t *grid_blocks, int64_t *cells);
+
+/* Test hook: for grid block b (b = (bz gy + by) gx + bx), dev_out[3b..3b+2]
+ * = its tile (i, j, k), or -1 three times when the block is discarded. */
+tri_status tri_tet_dump(const tri_tet *plan, int64_t *dev_out, void *stream);
+
+/* Test hook: the tetrahedral lambda of count arbitrary omega < 2^62
+ * (uint64) into dev_out[3t..3t+2] = (i, j, k); flags as for the plan. */
+tri_status tri_lambda3_eval(const uint64_t *dev_omega, int64_t count, uint32_t flags,
+                            int64_t *dev_out, void *stream);
+
+/* A triplet kernel over the strict tetrahedron: triangles of the neighbour
+ * graph of n points (rows (x, y, z, unused) of `points`, FP32, 16-byte
+ * aligned).  Points a and b are neighbours when, in binary32 without fused
+ * multiply-add, ((dx^2 + dy^2) + dz^2) < r2 with d. = a. - b.  Every triple
+ * a > b > c of mutual neighbours is a triangle: counts[v] (int32[n]) gets the
+ * number of triangles with vertex v, *total (uint64, 8-byte aligned) their
+ * number; the call clears both first.  The plan must be strict. */
+tri_status tri_triangles(const tri_tet *plan, const float *points, float r2, int32_t *counts,
+                         unsigned long long *total, void *stream);
+
+/* The dummy kernel on the tetrahedron: each triple (a, b, c) of the plan's
+ * domain forms its indices through the map and computes a + b + c; triples
+ * with a + b + c == target store it to sink[0] (device int32). */
+tri_status tri_tet_dummy(const tri_tet *plan, int32_t target, int32_t *sink, void *stream);
 
 /* Game of Life B3/S23 on the lower triangle (include_diag must be 1; UTM
  * is not supported: it has no 2-D block to stage a halo in).  cur and nxt

@@ -64,6 +64,14 @@ def lib() -> ctypes.CDLL:
         L.orc_edm_rows.argtypes = [i64, i64, vp, i64, vp, i64, vp]
         L.orc_edm4.argtypes = [i64, vp, i64, i64, vp, i64]
         L.orc_collide.argtypes = [i64, ctypes.c_int, vp, vp]
+        L.orc_tet.restype = u64
+        L.orc_tet.argtypes = [u64]
+        L.orc_lambda3.argtypes = [u64, p64, p64, p64]
+        L.orc_bb3_dump.restype = i64
+        L.orc_bb3_dump.argtypes = [i64, vp]
+        L.orc_triangles.argtypes = [i64, vp, ctypes.c_float, vp, ctypes.POINTER(u64)]
+        L.orc_triangles_one.restype = ctypes.c_int32
+        L.orc_triangles_one.argtypes = [i64, vp, ctypes.c_float, i64, vp]
         L.orc_collide_one.restype = ctypes.c_int32
         L.orc_collide_one.argtypes = [i64, ctypes.c_int, vp, i64]
         L.orc_queue_locate.restype = ctypes.c_int
@@ -170,6 +178,44 @@ def collide_one(S: np.ndarray, dim: int, k: int) -> int:
     """Overlap count of sphere k alone."""
     S = np.ascontiguousarray(S, dtype=np.float32)
     return int(lib().orc_collide_one(S.shape[0], dim, _ptr(S), int(k)))
+
+
+def tet(k: int) -> int:
+    """Tetrahedral number k(k+1)(k+2)/6."""
+    return int(lib().orc_tet(k))
+
+
+def lam3(omega: int) -> tuple[int, int, int]:
+    """Tetrahedral lambda(omega) = (i, j, k), i <= j <= k."""
+    i, j, k = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    lib().orc_lambda3(omega, ctypes.byref(i), ctypes.byref(j), ctypes.byref(k))
+    return i.value, j.value, k.value
+
+
+def bb3_dump(m: int) -> np.ndarray:
+    """(i, j, k) per block of the m^3 bounding-box grid, -1 if discarded."""
+    out = np.empty((m * m * m, 3), dtype=np.int64)
+    lib().orc_bb3_dump(m, _ptr(out))
+    return out
+
+
+def triangles(P: np.ndarray, r2: float) -> tuple[np.ndarray, int]:
+    """Per-point triangle counts of the neighbour graph, and the total."""
+    P = np.ascontiguousarray(P, dtype=np.float32)
+    assert P.ndim == 2 and P.shape[1] == 4
+    counts = np.zeros(P.shape[0], dtype=np.int32)
+    tot = ctypes.c_uint64()
+    lib().orc_triangles(P.shape[0], _ptr(P), float(np.float32(r2)), _ptr(counts),
+                        ctypes.byref(tot))
+    return counts, tot.value
+
+
+def triangles_one(P: np.ndarray, r2: float, v: int) -> int:
+    """Triangle count of vertex v alone."""
+    P = np.ascontiguousarray(P, dtype=np.float32)
+    nb = np.empty(P.shape[0], dtype=np.int64)
+    return int(lib().orc_triangles_one(P.shape[0], _ptr(P), float(np.float32(r2)), int(v),
+                                       _ptr(nb)))
 
 
 def gol(grid: np.ndarray, n: int, steps: int, r0: int = 0, c0_: int = 0,

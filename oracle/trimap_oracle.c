@@ -460,6 +460,108 @@ int32_t orc_collide_one(int64_t n, int dim, const float *S, int64_t k)
 }
 
 /* ------------------------------------------------------------------------ */
+/* Tetrahedral block map (Section 6, the extension to 3-D)                    */
+/* ------------------------------------------------------------------------ */
+
+/* Tetrahedral number Tet(k) = k(k+1)(k+2)/6: the number of blocks in layers
+ * 0..k-1, layer k being a triangle of (k+1)(k+2)/2 blocks (Section 6). */
+uint64_t orc_tet(uint64_t k)
+{
+    return k * (k + 1ull) / 2ull * (k + 2ull) / 3ull;
+}
+
+/* The 3-D lambda: block omega lies in layer k, the largest k with
+ * Tet(k) <= omega (the integer part of the real root of the cubic of
+ * Section 6, found here by an integer binary search, which is exact); within
+ * the layer omega_2D = omega - Tet(k) is mapped by the 2-D lambda to row j
+ * and column i.  Result (i, j, k) with 0 <= i <= j <= k. */
+void orc_lambda3(uint64_t omega, int64_t *i, int64_t *j, int64_t *k)
+{
+    uint64_t lo = 0, hi = 3100000ull; /* Tet(3.1e6) > 2^62; k(k+1)/2 (k+2) < 2^64 */
+    while (lo < hi) {
+        uint64_t mid = lo + (hi - lo + 1) / 2;
+        if (orc_tet(mid) <= omega)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    *k = (int64_t)lo;
+    orc_lambda(omega - orc_tet(lo), j, i);
+}
+
+/* Bounding box of the tetrahedron: an m x m x m grid, block (bx, by, bz)
+ * (id = (bz m + by) m + bx) kept iff bx <= by <= bz, as tile (i, j, k) =
+ * (bx, by, bz).  Writes 3 entries per grid block, -1 for discarded ones;
+ * returns the number of blocks. */
+int64_t orc_bb3_dump(int64_t m, int64_t *out)
+{
+    int64_t b = 0;
+    for (int64_t bz = 0; bz < m; ++bz)
+        for (int64_t by = 0; by < m; ++by)
+            for (int64_t bx = 0; bx < m; ++bx, ++b) {
+                int keep = bx <= by && by <= bz;
+                out[3 * b + 0] = keep ? bx : -1;
+                out[3 * b + 1] = keep ? by : -1;
+                out[3 * b + 2] = keep ? bz : -1;
+            }
+    return b;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Triangles of the neighbour graph (a triplet kernel on the tetrahedron)    */
+/* ------------------------------------------------------------------------ */
+
+/* Points are rows (x, y, z, w) of P (n x 4; w unused).  Points a and b are
+ * neighbours when their squared distance, in binary32 without fused
+ * multiply-add, ((dx^2 + dy^2) + dz^2) with d. = a. - b., is below r2
+ * (strict).  The test is symmetric: a - b is exactly -(b - a). */
+static int orc_near(const float *a, const float *b, float r2)
+{
+    float dx = a[0] - b[0], dy = a[1] - b[1], dz = a[2] - b[2];
+    float sx = dx * dx, sy = dy * dy, sz = dz * dz;
+    float s = sx + sy;
+    s = s + sz;
+    return s < r2;
+}
+
+/* Every triple a > b > c of mutual neighbours is one triangle: counts[v]
+ * receives the number of triangles with vertex v, *total their number. */
+void orc_triangles(int64_t n, const float *P, float r2, int32_t *counts, uint64_t *total)
+{
+    uint64_t t = 0;
+    for (int64_t v = 0; v < n; ++v)
+        counts[v] = 0;
+    for (int64_t a = 2; a < n; ++a)
+        for (int64_t b = 1; b < a; ++b) {
+            if (!orc_near(P + 4 * a, P + 4 * b, r2))
+                continue;
+            for (int64_t c = 0; c < b; ++c)
+                if (orc_near(P + 4 * a, P + 4 * c, r2) && orc_near(P + 4 * b, P + 4 * c, r2)) {
+                    counts[a]++;
+                    counts[b]++;
+                    counts[c]++;
+                    t++;
+                }
+        }
+    *total = t;
+}
+
+/* The triangle count of one vertex v alone: pairs u > w of neighbours of v
+ * that are neighbours of each other.  nb is scratch for n indices. */
+int32_t orc_triangles_one(int64_t n, const float *P, float r2, int64_t v, int64_t *nb)
+{
+    int64_t d = 0;
+    for (int64_t u = 0; u < n; ++u)
+        if (u != v && orc_near(P + 4 * (u > v ? u : v), P + 4 * (u > v ? v : u), r2))
+            nb[d++] = u;
+    int32_t c = 0;
+    for (int64_t x = 1; x < d; ++x)
+        for (int64_t y = 0; y < x; ++y)
+            c += orc_near(P + 4 * nb[x], P + 4 * nb[y], r2);
+    return c;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Batched work queue over per-instance lambda numberings                    */
 /* ------------------------------------------------------------------------ */
 

@@ -31,6 +31,36 @@ struct TileGrid {
 // it exact; that is why no epsilon is added as in the paper's lambda_N and
 // lambda_R.  omega >= 2^32 always takes the FP64 root.
 // ---------------------------------------------------------------------------
+// Square root of the lambda_N variant (Section 5.1): reciprocal square root
+// from the integer bit trick of the fast inverse square root (initial
+// constant 0x5f3759df, Lomont's analysis), three Newton-Raphson steps
+// y <- y (3/2 - (x/2) y^2), then sqrt(x) = x y.
+__device__ __forceinline__ float sqrt_newton3(float x)
+{
+    float y = __uint_as_float(0x5f3759dfu - (__float_as_uint(x) >> 1));
+    const float h = 0.5f * x;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) y = y * (1.5f - h * y * y);
+    return x * y;
+}
+
+__device__ __forceinline__ float sqrt_variant(float x, uint32_t flags)
+{
+    if (flags & TRI_FLAG_SQRT_RSQ) return x * __builtin_amdgcn_rsqf(x);
+    if (flags & TRI_FLAG_SQRT_NEWTON) return sqrt_newton3(x);
+    return __builtin_amdgcn_sqrtf(x);
+}
+
+// The paper's inexact form (Section 5.1): i = floor(sqrt(1/4 + 2 omega) + eps
+// - 1/2) with eps = 1e-4 and no integer correction.  Kept for the square-root
+// study only: it is wrong for some omega, so kernels may miss or repeat tiles.
+__device__ __forceinline__ uint32_t lambda_row_eps(uint64_t w, uint32_t flags)
+{
+    const float s = sqrt_variant(0.25f + 2.0f * (float)(uint32_t)w, flags) + 1e-4f;
+    const float r = s - 0.5f;
+    return r < 0.f ? 0u : (uint32_t)r;
+}
+
 __device__ __forceinline__ uint32_t lambda_row(uint64_t w, uint32_t flags)
 {
     int32_t r;
@@ -38,9 +68,9 @@ __device__ __forceinline__ uint32_t lambda_row(uint64_t w, uint32_t flags)
         double s = __builtin_sqrt(8.0 * (double)w + 1.0);
         r = (int32_t)((s - 1.0) * 0.5);
     } else {
+        if (flags & TRI_FLAG_SQRT_EPS) return lambda_row_eps(w, flags);
         float x = __builtin_fmaf(8.0f, (float)(uint32_t)w, 1.0f);
-        float s = (flags & TRI_FLAG_SQRT_RSQ) ? x * __builtin_amdgcn_rsqf(x)
-                                              : __builtin_amdgcn_sqrtf(x);
+        float s = sqrt_variant(x, flags);
         r = (int32_t)((s - 1.0f) * 0.5f);
     }
     uint32_t i = r < 0 ? 0u : (uint32_t)r;

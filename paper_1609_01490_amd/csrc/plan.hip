@@ -130,7 +130,8 @@ tri_status tri_map_plan(tri_plan **out, int64_t n, int tile, int map, int includ
         return fail(TRI_E_INVAL, "tri_map_plan: include_diag = %d", include_diag);
     if (flags & ~(uint32_t)(TRI_FLAG_XCD_SWIZZLE | TRI_FLAG_SQRT_RSQ | TRI_FLAG_SQRT_F64 |
                             TRI_FLAG_ORDER_REVERSE | TRI_FLAG_ORDER_PAIRS |
-                            TRI_FLAG_LIFE_TEMPORAL))
+                            TRI_FLAG_LIFE_TEMPORAL | TRI_FLAG_SQRT_NEWTON |
+                            TRI_FLAG_SQRT_EPS))
         return fail(TRI_E_INVAL, "tri_map_plan: unknown flags 0x%x", flags);
 
     tri_plan p{};
@@ -266,7 +267,8 @@ tri_status tri_lambda_eval(const uint64_t *dev_omega, int64_t count, int include
     clear_error();
     if (count < 0 || (count > 0 && (!dev_omega || !dev_out)))
         return fail(TRI_E_INVAL, "tri_lambda_eval: bad arguments");
-    if (flags & ~(uint32_t)(TRI_FLAG_SQRT_RSQ | TRI_FLAG_SQRT_F64))
+    if (flags & ~(uint32_t)(TRI_FLAG_SQRT_RSQ | TRI_FLAG_SQRT_F64 | TRI_FLAG_SQRT_NEWTON |
+                            TRI_FLAG_SQRT_EPS))
         return fail(TRI_E_INVAL, "tri_lambda_eval: unknown flags 0x%x", flags);
     if (count == 0) return TRI_OK;
     const int64_t blocks = (count + 255) / 256;

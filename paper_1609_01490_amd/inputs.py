@@ -16,6 +16,8 @@ Workloads (sizes of the defaults):
   * collision detection: n = 131072 spheres, centres uniform in the unit
                        box (3-D, or 1-D on x), radii uniform in [0, r_max)
                        with r_max set for about 4 overlaps per sphere.
+  * triangles (tetrahedral domain): n = 8192 points uniform in the unit
+                       cube, neighbour radius for about 8 neighbours each.
   * batched:           512 instances, n log-uniform in [64, 8192]; even
                        instance index = distance map (d = 32), odd = Life
                        (density 0.3, 20 steps).
@@ -185,6 +187,18 @@ def spheres(n: int = 131072, dim: int = 3, mean_degree: float = 4.0,
         r_max = mean_degree / (2.0 * pairs_per)
     S[:, 3] = uniform_f32((n,), sr, 0.0, float(r_max))
     return S
+
+
+def points3(n: int = 8192, mean_degree: float = 8.0, seed: int | None = None):
+    """P float32[n, 4] = (x, y, z, 0), points uniform in the unit cube, and
+    the squared radius r2 (float32) that gives about mean_degree neighbours
+    per point away from the walls: (n - 1) (4/3) pi r^3 = mean_degree."""
+    seed = seed_for(8) if seed is None else seed
+    (sp,) = _streams(seed, 1)
+    P = np.zeros((n, 4), dtype=np.float32)
+    P[:, :3] = uniform_f32((n, 3), sp, 0.0, 1.0)
+    r = (3.0 * mean_degree / (4.0 * np.pi * max(n - 1, 1))) ** (1.0 / 3.0)
+    return P, np.float32(r * r)
 
 
 def batch_instances(count: int = 512, n_lo: int = 64, n_hi: int = 8192,

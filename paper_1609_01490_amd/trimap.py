@@ -21,6 +21,7 @@ MAP_NAMES = {v: k for k, v in MAPS.items()}
 
 FLAG_XCD_SWIZZLE, FLAG_SQRT_RSQ, FLAG_SQRT_F64 = 1, 2, 4
 FLAG_ORDER_REVERSE, FLAG_ORDER_PAIRS, FLAG_LIFE_TEMPORAL = 8, 16, 32
+FLAG_SQRT_NEWTON, FLAG_SQRT_EPS = 64, 128
 OP_XORMUL_I32, OP_AXPYT_F32, OP_EDM4_F32 = 0, 1, 2
 EDM_FP32, EDM_BF16X3, EDM_BF16 = 0, 1, 2
 KIND_EDM, KIND_LIFE = 0, 1
@@ -85,6 +86,23 @@ def _load() -> ctypes.CDLL:
     L.tri_edm_workspace_size.argtypes = [vp, i64, i32, ctypes.POINTER(ctypes.c_size_t)]
     L.tri_edm.restype = st
     L.tri_edm.argtypes = [vp, vp, i64, i64, vp, i32, ctypes.c_float, vp, ctypes.c_size_t, vp]
+    L.tri_tet_plan.restype = st
+    L.tri_tet_plan.argtypes = [ctypes.POINTER(vp), i64, i32, i32, i32, u32]
+    L.tri_tet_destroy.restype = st
+    L.tri_tet_destroy.argtypes = [vp]
+    L.tri_tet_query.restype = st
+    L.tri_tet_query.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                ctypes.POINTER(ctypes.c_int64)]
+    L.tri_tet_dump.restype = st
+    L.tri_tet_dump.argtypes = [vp, vp, vp]
+    L.tri_lambda3_eval.restype = st
+    L.tri_lambda3_eval.argtypes = [vp, i64, u32, vp, vp]
+    L.tri_triangles.restype = st
+    L.tri_triangles.argtypes = [vp, vp, ctypes.c_float, vp, vp, vp]
+    L.tri_tet_dummy.restype = st
+    L.tri_tet_dummy.argtypes = [vp, i32, vp, vp]
+    L.tri_launch_dummy.restype = st
+    L.tri_launch_dummy.argtypes = [vp, i32, vp, vp]
     L.tri_collide.restype = st
     L.tri_collide.argtypes = [vp, vp, i32, vp, vp]
     L.tri_batch_plan.restype = st
@@ -231,11 +249,68 @@ class Plan:
         _check(lib.tri_edm(self._h, _dptr(x), int(d), int(x.stride(0)), _dptr(out), int(mode),
                            float(fixup_thr), _dptr(ws), int(wsb), _stream(stream)))
 
+    def dummy(self, target: int, sink, stream=None):
+        """The square-root study's dummy kernel (tri_launch_dummy)."""
+        _check(lib.tri_launch_dummy(self._h, int(target), _dptr(sink), _stream(stream)))
+
     def collide(self, spheres, counts, dim: int = 3, stream=None):
         """Per-sphere overlap counts (tri_collide); spheres is a float32
         device tensor n x 4 (x, y, z, r), counts an int32 device tensor."""
         _check(lib.tri_collide(self._h, _dptr(spheres), int(dim), _dptr(counts),
                                _stream(stream)))
+
+
+class TetPlan:
+    """A tile space of a tetrahedral domain (tri_tet_plan): BB or lambda."""
+
+    def __init__(self, n: int, tile: int = 16, map: int | str = LAMBDA, strict: bool = True,
+                 flags: int = 0):
+        if isinstance(map, str):
+            map = MAPS[map]
+        h = ctypes.c_void_p()
+        _check(lib.tri_tet_plan(ctypes.byref(h), int(n), int(tile), int(map),
+                                1 if strict else 0, int(flags)))
+        self._h = h
+        t, g, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib.tri_tet_query(h, ctypes.byref(t), ctypes.byref(g), ctypes.byref(c)))
+        self.n, self.tile, self.map, self.strict = int(n), int(tile), int(map), bool(strict)
+        self.tiles, self.grid_blocks, self.cells = t.value, g.value, c.value
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            lib.tri_tet_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def dump(self, stream=None):
+        """(i, j, k) per grid block, -1 for discarded blocks (int64 [blocks, 3])."""
+        import torch
+        out = torch.empty((max(self.grid_blocks, 0), 3), dtype=torch.int64, device="cuda")
+        if self.grid_blocks:
+            _check(lib.tri_tet_dump(self._h, _dptr(out), _stream(stream)))
+        return out
+
+    def triangles(self, points, r2: float, counts, total, stream=None):
+        """Triangle counts of the neighbour graph (tri_triangles)."""
+        _check(lib.tri_triangles(self._h, _dptr(points), float(r2), _dptr(counts), _dptr(total),
+                                 _stream(stream)))
+
+    def dummy(self, target: int, sink, stream=None):
+        _check(lib.tri_tet_dummy(self._h, int(target), _dptr(sink), _stream(stream)))
+
+
+def lambda3_eval(omega, flags: int = 0, stream=None):
+    """Device tetrahedral lambda(omega) -> int64 [count, 3] = (i, j, k)."""
+    import torch
+    out = torch.empty((omega.numel(), 3), dtype=torch.int64, device=omega.device)
+    _check(lib.tri_lambda3_eval(_dptr(omega), int(omega.numel()), int(flags), _dptr(out),
+                                _stream(stream)))
+    return out
 
 
 def lambda_eval(omega, include_diag: bool = True, flags: int = 0, stream=None):

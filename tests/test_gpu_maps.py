@@ -104,7 +104,7 @@ def _boundary_omegas():
     return np.unique(w)
 
 
-@pytest.mark.parametrize("flags", [0, 2, 4])
+@pytest.mark.parametrize("flags", [0, 2, 4, 64])
 def test_lambda_exact_at_row_boundaries(flags):
     tm = _tm()
     w = _boundary_omegas()
@@ -130,3 +130,55 @@ def test_lambda_nodiag_eval():
     i = got[:, 0].astype(np.uint64)
     j = got[:, 1].astype(np.uint64)
     assert (j < i).all() and (((i - 1) * i // 2 + j) == w).all()
+
+
+@pytest.mark.parametrize("base", [0, 2, 64])
+def test_lambda_epsilon_variants_study(base):
+    """The paper's inexact rows (TRI_FLAG_SQRT_EPS: +1e-4, no integer
+    correction) with each FP32 square root.  Below T_1000 they are exact:
+    there 1/4 + 2 omega is exact in FP32, the root is off by a few units in
+    the last place (<= 2e-4) and the row boundaries are 2/(2i + 1) >= 1e-3
+    apart from the nearest integer, so the epsilon only repairs roots that
+    fall just short of an exact integer.  Higher up the gap shrinks below
+    epsilon and the rounding of 2 omega grows, and they go wrong, though
+    never by more than one row.  The corrected variants (test above) are
+    exact everywhere."""
+    tm = _tm()
+    w = _boundary_omegas()
+    w = w[w < 2**32]
+    note("lambda eps eval", base, w.size)
+    got = host(tm.lambda_eval(dev(w.view(np.int64)), True, base | tm.FLAG_SQRT_EPS))
+    i = got[:, 0].astype(np.int64)
+    wi = w.astype(np.int64)
+    # the true row from the exact integer relation T_i <= w < T_{i+1}
+    t = np.floor((np.sqrt(8.0 * w.astype(np.float64) + 1.0) - 1.0) / 2.0).astype(np.int64)
+    t -= (t * (t + 1) // 2 > wi).astype(np.int64)
+    t += ((t + 1) * (t + 2) // 2 <= wi).astype(np.int64)
+    assert (np.abs(i - t) <= 1).all()
+    small = wi < 1000 * 1001 // 2
+    assert (i[small] == t[small]).all()
+    wrong = w[i != t]
+    note("eps variant", base, "wrong", wrong.size, "of", w.size,
+         "first", int(wrong.min()) if wrong.size else None)
+    assert wrong.size > 0
+
+
+@pytest.mark.parametrize("map_name", ["bb", "rb", "rec", "utm", "lambda"])
+@pytest.mark.parametrize("tile", [8, 16, 32, 64])
+def test_dummy_kernel_reaches_every_sum(map_name, tile):
+    """Cells of the domain reach exactly the sums i + j in 0..2n-2 (with the
+    diagonal) or 1..2n-3 (without); only a reached target is stored."""
+    import torch
+    tm = _tm()
+    for n, diag in ((1, True), (5, True), (100, True), (257, False), (300, True), (513, False)):
+        m = -(-(n if diag else n - 1) // tile)
+        if map_name == "rec" and m and (m & (m - 1)):
+            continue
+        p = tm.Plan(n, tile, map_name, include_diag=diag)
+        lo, hi = (0, 2 * n - 2) if diag else (1, 2 * n - 3)
+        for target in sorted({-1, 0, 1, lo, hi, hi + 1, n - 1, (lo + hi) // 2, 2 * n + 5}):
+            note("dummy", map_name, tile, n, diag, target)
+            sink = torch.full((1,), -123, dtype=torch.int32, device="cuda")
+            p.dummy(target, sink)
+            exp = target if (lo <= target <= hi and n > (0 if diag else 1)) else -123
+            assert int(host(sink)[0]) == exp, (map_name, tile, n, diag, target)

@@ -1,0 +1,128 @@
+"""GPU parity of the tetrahedral extension (Section 6): the 3-D lambda and
+the 3-D bounding box against the oracle block by block, the 3-D lambda
+exact at every layer boundary (FP32 and FP64 roots), the triangle counts of
+the neighbour graph (a triplet kernel over the strict tetrahedron)
+bit-exact per point, and the dummy kernel reaching every index sum."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import dev, host, note
+from paper_1609_01490_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _tm():
+    from paper_1609_01490_amd import trimap
+    return trimap
+
+
+@pytest.mark.parametrize("map_name", ["bb", "lambda"])
+@pytest.mark.parametrize("tile", [8, 16, 32])
+def test_tet_dump_equals_oracle(map_name, tile):
+    tm = _tm()
+    for n, strict in ((1, False), (tile, False), (5 * tile - 3, False), (13 * tile, False),
+                      (2, True), (3, True), (7 * tile + 1, True), (20 * tile + 2, True)):
+        p = tm.TetPlan(n, tile, map_name, strict=strict)
+        ne = n - 2 if strict else n
+        m = -(-max(ne, 0) // tile)
+        assert p.tiles == oracle.tet(m)
+        note("tet dump", map_name, tile, n, strict)
+        got = host(p.dump())
+        if map_name == "bb":
+            assert (got == oracle.bb3_dump(m)).all()
+        else:
+            exp = np.array([oracle.lam3(w) for w in range(p.tiles)], dtype=np.int64).reshape(-1, 3)
+            assert (got[:p.tiles] == exp).all()
+            assert (got[p.tiles:] == -1).all()
+
+
+def _layer_omegas():
+    k = np.arange(0, 2952, dtype=np.uint64)           # every layer starting below 2^32
+    T = k * (k + 1) // 2 * (k + 2) // 3
+    L = (k + 1) * (k + 2) // 2
+    w = np.concatenate([T, T + L - 1, np.maximum(T, 1) - 1, T + L // 2])
+    rng = np.random.default_rng(4)
+    big = rng.integers(2 ** 32, 2 ** 62, 3000, dtype=np.uint64)
+    kb = np.array([oracle.lam3(int(x))[2] for x in big[:300]], dtype=np.uint64)
+    Tb = kb * (kb + 1) // 2 * (kb + 2) // 3
+    w = np.concatenate([w, rng.integers(0, 2 ** 32, 100000, dtype=np.uint64), big, Tb, Tb - 1,
+                        np.array([2 ** 32 - 1, 2 ** 32], dtype=np.uint64)])
+    return np.unique(w)
+
+
+@pytest.mark.parametrize("flags", [0, 4])
+def test_lambda3_exact_at_layer_boundaries(flags):
+    tm = _tm()
+    w = _layer_omegas()
+    note("lambda3 eval", flags, w.size)
+    got = host(tm.lambda3_eval(dev(w.view(np.int64)), flags)).astype(np.uint64)
+    i, j, k = got[:, 0], got[:, 1], got[:, 2]
+    assert ((i <= j) & (j <= k)).all()
+    tk = k * (k + 1) // 2 * (k + 2) // 3
+    k1 = k + 1
+    tk1 = k1 * (k1 + 1) // 2 * (k1 + 2) // 3
+    assert (tk + j * (j + 1) // 2 + i == w).all()
+    assert (w < tk1).all()
+    for s in np.random.default_rng(5).choice(w.size, 2000, replace=False):
+        assert oracle.lam3(int(w[s])) == tuple(int(x) for x in got[s])
+
+
+def _lattice(n, seed):
+    rng = np.random.default_rng(seed)
+    P = np.zeros((n, 4), dtype=np.float32)
+    P[:, :3] = rng.integers(0, 16, (n, 3)) / 16.0
+    return P, np.float32(5 / 256)        # exact ties at squared distance 5/256
+
+
+@pytest.mark.parametrize("map_name", ["bb", "lambda"])
+@pytest.mark.parametrize("tile", [8, 16, 32])
+def test_triangles_bit_exact(map_name, tile):
+    import torch
+    tm = _tm()
+    for n in (1, 2, 3, 10, 33, 100, 257, 300):
+        p = tm.TetPlan(n, tile, map_name, strict=True)
+        P, r2 = inputs.points3(n, mean_degree=12.0, seed=7000 + n)
+        for case, (arr, rr) in (("random", (P, r2)), ("lattice", _lattice(n, n))):
+            exp_c, exp_t = oracle.triangles(arr, rr)
+            note("triangles", map_name, tile, n, case)
+            counts = torch.full((n,), -5, dtype=torch.int32, device="cuda")
+            total = torch.full((1,), -5, dtype=torch.int64, device="cuda")
+            p.triangles(dev(arr), float(rr), counts, total)
+            assert (host(counts) == exp_c).all(), (map_name, tile, n, case)
+            assert int(host(total)[0]) == exp_t, (map_name, tile, n, case)
+
+
+@pytest.mark.parametrize("map_name", ["bb", "lambda"])
+@pytest.mark.parametrize("tile", [8, 16])
+def test_tet_dummy_reaches_every_sum(map_name, tile):
+    import torch
+    tm = _tm()
+    for n, strict in ((1, False), (3, True), (20, True), (37, False), (50, True)):
+        p = tm.TetPlan(n, tile, map_name, strict=strict)
+        lo, hi = (3, 3 * n - 6) if strict else (0, 3 * n - 3)
+        for target in sorted({-1, 0, 2, lo, hi, hi + 1, (lo + hi) // 2}):
+            note("tet dummy", map_name, tile, n, strict, target)
+            sink = torch.full((1,), -123, dtype=torch.int32, device="cuda")
+            p.dummy(target, sink)
+            ok = lo <= target <= hi and n >= (3 if strict else 1)
+            assert int(host(sink)[0]) == (target if ok else -123), (n, strict, target)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("map_name,tile", [("lambda", 32), ("bb", 32), ("lambda", 16)])
+def test_triangles_full_size(map_name, tile):
+    """n = 8192 points, about 8 neighbours each: every per-point count and
+    the total equal the oracle's."""
+    import torch
+    tm = _tm()
+    n = 8192
+    P, r2 = inputs.points3(n)
+    note("triangles full", map_name, tile, n)
+    counts = torch.zeros(n, dtype=torch.int32, device="cuda")
+    total = torch.zeros(1, dtype=torch.int64, device="cuda")
+    tm.TetPlan(n, tile, map_name, strict=True).triangles(dev(P), float(r2), counts, total)
+    exp_c, exp_t = oracle.triangles(P, r2)
+    assert (host(counts) == exp_c).all()
+    assert int(host(total)[0]) == exp_t and exp_t > 1000

@@ -15,9 +15,14 @@ namespace trimap {
 // Uniform description of the tile grid handed to every tile kernel.
 struct TileGrid {
     int32_t m;       // tiles per side
-    uint32_t flags;  // TRI_FLAG_*
+    uint32_t flags;  // TRI_FLAG_*, plus kLambda24
     uint64_t T;      // tiles, m (m + 1) / 2
 };
+
+// Internal TileGrid flag: lambda launched as a 1-D grid of exactly T < 2^24
+// blocks with the default root and order (the swizzle allowed), so the map
+// can take its 32-bit path.
+constexpr uint32_t kLambda24 = 1u << 31;
 
 // ---------------------------------------------------------------------------
 // lambda(omega), Eq. eq_gmap: row i = floor((sqrt(8 omega + 1) - 1) / 2),
@@ -89,6 +94,28 @@ __device__ __forceinline__ void lambda_tile(uint64_t w, uint32_t flags, int32_t 
     bj = (int32_t)(w - (uint64_t)i * (i + 1) / 2);
 }
 
+// The same map for w < 2^24 (a 1-D grid) in 32-bit arithmetic: 8w + 1 is
+// rounded once to 24 bits, the root is off by far less than one row, and
+// rows stay below 2^12.5, so T_i and the one-step correction fit in 32 bits.
+// The map is wave-uniform: a handful of scalar instructions per wave after
+// the square root (the scalar unit is shared by the CU's waves, so its
+// instruction count, not the root, is what the map costs).
+__device__ __forceinline__ void lambda_tile_24(uint32_t w, int32_t &bi, int32_t &bj)
+{
+    const float x = __builtin_fmaf(8.0f, (float)w, 1.0f);
+    uint32_t i = (uint32_t)((__builtin_amdgcn_sqrtf(x) - 1.0f) * 0.5f);
+    uint32_t t = i * (i + 1) / 2;
+    if (t > w) {
+        --i;
+        t -= i + 1;
+    } else if (t + i + 1 <= w) {
+        t += i + 1;
+        ++i;
+    }
+    bi = (int32_t)i;
+    bj = (int32_t)(w - t);
+}
+
 // Give each of the 8 XCDs a contiguous range of omega.  Workgroups are
 // dispatched to XCDs round-robin by linear id; block L runs on XCD L mod 8.
 // With G = 8q + r blocks, XCD x holds q + (x < r) blocks, so its range starts
@@ -152,6 +179,16 @@ __device__ __forceinline__ bool tile_of_block_raw(const TileGrid &g, int32_t &bi
         bj = q * 2 * s + c;
         return true;
     } else {  // MAP_LAMBDA
+        if (g.flags & kLambda24) {
+            // 1-D grid of exactly T < 2^24 blocks, default root and order
+            uint32_t L = blockIdx.x;
+            if (g.flags & TRI_FLAG_XCD_SWIZZLE) {
+                const uint32_t x = L & 7, l = L >> 3, G = (uint32_t)g.T, q = G >> 3, r = G & 7;
+                L = x * q + (x < r ? x : r) + l;
+            }
+            lambda_tile_24(L, bi, bj);
+            return true;
+        }
         uint64_t L = (uint64_t)blockIdx.y * gridDim.x + blockIdx.x;
         if (g.flags & TRI_FLAG_XCD_SWIZZLE)
             L = xcd_swizzle(L, (uint64_t)gridDim.x * gridDim.y);

@@ -50,7 +50,14 @@ static bool grid_1d(uint64_t blocks, uint32_t &gx, uint32_t &gy)
     return true;
 }
 
-static TileGrid tile_grid(const tri_plan *p) { return TileGrid{(int32_t)p->m, p->flags, (uint64_t)p->T}; }
+static TileGrid tile_grid(const tri_plan *p)
+{
+    uint32_t f = p->flags;
+    if (p->map == TRI_MAP_LAMBDA && p->gy == 1 && (uint64_t)p->gx == (uint64_t)p->T &&
+        p->T <= (1ll << 24) && (f & ~(uint32_t)TRI_FLAG_XCD_SWIZZLE) == 0)
+        f |= kLambda24;
+    return TileGrid{(int32_t)p->m, f, (uint64_t)p->T};
+}
 
 // ---------------------------------------------------------------------------
 // map dump / lambda evaluation kernels

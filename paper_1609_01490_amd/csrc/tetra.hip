@@ -78,6 +78,22 @@ __device__ __forceinline__ void lambda3_tile(uint64_t w, uint32_t flags, int32_t
     i = (int32_t)(w2 - (uint64_t)r * (r + 1) / 2);
 }
 
+// The same map for w < 2^24 (a 1-D grid, FP32 roots) in 32-bit arithmetic:
+// there k <= 470, so Tet(k + 1) and the layer's 2-D numbering fit in 32 bits.
+__device__ __forceinline__ uint32_t tet32(uint32_t k) { return k * (k + 1) / 2 * (k + 2) / 3; }
+
+__device__ __forceinline__ void lambda3_tile_24(uint32_t w, int32_t &i, int32_t &j, int32_t &k)
+{
+    const float x = 6.0f * (float)w;
+    const float u = x > 0.f ? __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(x) * (1.0f / 3.0f)) : 0.f;
+    int32_t kk = (int32_t)u - 1;
+    if (kk < 0) kk = 0;
+    while (kk > 0 && tet32((uint32_t)kk) > w) --kk;
+    while (tet32((uint32_t)kk + 1) <= w) ++kk;
+    k = kk;
+    lambda_tile_24(w - tet32((uint32_t)kk), j, i);
+}
+
 template <int MAP>
 __device__ __forceinline__ bool tet_of_block_raw(const TetGrid &g, int32_t &i, int32_t &j,
                                                  int32_t &k)
@@ -88,6 +104,10 @@ __device__ __forceinline__ bool tet_of_block_raw(const TetGrid &g, int32_t &i, i
         k = (int32_t)blockIdx.z;
         return i <= j && j <= k;
     } else {
+        if (g.flags & kLambda24) {  // 1-D grid of exactly T < 2^24 blocks
+            lambda3_tile_24(blockIdx.x, i, j, k);
+            return true;
+        }
         const uint64_t L = (uint64_t)blockIdx.y * gridDim.x + blockIdx.x;
         if (L >= g.T) return false;
         lambda3_tile(L, g.flags, i, j, k);
@@ -102,7 +122,14 @@ __device__ __forceinline__ bool tet_of_block(const TetGrid &g, int32_t &i, int32
     return (uint32_t)k < (uint32_t)g.m && (uint32_t)j <= (uint32_t)k && (uint32_t)i <= (uint32_t)j;
 }
 
-static TetGrid tet_grid(const tri_tet *p) { return TetGrid{(int32_t)p->m, p->flags, p->T}; }
+static TetGrid tet_grid(const tri_tet *p)
+{
+    uint32_t f = p->flags;
+    if (p->map == TRI_MAP_LAMBDA && f == 0 && p->gy == 1 && (uint64_t)p->gx == p->T &&
+        p->T <= (1ull << 24))
+        f |= kLambda24;
+    return TetGrid{(int32_t)p->m, f, p->T};
+}
 
 // ---------------------------------------------------------------------------
 // test hooks
@@ -160,10 +187,16 @@ __device__ __forceinline__ bool near3(f4 a, f4 b, float r2)
 // as bit masks (one wave ballot gives 64 / rho rows), so a pair (a, b) of
 // neighbours finds all its triangles with one AND and a population count:
 // rho^2 distance tests per relation instead of rho^3 per triple.
+template <int TILE>
+struct TriShape {
+    static constexpr int NT = TILE == 8 ? 64 : 256;  // one wave holds the 64 pairs of rho = 8
+};
+
 template <int MAP, int TILE>
-__global__ void __launch_bounds__(256) k_triangles(TriArgs p, int32_t strict)
+__global__ void __launch_bounds__((TriShape<TILE>::NT)) k_triangles(TriArgs p, int32_t strict)
 {
     static_assert(TILE == 8 || TILE == 16 || TILE == 32, "mask width");
+    constexpr int NT = TriShape<TILE>::NT;
     int32_t ti, tj, tk;
     if (!tet_of_block<MAP>(p.g, ti, tj, tk)) return;
 
@@ -184,7 +217,7 @@ __global__ void __launch_bounds__(256) k_triangles(TriArgs p, int32_t strict)
     constexpr int RPB = 64 / TILE;           // rows per ballot
     constexpr int BALLOTS = 3 * TILE / RPB;  // over the three relations
     const int w = t >> 6, l = t & 63;
-    for (int b = w; b < BALLOTS; b += 4) {
+    for (int b = w; b < BALLOTS; b += NT / 64) {
         const int s = b / (TILE / RPB);
         const int row = (b % (TILE / RPB)) * RPB + l / TILE;
         const int col = l % TILE;
@@ -199,9 +232,9 @@ __global__ void __launch_bounds__(256) k_triangles(TriArgs p, int32_t strict)
     }
     __syncthreads();
 
-    // pairs (a, b): TILE^2 of them, over the 256 threads
+    // pairs (a, b): TILE^2 of them, over the NT threads
     const bool same_kj = (tk == tj), same_ji = (tj == ti);
-    for (int q = t; q < TILE * TILE; q += 256) {
+    for (int q = t; q < TILE * TILE; q += NT) {
         const int ta = q / TILE, tb = q % TILE;
         // a > b: always across tiles, within one tile index iff ta >= tb
         // (a = tb + 2 + ..., b = tb + 1 + ... on the shifted tetrahedron)
@@ -236,9 +269,9 @@ static bool triangles_tile(const tri_tet *p, const TriArgs &a, hipStream_t s)
     const dim3 grid(p->gx, p->gy, p->gz);
     const int32_t st = p->strict;
     switch (p->tile) {
-    case 8: k_triangles<MAP, 8><<<grid, 256, 0, s>>>(a, st); return true;
-    case 16: k_triangles<MAP, 16><<<grid, 256, 0, s>>>(a, st); return true;
-    case 32: k_triangles<MAP, 32><<<grid, 256, 0, s>>>(a, st); return true;
+    case 8: k_triangles<MAP, 8><<<grid, TriShape<8>::NT, 0, s>>>(a, st); return true;
+    case 16: k_triangles<MAP, 16><<<grid, TriShape<16>::NT, 0, s>>>(a, st); return true;
+    case 32: k_triangles<MAP, 32><<<grid, TriShape<32>::NT, 0, s>>>(a, st); return true;
     }
     return false;
 }

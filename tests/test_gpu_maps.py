@@ -163,21 +163,26 @@ def test_lambda_epsilon_variants_study(base):
     assert wrong.size > 0
 
 
-@pytest.mark.parametrize("map_name", ["bb", "rb", "rec", "utm", "lambda"])
+@pytest.mark.parametrize("map_name,flags", [("bb", 0), ("rb", 0), ("rec", 0), ("utm", 0),
+                                            ("lambda", 0), ("lambda", 1), ("lambda", 2),
+                                            ("lambda", 64), ("lambda", 4), ("lambda", 128),
+                                            ("lambda", 130), ("lambda", 192), ("lambda", 16)])
 @pytest.mark.parametrize("tile", [8, 16, 32, 64])
-def test_dummy_kernel_reaches_every_sum(map_name, tile):
+def test_dummy_kernel_reaches_every_sum(map_name, flags, tile):
     """Cells of the domain reach exactly the sums i + j in 0..2n-2 (with the
-    diagonal) or 1..2n-3 (without); only a reached target is stored."""
+    diagonal) or 1..2n-3 (without); only a reached target is stored.  For
+    lambda every root of the square-root study, with the correction and in
+    the paper's epsilon form (exact at these sizes: below T_1000)."""
     import torch
     tm = _tm()
     for n, diag in ((1, True), (5, True), (100, True), (257, False), (300, True), (513, False)):
         m = -(-(n if diag else n - 1) // tile)
         if map_name == "rec" and m and (m & (m - 1)):
             continue
-        p = tm.Plan(n, tile, map_name, include_diag=diag)
+        p = tm.Plan(n, tile, map_name, include_diag=diag, flags=flags)
         lo, hi = (0, 2 * n - 2) if diag else (1, 2 * n - 3)
         for target in sorted({-1, 0, 1, lo, hi, hi + 1, n - 1, (lo + hi) // 2, 2 * n + 5}):
-            note("dummy", map_name, tile, n, diag, target)
+            note("dummy", map_name, flags, tile, n, diag, target)
             sink = torch.full((1,), -123, dtype=torch.int32, device="cuda")
             p.dummy(target, sink)
             exp = target if (lo <= target <= hi and n > (0 if diag else 1)) else -123

@@ -19,10 +19,12 @@ struct TileGrid {
     uint64_t T;      // tiles, m (m + 1) / 2
 };
 
-// Internal TileGrid flag: lambda launched as a 1-D grid of exactly T < 2^24
-// blocks with the default root and order (the swizzle allowed), so the map
-// can take its 32-bit path.
+// Internal TileGrid flags: lambda launched as a 1-D grid of exactly T < 2^24
+// blocks with the default root and order (the swizzle allowed), or as a
+// 2-D grid of 2^16-block rows over T < 2^32 blocks with no flags, so the map
+// can take a 32-bit path.
 constexpr uint32_t kLambda24 = 1u << 31;
+constexpr uint32_t kLambda32 = 1u << 30;
 
 // ---------------------------------------------------------------------------
 // lambda(omega), Eq. eq_gmap: row i = floor((sqrt(8 omega + 1) - 1) / 2),
@@ -116,6 +118,26 @@ __device__ __forceinline__ void lambda_tile_24(uint32_t w, int32_t &bi, int32_t 
     bj = (int32_t)(w - t);
 }
 
+// The same for w < 2^32: 8w + 1 is rounded twice to 24 bits and the root is
+// still within one row (rows stay below 2^16.5).  T_i < 2^32 is formed
+// from the even factor of i (i + 1) so that no product overflows, and the
+// upward step compares w - T_i with the row length.
+__device__ __forceinline__ void lambda_tile_32(uint32_t w, int32_t &bi, int32_t &bj)
+{
+    const float x = __builtin_fmaf(8.0f, (float)w, 1.0f);
+    uint32_t i = (uint32_t)((__builtin_amdgcn_sqrtf(x) - 1.0f) * 0.5f);
+    uint32_t t = (i & 1u) ? i * ((i + 1) >> 1) : (i >> 1) * (i + 1);
+    if (t > w) {
+        --i;
+        t -= i + 1;
+    } else if (w - t >= i + 1) {
+        t += i + 1;
+        ++i;
+    }
+    bi = (int32_t)i;
+    bj = (int32_t)(w - t);
+}
+
 // Give each of the 8 XCDs a contiguous range of omega.  Workgroups are
 // dispatched to XCDs round-robin by linear id; block L runs on XCD L mod 8.
 // With G = 8q + r blocks, XCD x holds q + (x < r) blocks, so its range starts
@@ -187,6 +209,13 @@ __device__ __forceinline__ bool tile_of_block_raw(const TileGrid &g, int32_t &bi
                 L = x * q + (x < r ? x : r) + l;
             }
             lambda_tile_24(L, bi, bj);
+            return true;
+        }
+        if (g.flags & kLambda32) {
+            // 2-D grid of 2^16-block rows, T < 2^32, default root and order
+            const uint32_t L = (blockIdx.y << 16) + blockIdx.x;
+            if (L >= (uint32_t)g.T) return false;
+            lambda_tile_32(L, bi, bj);
             return true;
         }
         uint64_t L = (uint64_t)blockIdx.y * gridDim.x + blockIdx.x;

@@ -56,6 +56,9 @@ static TileGrid tile_grid(const tri_plan *p)
     if (p->map == TRI_MAP_LAMBDA && p->gy == 1 && (uint64_t)p->gx == (uint64_t)p->T &&
         p->T <= (1ll << 24) && (f & ~(uint32_t)TRI_FLAG_XCD_SWIZZLE) == 0)
         f |= kLambda24;
+    else if (p->map == TRI_MAP_LAMBDA && p->gy > 1 && p->gx == (1u << 16) && f == 0 &&
+             p->T < (1ll << 32))
+        f |= kLambda32;
     return TileGrid{(int32_t)p->m, f, (uint64_t)p->T};
 }
 

@@ -187,3 +187,30 @@ def test_dummy_kernel_reaches_every_sum(map_name, flags, tile):
             p.dummy(target, sink)
             exp = target if (lo <= target <= hi and n > (0 if diag else 1)) else -123
             assert int(host(sink)[0]) == exp, (map_name, tile, n, diag, target)
+
+
+@pytest.mark.parametrize("n,tile,flags", [(65537, 8, 0), (65537, 8, 1), (50000, 8, 2)])
+def test_lambda_two_dimensional_grid_dump(n, tile, flags):
+    """More than 2^24 tiles: lambda is launched on a 2-D grid of 2^16-block
+    rows (32-bit map path without flags, the general path with them); every
+    block within T maps to lambda(L) and the surplus blocks are discarded."""
+    tm = _tm()
+    p = tm.Plan(n, tile, "lambda", flags=flags)
+    assert p.info.tiles > 2 ** 24 and p.info.grid_y > 1
+    note("lambda 2-D dump", n, tile, flags, p.info.tiles)
+    got = host(p.dump())
+    T = p.info.tiles
+    L = np.arange(T, dtype=np.int64)
+    if flags & tm.FLAG_XCD_SWIZZLE:
+        # the swizzle permutes the grid blocks: the kept tiles are all of them
+        kept = got[got[:, 0] >= 0]
+        assert kept.shape[0] == T
+        w = kept[:, 0] * (kept[:, 0] + 1) // 2 + kept[:, 1]
+        assert (np.sort(w) == L).all()
+        return
+    i, j = got[:T, 0], got[:T, 1]
+    assert ((j >= 0) & (j <= i)).all()
+    assert (i * (i + 1) // 2 + j == L).all()
+    assert (got[T:] == -1).all()
+    for s in np.random.default_rng(1).choice(T, 2000, replace=False):
+        assert oracle.lam(int(s)) == (int(i[s]), int(j[s]))

@@ -237,8 +237,9 @@ def bench_edm(tm, torch, timer):
     out = torch.empty((n * (n - 1) // 2,), dtype=torch.float32, device="cuda")
     pairs = n * (n - 1) // 2
     res = {}
-    p = tm.Plan(n, 64, "lambda", include_diag=False)
+    p = tm.Plan(n, 128, "lambda", include_diag=False)
     ms = timer.run(lambda: p.edm(xd, out, mode=tm.EDM_FP32), 3, 1)
+    res["fp32_tile"] = 128
     res["fp32_ms"] = round(ms, 4)
     res["fp32_pairs_per_s"] = round(pairs / (ms * 1e-3), 1)
     best, _ = tune_table(tm, tm.TUNE_EDM_BF16X3, n, d, reps=2)  # lambda with or without swizzle

@@ -226,7 +226,7 @@ tri_status tri_launch_stencil(const tri_plan *plan, uint8_t *cur, uint8_t *nxt, 
  * condensed strict lower triangle, n(n-1)/2 floats; n(n-1)/2 < 2^32).  x is
  * n x d FP32 (1 <= d <= 4096), leading dimension ldx >= d, 4-byte aligned.
  * mode is a TRI_EDM_* value:
- *  - TRI_EDM_FP32: plan tile 16, 32 or 64; no workspace (ws may be NULL).
+ *  - TRI_EDM_FP32: plan tile 16, 32, 64 or 128; no workspace (ws may be NULL).
  *  - TRI_EDM_BF16X3 / TRI_EDM_BF16: plan tile 128; `out` 16-byte aligned
  *    (rows are written as 16-byte vectors); ws a device buffer of at least
  *    tri_edm_workspace_size() bytes, 256-byte aligned, else TRI_E_NOMEM /

@@ -246,20 +246,50 @@ struct EdmF32Shape {
     static constexpr int NT = 256;
     static constexpr int TX = 16;                  // lanes along columns
     static constexpr int TY = NT / TX;             // lanes along rows
-    static constexpr int RB = TILE / TY;           // register rows per lane
-    static constexpr int CB = TILE / TX;           // register columns per lane
+    static constexpr int RB = TILE / TY;           // register rows per lane (contiguous)
+    static constexpr int CB = TILE / TX;           // register columns per lane (stride TX)
     static constexpr int K = TILE >= 64 ? 32 : 64;  // dimensions staged per step
-    static constexpr int LDS_FLOATS = 2 * K * (TILE + 1);
+    // row stride of the staged blocks: a multiple of 4 so that a lane's RB
+    // consecutive row values are one aligned vector read
+    static constexpr int LD = TILE + 4;
+    static constexpr int LDS_FLOATS = 2 * K * LD;
     static_assert(RB >= 1 && CB >= 1 && RB * TY == TILE && CB * TX == TILE, "edm tile");
+    static_assert(RB == 1 || RB == 2 || RB % 4 == 0, "row block");
 };
 
+// RB consecutive floats from LDS (16-byte aligned when RB >= 4).
+template <int RB>
+__device__ __forceinline__ void lds_read_rows(const float *src, float (&dst)[RB])
+{
+    if constexpr (RB % 4 == 0) {
+        typedef float f4v __attribute__((ext_vector_type(4)));
+#pragma unroll
+        for (int q = 0; q < RB / 4; ++q) {
+            const f4v v = *(const f4v *)(src + 4 * q);
+            dst[4 * q + 0] = v.x;
+            dst[4 * q + 1] = v.y;
+            dst[4 * q + 2] = v.z;
+            dst[4 * q + 3] = v.w;
+        }
+    } else {
+#pragma unroll
+        for (int a = 0; a < RB; ++a) dst[a] = src[a];
+    }
+}
+
+// Distances of one tile of the strict lower triangle: tile (bi, bj) covers
+// rows 1 + bi rho .. and columns bj rho ..; d(i, j) = sqrt(sum_k (x_ik -
+// x_jk)^2) with FP32 fused multiply-adds in k order, written to the
+// condensed out[i (i - 1) / 2 + j] for j < i < n.  Each lane holds an RB x CB
+// block: RB consecutive rows (one vector read from LDS per step) against CB
+// columns TX apart (so that the 16 lanes of a row store consecutive words).
 template <int TILE>
 __device__ __forceinline__ void edm_f32_tile_body(const EdmTile &p, int32_t bi, int32_t bj,
                                                   float *lds)
 {
     using S = EdmF32Shape<TILE>;
-    float *XI = lds;                       // [K][TILE + 1]
-    float *XJ = lds + S::K * (TILE + 1);   // [K][TILE + 1]
+    float *XI = lds;                  // [K][LD]
+    float *XJ = lds + S::K * S::LD;   // [K][LD]
     const int32_t n = p.n, d = p.d;
     const int64_t ldx = p.ldx;
     const int32_t ri0 = 1 + bi * TILE;  // first row of the tile
@@ -277,17 +307,16 @@ __device__ __forceinline__ void edm_f32_tile_body(const EdmTile &p, int32_t bi, 
             const int row = idx / S::K, kk = idx % S::K;
             const int32_t k = k0 + kk;
             const int32_t gi = ri0 + row, gj = cj0 + row;
-            XI[kk * (TILE + 1) + row] = (gi < n && k < d) ? p.x[(int64_t)gi * ldx + k] : 0.f;
-            XJ[kk * (TILE + 1) + row] = (gj < n && k < d) ? p.x[(int64_t)gj * ldx + k] : 0.f;
+            XI[kk * S::LD + row] = (gi < n && k < d) ? p.x[(int64_t)gi * ldx + k] : 0.f;
+            XJ[kk * S::LD + row] = (gj < n && k < d) ? p.x[(int64_t)gj * ldx + k] : 0.f;
         }
         __syncthreads();
-#pragma unroll 8
+#pragma unroll 4
         for (int kk = 0; kk < S::K; ++kk) {
             float xa[S::RB], xb[S::CB];
+            lds_read_rows<S::RB>(XI + kk * S::LD + ty * S::RB, xa);
 #pragma unroll
-            for (int a = 0; a < S::RB; ++a) xa[a] = XI[kk * (TILE + 1) + ty + S::TY * a];
-#pragma unroll
-            for (int c = 0; c < S::CB; ++c) xb[c] = XJ[kk * (TILE + 1) + tx + S::TX * c];
+            for (int c = 0; c < S::CB; ++c) xb[c] = XJ[kk * S::LD + tx + S::TX * c];
 #pragma unroll
             for (int a = 0; a < S::RB; ++a)
 #pragma unroll
@@ -301,7 +330,7 @@ __device__ __forceinline__ void edm_f32_tile_body(const EdmTile &p, int32_t bi, 
 
 #pragma unroll
     for (int a = 0; a < S::RB; ++a) {
-        const int32_t i = ri0 + ty + S::TY * a;
+        const int32_t i = ri0 + ty * S::RB + a;
         if (i >= n) continue;
         float *orow = p.out + (int64_t)i * (i - 1) / 2;
 #pragma unroll

@@ -42,7 +42,7 @@ __global__ void __launch_bounds__(256) k_edm_f32(EdmArgs p)
 {
     int32_t bi, bj;
     if (!tile_of_block<MAP>(p.g, bi, bj)) return;
-    __shared__ float lds[EdmF32Shape<TILE>::LDS_FLOATS];
+    __shared__ __attribute__((aligned(16))) float lds[EdmF32Shape<TILE>::LDS_FLOATS];
     edm_f32_tile_body<TILE>(p.t, bi, bj, lds);
 }
 
@@ -54,6 +54,7 @@ static bool edm_f32_tile(const tri_plan *p, const EdmArgs &a, hipStream_t s)
     case 16: k_edm_f32<MAP, 16><<<grid, 256, 0, s>>>(a); return true;
     case 32: k_edm_f32<MAP, 32><<<grid, 256, 0, s>>>(a); return true;
     case 64: k_edm_f32<MAP, 64><<<grid, 256, 0, s>>>(a); return true;
+    case 128: k_edm_f32<MAP, 128><<<grid, 256, 0, s>>>(a); return true;
     }
     return false;
 }
@@ -423,8 +424,8 @@ static tri_status edm_check(const tri_plan *p, int64_t d, int mode)
     if (p->map == TRI_MAP_UTM) return fail(TRI_E_UNSUPPORTED, "tri_edm: UTM is not supported");
     if (d < 1 || d > 4096) return fail(TRI_E_RANGE, "tri_edm: d = %lld not in [1, 4096]", (long long)d);
     if (mode == TRI_EDM_FP32) {
-        if (p->tile != 16 && p->tile != 32 && p->tile != 64)
-            return fail(TRI_E_UNSUPPORTED, "tri_edm: FP32 mode needs tile 16, 32 or 64");
+        if (p->tile != 16 && p->tile != 32 && p->tile != 64 && p->tile != 128)
+            return fail(TRI_E_UNSUPPORTED, "tri_edm: FP32 mode needs tile 16, 32, 64 or 128");
         return TRI_OK;
     }
     if (mode == TRI_EDM_BF16X3 || mode == TRI_EDM_BF16) {

@@ -41,7 +41,7 @@ def _check_rows(X, out_host, rows, tol, dup_rows=()):
 
 
 @pytest.mark.parametrize("map_name", ["bb", "rb", "rec", "lambda"])
-@pytest.mark.parametrize("tile", [16, 32, 64])
+@pytest.mark.parametrize("tile", [16, 32, 64, 128])
 def test_edm_fp32_small(map_name, tile):
     import torch
     tm = _tm()
@@ -60,13 +60,14 @@ def test_edm_fp32_small(map_name, tile):
 
 
 @pytest.mark.slow
-def test_edm_fp32_full_size_sampled_rows():
+@pytest.mark.parametrize("tile", [64, 128])
+def test_edm_fp32_full_size_sampled_rows(tile):
     import torch
     tm = _tm()
     n, d = 65536, 128
     X, pairs = inputs.points(n, d)
-    p = tm.Plan(n, 64, "lambda", include_diag=False)
-    note("edm fp32 full", n, d)
+    p = tm.Plan(n, tile, "lambda", include_diag=False)
+    note("edm fp32 full", n, d, tile)
     out = torch.empty((n * (n - 1) // 2,), dtype=torch.float32, device="cuda")
     p.edm(dev(X), out, mode=tm.EDM_FP32)
     torch.cuda.synchronize()

@@ -202,8 +202,10 @@ tri_status tri_triangles(const tri_tet *plan, const float *points, float r2, int
  * with a + b + c == target store it to sink[0] (device int32). */
 tri_status tri_tet_dummy(const tri_tet *plan, int32_t target, int32_t *sink, void *stream);
 
-/* Game of Life B3/S23 on the lower triangle (include_diag must be 1; UTM
- * is not supported: it has no 2-D block to stage a halo in).  cur and nxt
+/* Game of Life B3/S23 on the lower triangle (include_diag must be 1).  The
+ * tile maps stage each tile with a one-cell halo in LDS; UTM (thread space)
+ * has no 2-D block, so its threads read their eight neighbours from global
+ * memory (and it has no temporal blocking).  cur and nxt
  * are uint8 n x ld grids whose domain cells hold 0 or 1; cells above the
  * diagonal are treated as dead whatever they hold, and are never written.
  * Runs `steps` synchronous generations, reading cur and writing nxt, then
@@ -339,11 +341,11 @@ tri_status tri_batch_autotune(int32_t count, const int32_t *host_kind, const int
 /* ------------------------------------------------------------------------
  * Autotuner: tile size and map for a workload and problem size.
  *
- * tri_autotune times every candidate (tiles 8/16/32/64 — 16/32/64 for the
- * FP32 distance map, 128 for the MFMA one — times maps BB, RB, REC (when m is
- * a power of two) and lambda, the latter plain, with TRI_FLAG_XCD_SWIZZLE,
- * TRI_FLAG_ORDER_REVERSE, TRI_FLAG_ORDER_PAIRS and swizzle + pairs, plus UTM
- * for the elementwise bodies) on this GPU: one warm-up and `reps` timed calls
+ * tri_autotune times every candidate (tiles 8/16/32/64 — 16/32/64/128 for
+ * the FP32 distance map, 128 for the MFMA one — times maps BB, RB, REC (when
+ * m is a power of two) and lambda, the latter plain, with
+ * TRI_FLAG_XCD_SWIZZLE, TRI_FLAG_ORDER_REVERSE, TRI_FLAG_ORDER_PAIRS and
+ * swizzle + pairs, plus UTM for the elementwise bodies and Life) on this GPU: one warm-up and `reps` timed calls
  * with HIP events on `stream`, on zeroed scratch buffers of the problem's
  * size that it allocates and frees itself (so it is not for graph capture).
  * Life is timed over four generations (also with TRI_FLAG_LIFE_TEMPORAL

@@ -85,8 +85,8 @@ static std::vector<Candidate> candidates(int workload, int64_t n)
     switch (workload) {
     case TRI_TUNE_ELEMENTWISE_F32:
     case TRI_TUNE_ELEMENTWISE_I32: tiles = {8, 16, 32, 64}; utm = true; break;
-    case TRI_TUNE_LIFE: tiles = {8, 16, 32, 64}; break;
-    case TRI_TUNE_EDM_FP32: tiles = {16, 32, 64}; break;
+    case TRI_TUNE_LIFE: tiles = {8, 16, 32, 64}; utm = true; break;
+    case TRI_TUNE_EDM_FP32: tiles = {16, 32, 64, 128}; break;
     case TRI_TUNE_EDM_BF16X3: tiles = {128}; break;
     }
     std::vector<Candidate> c;

@@ -39,6 +39,31 @@ __global__ void __launch_bounds__(life_threads<TILE>()) k_life(LifeArgs p)
     life_tile_body<TILE, NT>(p.t, bi, bj, L);
 }
 
+// UTM (thread space): thread k owns the cell utm_cell(k) and reads its eight
+// neighbours straight from global memory; there is no tile to stage a halo
+// in, so this is the global-memory variant of the update.
+__global__ void __launch_bounds__(kUtmThreads) k_life_utm(LifeArgs p)
+{
+    const LifeTile &t = p.t;
+    const int64_t cells = (int64_t)t.n * (t.n + 1) / 2;
+    const uint64_t k = ((uint64_t)blockIdx.y * gridDim.x + blockIdx.x) * kUtmThreads + threadIdx.x;
+    if (k >= (uint64_t)cells) return;
+    int32_t i, j;
+    utm_cell(k, t.n, i, j);
+    if ((uint32_t)i >= (uint32_t)t.n || (uint32_t)j > (uint32_t)i) return;
+    int cnt = 0;
+#pragma unroll
+    for (int di = -1; di <= 1; ++di)
+#pragma unroll
+        for (int dj = -1; dj <= 1; ++dj) {
+            if (di == 0 && dj == 0) continue;
+            const int32_t r = i + di, c = j + dj;
+            if (r >= 0 && r < t.n && c >= 0 && c <= r) cnt += t.cur[(int64_t)r * t.ld + c];
+        }
+    const uint8_t alive = t.cur[(int64_t)i * t.ld + j];
+    t.nxt[(int64_t)i * t.ld + j] = (uint8_t)(cnt == 3 || (alive && cnt == 2));
+}
+
 template <int MAP>
 static bool life_tile(const tri_plan *p, const LifeArgs &a, hipStream_t s)
 {
@@ -126,6 +151,7 @@ static bool life_kernel_tile(int tile, const void *&fn, int &threads)
 static bool life_kernel(const tri_plan *p, const void *&fn, int &threads)
 {
     switch (p->map) {
+    case TRI_MAP_UTM: fn = (const void *)k_life_utm; threads = kUtmThreads; return true;
     case TRI_MAP_BB: return life_kernel_tile<MAP_BB>(p->tile, fn, threads);
     case TRI_MAP_RB: return life_kernel_tile<MAP_RB>(p->tile, fn, threads);
     case TRI_MAP_REC: return life_kernel_tile<MAP_REC>(p->tile, fn, threads);
@@ -137,6 +163,9 @@ static bool life_kernel(const tri_plan *p, const void *&fn, int &threads)
 static bool life_step(const tri_plan *p, const LifeArgs &a, hipStream_t s)
 {
     switch (p->map) {
+    case TRI_MAP_UTM:
+        k_life_utm<<<dim3(p->gx, p->gy), kUtmThreads, 0, s>>>(a);
+        return true;
     case TRI_MAP_BB: return life_tile<MAP_BB>(p, a, s);
     case TRI_MAP_RB: return life_tile<MAP_RB>(p, a, s);
     case TRI_MAP_REC: return life_tile<MAP_REC>(p, a, s);
@@ -216,9 +245,10 @@ extern "C" tri_status tri_launch_stencil(const tri_plan *p, uint8_t *cur, uint8_
     clear_error();
     if (!p) return fail(TRI_E_INVAL, "tri_launch_stencil: plan is NULL");
     if (!p->diag) return fail(TRI_E_UNSUPPORTED, "tri_launch_stencil: needs include_diag = 1");
-    if (p->map == TRI_MAP_UTM)
-        return fail(TRI_E_UNSUPPORTED, "tri_launch_stencil: UTM has no tile to stage a halo in");
-    if (p->tile > 64) return fail(TRI_E_UNSUPPORTED, "tri_launch_stencil: tile %d > 64", p->tile);
+    if (p->map != TRI_MAP_UTM && p->tile > 64)
+        return fail(TRI_E_UNSUPPORTED, "tri_launch_stencil: tile %d > 64", p->tile);
+    if (p->map == TRI_MAP_UTM && (p->flags & TRI_FLAG_LIFE_TEMPORAL))
+        return fail(TRI_E_UNSUPPORTED, "tri_launch_stencil: UTM has no tile for temporal blocking");
     if (steps < 0) return fail(TRI_E_INVAL, "tri_launch_stencil: steps < 0");
     if (p->n == 0 || steps == 0) return TRI_OK;
     if (!cur || !nxt || cur == nxt) return fail(TRI_E_INVAL, "tri_launch_stencil: bad buffers");

@@ -11,7 +11,7 @@ from paper_1609_01490_amd import inputs
 
 pytestmark = pytest.mark.gpu
 
-MAPS = ["bb", "rb", "rec", "lambda"]
+MAPS = ["bb", "rb", "rec", "lambda", "utm"]
 
 
 def _tm():
@@ -96,8 +96,8 @@ def test_life_errors():
     tm = _tm()
     x = torch.zeros((64, 64), dtype=torch.uint8, device="cuda")
     y = torch.zeros((64, 64), dtype=torch.uint8, device="cuda")
-    with pytest.raises(tm.TrimapError):
-        tm.Plan(64, 16, "utm").stencil(x, y, 1)
+    with pytest.raises(tm.TrimapError):  # UTM has no tile for temporal blocking
+        tm.Plan(64, 16, "utm", flags=tm.FLAG_LIFE_TEMPORAL).stencil(x, y, 1)
     with pytest.raises(tm.TrimapError):
         tm.Plan(64, 16, "lambda").stencil(x, y, 1, ld=63)
     with pytest.raises(tm.TrimapError):
@@ -105,7 +105,7 @@ def test_life_errors():
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("map_name,tile", [("lambda", 32), ("bb", 32)])
+@pytest.mark.parametrize("map_name,tile", [("lambda", 32), ("bb", 32), ("utm", 16)])
 def test_life_full_size_windows(map_name, tile):
     """n = 16384, density 0.3, 100 steps.  The oracle recomputes 64 x 64 cell
     blocks from their light cones (the initial state within 100 cells):
@@ -137,7 +137,8 @@ def test_life_full_size_windows(map_name, tile):
     torch.cuda.empty_cache()
 
 
-def test_life_graph_mode_matches_eager_and_replays():
+@pytest.mark.parametrize("map_name", ["lambda", "utm"])
+def test_life_graph_mode_matches_eager_and_replays(map_name):
     """use_graph builds the generations into a hipGraph once per (buffers,
     steps) and replays it; every replay, with eager work in between, equals
     the eager launches and the oracle."""
@@ -146,7 +147,7 @@ def test_life_graph_mode_matches_eager_and_replays():
     n, steps = 200, 6
     ld = padded_ld(n)
     g = inputs.life(n, 0.3, seed=5, ld=ld)
-    p = tm.Plan(n, 32, "lambda")
+    p = tm.Plan(n, 32, map_name)
     eager = _run(tm, p, g, steps)
     cur, nxt = dev(g), torch.zeros((n, ld), dtype=torch.uint8, device="cuda")
     state = g.copy()

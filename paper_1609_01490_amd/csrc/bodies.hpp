@@ -153,11 +153,285 @@ __device__ __forceinline__ uint32_t life_window_mask(int32_t gi, int32_t gj, int
     return life_domain_mask(gi, gj);
 }
 
+// ---------------------------------------------------------------------------
+// Bit-sliced variant for 64 x 64 tiles: one bit per cell, 32 cells per word.
+// The staged window (rows i0-4 .. i0+67, cells j0-4 .. j0+67) is kept as four
+// words per row covering cells j0-32 .. j0+95: word 0 holds the left halo in
+// its top four bits, words 1 and 2 the tile's 64 cells, word 3 the right halo
+// in its low four bits.  Bytes are packed with one wave ballot per 64 cells
+// and unpacked one cell per lane.  Per generation a word's eight neighbour
+// planes are summed with bitwise adders: the row above and the row below as
+// 2-bit horizontal sums (west, self, east), the own row without the cell;
+// with s = their total, a cell lives next iff (s >> 1) == 1 and (s & 1 or it
+// lives now), i.e. s = 3, or s = 2 and alive (B3/S23).  Cells outside the
+// staged window are not loaded; like cells beyond the byte-sliced window
+// they only reach the tile after more than four generations.
+// ---------------------------------------------------------------------------
+struct LifeBitsShape {
+    static constexpr int TILE = 64;
+    static constexpr int K = kLifeMaxGen;    // halo rows and cells
+    static constexpr int R = TILE + 2 * K;   // staged rows
+    static constexpr int PR = R + 2;         // plus a zero row above and below
+    static constexpr int WPR = 4;            // words per row
+    static constexpr int WORDS = PR * WPR;   // one buffer; the body uses two
+};
+
+// bits b of word c (cells jb + b, jb = j0 - 32 + 32 c) of staged row gi that
+// lie in the domain 0 <= j <= gi < n
+__device__ __forceinline__ uint32_t life_bits_mask(int32_t gi, int32_t jb, int32_t n)
+{
+    if (gi < 0 || gi >= n) return 0u;
+    const int32_t lo = jb < 0 ? -jb : 0;        // first bit with j >= 0
+    const int32_t hi = gi - jb;                 // last bit with j <= gi
+    if (hi < lo || lo > 31) return 0u;
+    const uint32_t upto = hi >= 31 ? 0xFFFFFFFFu : ((2u << hi) - 1u);
+    return upto & (0xFFFFFFFFu << lo);
+}
+
+// lds: at least 2 * LifeBitsShape::WORDS words; 256 threads; 1 <= gens <= 4
+__device__ __forceinline__ void life_bits_tile_body(const LifeTile &p, int32_t bi, int32_t bj,
+                                                    int gens, uint32_t *lds)
+{
+    using S = LifeBitsShape;
+    constexpr int T = S::TILE, K = S::K;
+    uint32_t *A = lds, *B = lds + S::WORDS;
+    const int32_t n = p.n;
+    const int64_t ld = p.ld;
+    const int32_t i0 = bi * T, j0 = bj * T;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+
+    // zero border rows of both buffers (the generations never write them)
+    if (threadIdx.x < S::WPR) {
+        A[threadIdx.x] = A[(S::PR - 1) * S::WPR + threadIdx.x] = 0u;
+        B[threadIdx.x] = B[(S::PR - 1) * S::WPR + threadIdx.x] = 0u;
+    }
+    // pack: wave w stages rows w, w + 4, ... (RPW of them).  Every load is
+    // unconditional, from a clamped in-domain address, and masked afterwards,
+    // and all are issued before the first ballot waits for one.  The 64
+    // cells of a row: one byte per lane.  The halo cells (4 left, 4 right):
+    // lane l covers row l / 8 of a group of eight rows, cell l % 8.
+    constexpr int RPW = S::R / 4;
+    constexpr int HG = (RPW + 7) / 8;  // halo groups of eight rows
+    static_assert(RPW * 4 == S::R, "rows per wave");
+    uint32_t cell[RPW], halo[HG];
+    const int32_t gj = j0 + lane;
+#pragma unroll
+    for (int k = 0; k < RPW; ++k) {
+        const int32_t gi = i0 - K + wave + 4 * k;
+        const int32_t gic = gi < 0 ? 0 : (gi >= n ? n - 1 : gi);
+        const uint32_t v = p.cur[(int64_t)gic * ld + (gj < gic ? gj : gic)];
+        cell[k] = (gi >= 0 && gi < n && gj <= gi) ? v : 0u;
+    }
+    const int hh = lane & 7;
+    const int32_t hj = hh < 4 ? j0 - 4 + hh : j0 + T + (hh - 4);
+#pragma unroll
+    for (int q = 0; q < HG; ++q) {
+        const int kr = 8 * q + (lane >> 3);  // row of the wave's rows
+        const int32_t gi = i0 - K + wave + 4 * kr;
+        const int32_t gic = gi < 0 ? 0 : (gi >= n ? n - 1 : gi);
+        const int32_t hjc = hj < 0 ? 0 : (hj < gic ? hj : gic);
+        const uint32_t v = p.cur[(int64_t)gic * ld + hjc];
+        halo[q] = (kr < RPW && gi >= 0 && gi < n && hj >= 0 && hj <= gi) ? v : 0u;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    uint64_t hb[HG];
+#pragma unroll
+    for (int q = 0; q < HG; ++q) hb[q] = __ballot(halo[q] != 0u);
+#pragma unroll
+    for (int k = 0; k < RPW; ++k) {
+        const uint64_t c64 = __ballot(cell[k] != 0u);
+        const uint32_t h8 = (uint32_t)(hb[k >> 3] >> (8 * (k & 7))) & 0xFFu;
+        if (lane == 0) {
+            uint32_t *row = A + (wave + 4 * k + 1) * S::WPR;
+            row[0] = (h8 & 0xFu) << 28;
+            row[1] = (uint32_t)c64;
+            row[2] = (uint32_t)(c64 >> 32);
+            row[3] = h8 >> 4;
+        }
+    }
+    // this thread's words: column c, rows r0 and (if any) r0 + 64
+    const int c = threadIdx.x & 3;
+    const int r0 = threadIdx.x >> 2;
+    const int nr = r0 + 64 < S::R ? 2 : 1;
+    uint32_t msk[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) msk[q] = life_bits_mask(i0 - K + r0 + 64 * q, j0 - 32 + 32 * c, n);
+    __syncthreads();
+
+    for (int g = 0; g < gens; ++g) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            if (q >= nr) break;
+            const int r = r0 + 64 * q;
+            const uint32_t *up = A + r * S::WPR, *md = up + S::WPR, *dn = md + S::WPR;
+            const uint32_t uw = c > 0 ? up[c - 1] : 0u, uc = up[c], ue = c < 3 ? up[c + 1] : 0u;
+            const uint32_t mw = c > 0 ? md[c - 1] : 0u, mc = md[c], me = c < 3 ? md[c + 1] : 0u;
+            const uint32_t dw = c > 0 ? dn[c - 1] : 0u, dc = dn[c], de = c < 3 ? dn[c + 1] : 0u;
+            // west neighbour planes (cell j - 1 moved to bit j) and east ones
+            const uint32_t uW = __builtin_amdgcn_alignbit(uc, uw, 31), uE = __builtin_amdgcn_alignbit(ue, uc, 1);
+            const uint32_t mW = __builtin_amdgcn_alignbit(mc, mw, 31), mE = __builtin_amdgcn_alignbit(me, mc, 1);
+            const uint32_t dW = __builtin_amdgcn_alignbit(dc, dw, 31), dE = __builtin_amdgcn_alignbit(de, dc, 1);
+            // 2-bit sums: above and below of three cells, own row of two
+            const uint32_t u0 = uW ^ uc ^ uE, u1 = (uW & uc) | (uE & (uW ^ uc));
+            const uint32_t d0 = dW ^ dc ^ dE, d1 = (dW & dc) | (dE & (dW ^ dc));
+            const uint32_t m0 = mW ^ mE, m1 = mW & mE;
+            // total s = (u0 + d0 + m0) + 2 (u1 + d1 + m1)
+            const uint32_t t0 = u0 ^ d0 ^ m0;
+            const uint32_t c0 = (u0 & d0) | (m0 & (u0 ^ d0));
+            const uint32_t x1 = u1 ^ d1 ^ m1 ^ c0;                     // bit 1 of s
+            const uint32_t h2 = ((u1 & d1) | (m1 & (u1 ^ d1))) |       // s >= 4
+                                (c0 & (u1 | d1 | m1));
+            B[(r + 1) * S::WPR + c] = x1 & ~h2 & (t0 | mc) & msk[q];
+        }
+        __syncthreads();
+        uint32_t *t = A;
+        A = B;
+        B = t;
+    }
+
+    // unpack the tile: rows K .. K + 63 of the window, words 1 and 2
+    for (int tr = wave; tr < T; tr += 4) {
+        const int32_t gi = i0 + tr;
+        if (gi >= n) break;
+        const int32_t gj = j0 + lane;
+        if (gj > gi) continue;
+        const uint32_t wv = A[(K + tr + 1) * S::WPR + 1 + (lane >> 5)];
+        p.nxt[(int64_t)gi * ld + gj] = (uint8_t)((wv >> (lane & 31)) & 1u);
+    }
+}
+
+// The same update run by one wave per tile (64 threads): no workgroup
+// barriers, and four times as many tiles in flight per CU as with 256
+// threads, which is what the load-then-compute pattern needs to keep HBM
+// busy.  lds: at least 2 * LifeBitsShape::WORDS words.
+__device__ __forceinline__ void life_bits_wave_body(const LifeTile &p, int32_t bi, int32_t bj,
+                                                    int gens, uint32_t *lds)
+{
+    using S = LifeBitsShape;
+    constexpr int T = S::TILE, K = S::K;
+    constexpr int NWORD = S::R * S::WPR;       // 288 words per generation
+    constexpr int WPL = (NWORD + 63) / 64;     // words per lane
+    constexpr int CH = 18;                     // rows per load batch
+    constexpr int HG = S::R / 8;               // halo groups of eight rows
+    static_assert(S::R % CH == 0 && S::R % 8 == 0, "row batches");
+    uint32_t *A = lds, *B = lds + S::WORDS;
+    const int32_t n = p.n;
+    const int64_t ld = p.ld;
+    const int32_t i0 = bi * T, j0 = bj * T;
+    const int lane = threadIdx.x;
+
+    if (lane < S::WPR) {
+        A[lane] = A[(S::PR - 1) * S::WPR + lane] = 0u;
+        B[lane] = B[(S::PR - 1) * S::WPR + lane] = 0u;
+    }
+    // halo cells of all rows: lane covers row 8 q + lane / 8, cell lane % 8
+    uint64_t hb[HG];
+    {
+        const int hh = lane & 7;
+        const int32_t hj = hh < 4 ? j0 - 4 + hh : j0 + T + (hh - 4);
+        // raw values and their conditions kept apart until every load is
+        // issued (a value masked at once makes its load wait at once)
+        uint32_t hv[HG];
+        bool hok[HG];
+#pragma unroll
+        for (int q = 0; q < HG; ++q) {
+            const int32_t gi = i0 - K + 8 * q + (lane >> 3);
+            const int32_t gic = gi < 0 ? 0 : (gi >= n ? n - 1 : gi);
+            const int32_t hjc = hj < 0 ? 0 : (hj < gic ? hj : gic);
+            hv[q] = p.cur[(int64_t)gic * ld + hjc];
+            hok[q] = gi >= 0 && gi < n && hj >= 0 && hj <= gi;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int q = 0; q < HG; ++q) hb[q] = __ballot(hok[q] && hv[q] != 0u);
+    }
+    // the 64 cells of each row, CH rows per batch of loads
+    const int32_t gj = j0 + lane;
+#pragma unroll
+    for (int b0 = 0; b0 < S::R; b0 += CH) {
+        uint32_t cv[CH];
+        bool cok[CH];
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            const int32_t gi = i0 - K + b0 + k;
+            const int32_t gic = gi < 0 ? 0 : (gi >= n ? n - 1 : gi);
+            cv[k] = p.cur[(int64_t)gic * ld + (gj < gic ? gj : gic)];
+            cok[k] = gi >= 0 && gi < n && gj <= gi;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            const int r = b0 + k;
+            const uint64_t c64 = __ballot(cok[k] && cv[k] != 0u);
+            const uint32_t h8 = (uint32_t)(hb[r >> 3] >> (8 * (r & 7))) & 0xFFu;
+            if (lane == 0) {
+                uint32_t *row = A + (r + 1) * S::WPR;
+                row[0] = (h8 & 0xFu) << 28;
+                row[1] = (uint32_t)c64;
+                row[2] = (uint32_t)(c64 >> 32);
+                row[3] = h8 >> 4;
+            }
+        }
+    }
+    uint32_t msk[WPL];
+#pragma unroll
+    for (int k = 0; k < WPL; ++k) {
+        const int w = lane + 64 * k;
+        msk[k] = w < NWORD ? life_bits_mask(i0 - K + (w >> 2), j0 - 32 + 32 * (w & 3), n) : 0u;
+    }
+    // LDS operations of one wave complete in order; the wait and the
+    // barrier keep the compiler from moving reads of other lanes' words
+    // above the writes they depend on
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+    __builtin_amdgcn_wave_barrier();
+
+    for (int g = 0; g < gens; ++g) {
+#pragma unroll
+        for (int k = 0; k < WPL; ++k) {
+            const int w = lane + 64 * k;
+            if (w >= NWORD) break;
+            const int r = w >> 2, c = w & 3;
+            const uint32_t *up = A + r * S::WPR, *md = up + S::WPR, *dn = md + S::WPR;
+            const uint32_t uw = c > 0 ? up[c - 1] : 0u, uc = up[c], ue = c < 3 ? up[c + 1] : 0u;
+            const uint32_t mw = c > 0 ? md[c - 1] : 0u, mc = md[c], me = c < 3 ? md[c + 1] : 0u;
+            const uint32_t dw = c > 0 ? dn[c - 1] : 0u, dc = dn[c], de = c < 3 ? dn[c + 1] : 0u;
+            const uint32_t uW = __builtin_amdgcn_alignbit(uc, uw, 31), uE = __builtin_amdgcn_alignbit(ue, uc, 1);
+            const uint32_t mW = __builtin_amdgcn_alignbit(mc, mw, 31), mE = __builtin_amdgcn_alignbit(me, mc, 1);
+            const uint32_t dW = __builtin_amdgcn_alignbit(dc, dw, 31), dE = __builtin_amdgcn_alignbit(de, dc, 1);
+            const uint32_t u0 = uW ^ uc ^ uE, u1 = (uW & uc) | (uE & (uW ^ uc));
+            const uint32_t d0 = dW ^ dc ^ dE, d1 = (dW & dc) | (dE & (dW ^ dc));
+            const uint32_t m0 = mW ^ mE, m1 = mW & mE;
+            const uint32_t t0 = u0 ^ d0 ^ m0;
+            const uint32_t c0 = (u0 & d0) | (m0 & (u0 ^ d0));
+            const uint32_t x1 = u1 ^ d1 ^ m1 ^ c0;
+            const uint32_t h2 = ((u1 & d1) | (m1 & (u1 ^ d1))) | (c0 & (u1 | d1 | m1));
+            B[(r + 1) * S::WPR + c] = x1 & ~h2 & (t0 | mc) & msk[k];
+        }
+        __builtin_amdgcn_s_waitcnt(0xc07f);
+        __builtin_amdgcn_wave_barrier();
+        uint32_t *t = A;
+        A = B;
+        B = t;
+    }
+
+    for (int tr = 0; tr < T; ++tr) {
+        const int32_t gi = i0 + tr;
+        if (gi >= n) break;
+        const uint32_t wv = A[(K + tr + 1) * S::WPR + 1 + (lane >> 5)];
+        if (gj <= gi) p.nxt[(int64_t)gi * ld + gj] = (uint8_t)((wv >> (lane & 31)) & 1u);
+    }
+}
+
 // lds: 2 * LifeMultiShape<TILE>::WORDS words; 256 threads; 1 <= gens <= 4
 template <int TILE>
 __device__ __forceinline__ void life_multi_tile_body(const LifeTile &p, int32_t bi, int32_t bj,
                                                      int gens, uint32_t *lds)
 {
+    if constexpr (TILE == 64) {
+        static_assert(2 * LifeBitsShape::WORDS <= 2 * LifeMultiShape<64>::WORDS, "lds");
+        life_bits_tile_body(p, bi, bj, gens, lds);
+        return;
+    }
     using S = LifeMultiShape<TILE>;
     uint32_t *buf0 = lds, *buf1 = lds + S::WORDS;
     const int32_t n = p.n;

@@ -86,13 +86,23 @@ __global__ void __launch_bounds__(256) k_life_multi(LifeArgs p, int gens)
     life_multi_tile_body<TILE>(p.t, bi, bj, gens, buf);
 }
 
+// 64 x 64 tiles, bit-sliced, one wave per tile
+template <int MAP>
+__global__ void __launch_bounds__(64) k_life_bits(LifeArgs p, int gens)
+{
+    int32_t bi, bj;
+    if (!tile_of_block<MAP>(p.g, bi, bj)) return;
+    __shared__ uint32_t buf[2 * LifeBitsShape::WORDS];
+    life_bits_wave_body(p.t, bi, bj, gens, buf);
+}
+
 template <int MAP>
 static bool life_multi_kernel_tile(int tile, const void *&fn)
 {
     switch (tile) {
     case 16: fn = (const void *)k_life_multi<MAP, 16>; return true;
     case 32: fn = (const void *)k_life_multi<MAP, 32>; return true;
-    case 64: fn = (const void *)k_life_multi<MAP, 64>; return true;
+    case 64: fn = (const void *)k_life_bits<MAP>; return true;
     }
     return false;
 }
@@ -130,7 +140,7 @@ bool launch_life_multi_lambda(int tile, const TileGrid &g, const LifeTile &t, in
     switch (tile) {
     case 16: k_life_multi<MAP_LAMBDA, 16><<<grid, 256, 0, s>>>(a, gens); return true;
     case 32: k_life_multi<MAP_LAMBDA, 32><<<grid, 256, 0, s>>>(a, gens); return true;
-    case 64: k_life_multi<MAP_LAMBDA, 64><<<grid, 256, 0, s>>>(a, gens); return true;
+    case 64: k_life_bits<MAP_LAMBDA><<<grid, 64, 0, s>>>(a, gens); return true;
     }
     return false;
 }
@@ -269,7 +279,8 @@ extern "C" tri_status tri_launch_stencil(const tri_plan *p, uint8_t *cur, uint8_
             a.t.nxt = (k & 1) ? cur : nxt;
             int gens = sched[k];
             void *args[] = {&a, &gens};
-            TRI_HIP(hipLaunchKernel(fn, dim3(p->gx, p->gy), dim3(256), args, 0, s));
+            TRI_HIP(hipLaunchKernel(fn, dim3(p->gx, p->gy), dim3(p->tile == 64 ? 64 : 256), args,
+                                    0, s));
         }
         return TRI_OK;
     }

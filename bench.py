@@ -242,8 +242,9 @@ def bench_edm(tm, torch, timer):
     res["fp32_tile"] = 128
     res["fp32_ms"] = round(ms, 4)
     res["fp32_pairs_per_s"] = round(pairs / (ms * 1e-3), 1)
-    best, _ = tune_table(tm, tm.TUNE_EDM_BF16X3, n, d, reps=2)  # lambda with or without swizzle
-    q = tm.Plan(n, 128, best["map"], include_diag=False, flags=best["flags"])
+    _, table = tune_table(tm, tm.TUNE_EDM_BF16X3, n, d, reps=2)
+    best = best_of(table, "lambda")  # the lambda variant (swizzle, order) the autotuner finds fastest
+    q = tm.Plan(n, 128, "lambda", include_diag=False, flags=best["flags"])
     res["mfma_map"] = best["map"]
     res["mfma_flags"] = best["flags"]
     for mode, name in ((tm.EDM_BF16X3, "bf16x3"), (tm.EDM_BF16, "bf16")):

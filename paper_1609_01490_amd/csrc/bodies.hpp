@@ -188,122 +188,11 @@ __device__ __forceinline__ uint32_t life_bits_mask(int32_t gi, int32_t jb, int32
     return upto & (0xFFFFFFFFu << lo);
 }
 
-// lds: at least 2 * LifeBitsShape::WORDS words; 256 threads; 1 <= gens <= 4
-__device__ __forceinline__ void life_bits_tile_body(const LifeTile &p, int32_t bi, int32_t bj,
-                                                    int gens, uint32_t *lds)
-{
-    using S = LifeBitsShape;
-    constexpr int T = S::TILE, K = S::K;
-    uint32_t *A = lds, *B = lds + S::WORDS;
-    const int32_t n = p.n;
-    const int64_t ld = p.ld;
-    const int32_t i0 = bi * T, j0 = bj * T;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-
-    // zero border rows of both buffers (the generations never write them)
-    if (threadIdx.x < S::WPR) {
-        A[threadIdx.x] = A[(S::PR - 1) * S::WPR + threadIdx.x] = 0u;
-        B[threadIdx.x] = B[(S::PR - 1) * S::WPR + threadIdx.x] = 0u;
-    }
-    // pack: wave w stages rows w, w + 4, ... (RPW of them).  Every load is
-    // unconditional, from a clamped in-domain address, and masked afterwards,
-    // and all are issued before the first ballot waits for one.  The 64
-    // cells of a row: one byte per lane.  The halo cells (4 left, 4 right):
-    // lane l covers row l / 8 of a group of eight rows, cell l % 8.
-    constexpr int RPW = S::R / 4;
-    constexpr int HG = (RPW + 7) / 8;  // halo groups of eight rows
-    static_assert(RPW * 4 == S::R, "rows per wave");
-    uint32_t cell[RPW], halo[HG];
-    const int32_t gj = j0 + lane;
-#pragma unroll
-    for (int k = 0; k < RPW; ++k) {
-        const int32_t gi = i0 - K + wave + 4 * k;
-        const int32_t gic = gi < 0 ? 0 : (gi >= n ? n - 1 : gi);
-        const uint32_t v = p.cur[(int64_t)gic * ld + (gj < gic ? gj : gic)];
-        cell[k] = (gi >= 0 && gi < n && gj <= gi) ? v : 0u;
-    }
-    const int hh = lane & 7;
-    const int32_t hj = hh < 4 ? j0 - 4 + hh : j0 + T + (hh - 4);
-#pragma unroll
-    for (int q = 0; q < HG; ++q) {
-        const int kr = 8 * q + (lane >> 3);  // row of the wave's rows
-        const int32_t gi = i0 - K + wave + 4 * kr;
-        const int32_t gic = gi < 0 ? 0 : (gi >= n ? n - 1 : gi);
-        const int32_t hjc = hj < 0 ? 0 : (hj < gic ? hj : gic);
-        const uint32_t v = p.cur[(int64_t)gic * ld + hjc];
-        halo[q] = (kr < RPW && gi >= 0 && gi < n && hj >= 0 && hj <= gi) ? v : 0u;
-    }
-    __builtin_amdgcn_sched_barrier(0);
-    uint64_t hb[HG];
-#pragma unroll
-    for (int q = 0; q < HG; ++q) hb[q] = __ballot(halo[q] != 0u);
-#pragma unroll
-    for (int k = 0; k < RPW; ++k) {
-        const uint64_t c64 = __ballot(cell[k] != 0u);
-        const uint32_t h8 = (uint32_t)(hb[k >> 3] >> (8 * (k & 7))) & 0xFFu;
-        if (lane == 0) {
-            uint32_t *row = A + (wave + 4 * k + 1) * S::WPR;
-            row[0] = (h8 & 0xFu) << 28;
-            row[1] = (uint32_t)c64;
-            row[2] = (uint32_t)(c64 >> 32);
-            row[3] = h8 >> 4;
-        }
-    }
-    // this thread's words: column c, rows r0 and (if any) r0 + 64
-    const int c = threadIdx.x & 3;
-    const int r0 = threadIdx.x >> 2;
-    const int nr = r0 + 64 < S::R ? 2 : 1;
-    uint32_t msk[2];
-#pragma unroll
-    for (int q = 0; q < 2; ++q) msk[q] = life_bits_mask(i0 - K + r0 + 64 * q, j0 - 32 + 32 * c, n);
-    __syncthreads();
-
-    for (int g = 0; g < gens; ++g) {
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            if (q >= nr) break;
-            const int r = r0 + 64 * q;
-            const uint32_t *up = A + r * S::WPR, *md = up + S::WPR, *dn = md + S::WPR;
-            const uint32_t uw = c > 0 ? up[c - 1] : 0u, uc = up[c], ue = c < 3 ? up[c + 1] : 0u;
-            const uint32_t mw = c > 0 ? md[c - 1] : 0u, mc = md[c], me = c < 3 ? md[c + 1] : 0u;
-            const uint32_t dw = c > 0 ? dn[c - 1] : 0u, dc = dn[c], de = c < 3 ? dn[c + 1] : 0u;
-            // west neighbour planes (cell j - 1 moved to bit j) and east ones
-            const uint32_t uW = __builtin_amdgcn_alignbit(uc, uw, 31), uE = __builtin_amdgcn_alignbit(ue, uc, 1);
-            const uint32_t mW = __builtin_amdgcn_alignbit(mc, mw, 31), mE = __builtin_amdgcn_alignbit(me, mc, 1);
-            const uint32_t dW = __builtin_amdgcn_alignbit(dc, dw, 31), dE = __builtin_amdgcn_alignbit(de, dc, 1);
-            // 2-bit sums: above and below of three cells, own row of two
-            const uint32_t u0 = uW ^ uc ^ uE, u1 = (uW & uc) | (uE & (uW ^ uc));
-            const uint32_t d0 = dW ^ dc ^ dE, d1 = (dW & dc) | (dE & (dW ^ dc));
-            const uint32_t m0 = mW ^ mE, m1 = mW & mE;
-            // total s = (u0 + d0 + m0) + 2 (u1 + d1 + m1)
-            const uint32_t t0 = u0 ^ d0 ^ m0;
-            const uint32_t c0 = (u0 & d0) | (m0 & (u0 ^ d0));
-            const uint32_t x1 = u1 ^ d1 ^ m1 ^ c0;                     // bit 1 of s
-            const uint32_t h2 = ((u1 & d1) | (m1 & (u1 ^ d1))) |       // s >= 4
-                                (c0 & (u1 | d1 | m1));
-            B[(r + 1) * S::WPR + c] = x1 & ~h2 & (t0 | mc) & msk[q];
-        }
-        __syncthreads();
-        uint32_t *t = A;
-        A = B;
-        B = t;
-    }
-
-    // unpack the tile: rows K .. K + 63 of the window, words 1 and 2
-    for (int tr = wave; tr < T; tr += 4) {
-        const int32_t gi = i0 + tr;
-        if (gi >= n) break;
-        const int32_t gj = j0 + lane;
-        if (gj > gi) continue;
-        const uint32_t wv = A[(K + tr + 1) * S::WPR + 1 + (lane >> 5)];
-        p.nxt[(int64_t)gi * ld + gj] = (uint8_t)((wv >> (lane & 31)) & 1u);
-    }
-}
-
-// The same update run by one wave per tile (64 threads): no workgroup
-// barriers, and four times as many tiles in flight per CU as with 256
-// threads, which is what the load-then-compute pattern needs to keep HBM
-// busy.  lds: at least 2 * LifeBitsShape::WORDS words.
+// The update run by one wave per tile (64 threads): no workgroup barriers,
+// and four times as many tiles in flight per CU as with 256 threads, which
+// is what the load-then-compute pattern needs to keep HBM busy on large
+// grids (on small grids the byte-sliced body, whose tile finishes sooner,
+// is faster).  lds: at least 2 * LifeBitsShape::WORDS words.
 __device__ __forceinline__ void life_bits_wave_body(const LifeTile &p, int32_t bi, int32_t bj,
                                                     int gens, uint32_t *lds)
 {
@@ -427,11 +316,6 @@ template <int TILE>
 __device__ __forceinline__ void life_multi_tile_body(const LifeTile &p, int32_t bi, int32_t bj,
                                                      int gens, uint32_t *lds)
 {
-    if constexpr (TILE == 64) {
-        static_assert(2 * LifeBitsShape::WORDS <= 2 * LifeMultiShape<64>::WORDS, "lds");
-        life_bits_tile_body(p, bi, bj, gens, lds);
-        return;
-    }
     using S = LifeMultiShape<TILE>;
     uint32_t *buf0 = lds, *buf1 = lds + S::WORDS;
     const int32_t n = p.n;

@@ -96,24 +96,38 @@ __global__ void __launch_bounds__(64) k_life_bits(LifeArgs p, int gens)
     life_bits_wave_body(p.t, bi, bj, gens, buf);
 }
 
+// 64 x 64 tiles take the bit-sliced one-wave kernel on grids of at least
+// this many tiles, the byte-sliced 256-thread one below (measured: the
+// former wins at n = 16384, the latter on the batched workload's n <= 8192)
+constexpr uint64_t kLifeBitsMinTiles = 16384;
+
 template <int MAP>
-static bool life_multi_kernel_tile(int tile, const void *&fn)
+static bool life_multi_kernel_tile(int tile, uint64_t tiles, const void *&fn, int &threads)
 {
+    threads = 256;
     switch (tile) {
     case 16: fn = (const void *)k_life_multi<MAP, 16>; return true;
     case 32: fn = (const void *)k_life_multi<MAP, 32>; return true;
-    case 64: fn = (const void *)k_life_bits<MAP>; return true;
+    case 64:
+        if (tiles >= kLifeBitsMinTiles) {
+            fn = (const void *)k_life_bits<MAP>;
+            threads = 64;
+        } else {
+            fn = (const void *)k_life_multi<MAP, 64>;
+        }
+        return true;
     }
     return false;
 }
 
-static bool life_multi_kernel(const tri_plan *p, const void *&fn)
+static bool life_multi_kernel(const tri_plan *p, const void *&fn, int &threads)
 {
+    const uint64_t T = (uint64_t)p->T;
     switch (p->map) {
-    case TRI_MAP_BB: return life_multi_kernel_tile<MAP_BB>(p->tile, fn);
-    case TRI_MAP_RB: return life_multi_kernel_tile<MAP_RB>(p->tile, fn);
-    case TRI_MAP_REC: return life_multi_kernel_tile<MAP_REC>(p->tile, fn);
-    case TRI_MAP_LAMBDA: return life_multi_kernel_tile<MAP_LAMBDA>(p->tile, fn);
+    case TRI_MAP_BB: return life_multi_kernel_tile<MAP_BB>(p->tile, T, fn, threads);
+    case TRI_MAP_RB: return life_multi_kernel_tile<MAP_RB>(p->tile, T, fn, threads);
+    case TRI_MAP_REC: return life_multi_kernel_tile<MAP_REC>(p->tile, T, fn, threads);
+    case TRI_MAP_LAMBDA: return life_multi_kernel_tile<MAP_LAMBDA>(p->tile, T, fn, threads);
     }
     return false;
 }
@@ -140,7 +154,10 @@ bool launch_life_multi_lambda(int tile, const TileGrid &g, const LifeTile &t, in
     switch (tile) {
     case 16: k_life_multi<MAP_LAMBDA, 16><<<grid, 256, 0, s>>>(a, gens); return true;
     case 32: k_life_multi<MAP_LAMBDA, 32><<<grid, 256, 0, s>>>(a, gens); return true;
-    case 64: k_life_bits<MAP_LAMBDA><<<grid, 64, 0, s>>>(a, gens); return true;
+    case 64:
+        if (g.T >= kLifeBitsMinTiles) k_life_bits<MAP_LAMBDA><<<grid, 64, 0, s>>>(a, gens);
+        else k_life_multi<MAP_LAMBDA, 64><<<grid, 256, 0, s>>>(a, gens);
+        return true;
     }
     return false;
 }
@@ -271,7 +288,8 @@ extern "C" tri_status tri_launch_stencil(const tri_plan *p, uint8_t *cur, uint8_
         if (use_graph)
             return fail(TRI_E_UNSUPPORTED, "tri_launch_stencil: graphs of the temporal kernel are not built");
         const void *fn = nullptr;
-        if (!life_multi_kernel(p, fn))
+        int threads = 256;
+        if (!life_multi_kernel(p, fn, threads))
             return fail(TRI_E_UNSUPPORTED, "tri_launch_stencil: temporal blocking needs tile 16, 32 or 64");
         const std::vector<int> sched = life_multi_schedule(steps);
         for (size_t k = 0; k < sched.size(); ++k) {
@@ -279,8 +297,7 @@ extern "C" tri_status tri_launch_stencil(const tri_plan *p, uint8_t *cur, uint8_
             a.t.nxt = (k & 1) ? cur : nxt;
             int gens = sched[k];
             void *args[] = {&a, &gens};
-            TRI_HIP(hipLaunchKernel(fn, dim3(p->gx, p->gy), dim3(p->tile == 64 ? 64 : 256), args,
-                                    0, s));
+            TRI_HIP(hipLaunchKernel(fn, dim3(p->gx, p->gy), dim3(threads), args, 0, s));
         }
         return TRI_OK;
     }

@@ -289,6 +289,7 @@ static bool dispatch_tile(const tri_plan *p, const ElemArgs &args, hipStream_t s
     case 16: launch_tile<OP, MAP, 16, VECTOR>(p, args, s); return true;
     case 32: launch_tile<OP, MAP, 32, VECTOR>(p, args, s); return true;
     case 64: launch_tile<OP, MAP, 64, VECTOR>(p, args, s); return true;
+    case 128: launch_tile<OP, MAP, 128, VECTOR>(p, args, s); return true;
     }
     return false;
 }
@@ -322,8 +323,8 @@ extern "C" tri_status tri_launch_elementwise(const tri_plan *p, int op, const vo
         return fail(TRI_E_INVAL, "tri_launch_elementwise: op = %d", op);
     if (!p->diag)
         return fail(TRI_E_UNSUPPORTED, "tri_launch_elementwise: needs include_diag = 1");
-    if (p->tile > 64)
-        return fail(TRI_E_UNSUPPORTED, "tri_launch_elementwise: tile %d > 64", p->tile);
+    if (p->tile > 128)
+        return fail(TRI_E_UNSUPPORTED, "tri_launch_elementwise: tile %d > 128", p->tile);
     if (p->n == 0) return TRI_OK;
     if (!x || (!y && op != TRI_OP_EDM4_F32) || !c)
         return fail(TRI_E_INVAL, "tri_launch_elementwise: NULL buffer");

@@ -8,14 +8,27 @@ namespace trimap {
 
 typedef float f4p __attribute__((ext_vector_type(4)));
 
+// Each workgroup streams a contiguous block of 4 x 256 vectors: every
+// thread issues its four loads of a and of b before the first add.
+constexpr int kStreamUnroll = 4;
+
 __global__ void __launch_bounds__(256) k_stream_add(f4p *c, const f4p *a, const f4p *b,
                                                     uint64_t nvec)
 {
-    const uint64_t stride = (uint64_t)gridDim.x * 256;
-    for (uint64_t k = (uint64_t)blockIdx.x * 256 + threadIdx.x; k < nvec; k += stride) {
-        const f4p x = __builtin_nontemporal_load(a + k);
-        const f4p y = __builtin_nontemporal_load(b + k);
-        __builtin_nontemporal_store(x + y, c + k);
+    const uint64_t base = (uint64_t)blockIdx.x * (256 * kStreamUnroll) + threadIdx.x;
+    f4p x[kStreamUnroll], y[kStreamUnroll];
+#pragma unroll
+    for (int u = 0; u < kStreamUnroll; ++u) {
+        const uint64_t k = base + 256 * u;
+        if (k < nvec) {
+            x[u] = __builtin_nontemporal_load(a + k);
+            y[u] = __builtin_nontemporal_load(b + k);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < kStreamUnroll; ++u) {
+        const uint64_t k = base + 256 * u;
+        if (k < nvec) __builtin_nontemporal_store(x[u] + y[u], c + k);
     }
 }
 
@@ -32,14 +45,11 @@ extern "C" tri_status tri_stream_add(float *c, const float *a, const float *b, i
     if (count % 4 || (((uintptr_t)a | (uintptr_t)b | (uintptr_t)c) & 15))
         return fail(TRI_E_INVAL, "tri_stream_add: count must be a multiple of 4 and buffers 16-byte aligned");
     if (count == 0) return TRI_OK;
-    int dev = 0, cus = 0;
-    TRI_HIP(hipGetDevice(&dev));
-    TRI_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     const uint64_t nvec = (uint64_t)count / 4;
-    const uint64_t want = (nvec + 255) / 256;
-    const uint32_t grid = (uint32_t)(want < (uint64_t)cus * 16 ? want : (uint64_t)cus * 16);
-    k_stream_add<<<grid, 256, 0, (hipStream_t)stream>>>((f4p *)c, (const f4p *)a,
-                                                         (const f4p *)b, nvec);
+    const uint64_t blocks = (nvec + 256 * kStreamUnroll - 1) / (256 * kStreamUnroll);
+    if (blocks > kMaxWorkItems / 256) return fail(TRI_E_RANGE, "tri_stream_add: count too large");
+    k_stream_add<<<dim3((uint32_t)blocks), 256, 0, (hipStream_t)stream>>>((f4p *)c, (const f4p *)a,
+                                                                          (const f4p *)b, nvec);
     TRI_HIP(hipGetLastError());
     return TRI_OK;
 }

@@ -34,7 +34,7 @@ def _low(n, ld):
 
 
 @pytest.mark.parametrize("map_name", MAPS)
-@pytest.mark.parametrize("tile", [8, 16, 32, 64])
+@pytest.mark.parametrize("tile", [8, 16, 32, 64, 128])
 def test_xormul_i32_bit_exact(map_name, tile):
     tm = _tm()
     for n in SIZES:
@@ -53,7 +53,7 @@ def test_xormul_i32_bit_exact(map_name, tile):
 
 
 @pytest.mark.parametrize("map_name", MAPS)
-@pytest.mark.parametrize("tile", [8, 16, 32, 64])
+@pytest.mark.parametrize("tile", [8, 16, 32, 64, 128])
 def test_axpyt_f32_bit_exact(map_name, tile):
     tm = _tm()
     for n in SIZES:

@@ -341,8 +341,9 @@ tri_status tri_batch_autotune(int32_t count, const int32_t *host_kind, const int
 /* ------------------------------------------------------------------------
  * Autotuner: tile size and map for a workload and problem size.
  *
- * tri_autotune times every candidate (tiles 8/16/32/64 — 16/32/64/128 for
- * the FP32 distance map, 128 for the MFMA one — times maps BB, RB, REC (when
+ * tri_autotune times every candidate (tiles 8/16/32/64 — plus 128 for the
+ * fp32 elementwise body, 16/32/64/128 for the FP32 distance map, 128 for the
+ * MFMA one — times maps BB, RB, REC (when
  * m is a power of two) and lambda, the latter plain, with
  * TRI_FLAG_XCD_SWIZZLE, TRI_FLAG_ORDER_REVERSE, TRI_FLAG_ORDER_PAIRS and
  * swizzle + pairs, plus UTM for the elementwise bodies and Life) on this GPU: one warm-up and `reps` timed calls

@@ -83,7 +83,7 @@ static std::vector<Candidate> candidates(int workload, int64_t n)
     std::vector<int> maps = {TRI_MAP_BB, TRI_MAP_RB, TRI_MAP_REC, TRI_MAP_LAMBDA};
     bool utm = false;
     switch (workload) {
-    case TRI_TUNE_ELEMENTWISE_F32:
+    case TRI_TUNE_ELEMENTWISE_F32: tiles = {8, 16, 32, 64, 128}; utm = true; break;
     case TRI_TUNE_ELEMENTWISE_I32: tiles = {8, 16, 32, 64}; utm = true; break;
     case TRI_TUNE_LIFE: tiles = {8, 16, 32, 64}; utm = true; break;
     case TRI_TUNE_EDM_FP32: tiles = {16, 32, 64, 128}; break;

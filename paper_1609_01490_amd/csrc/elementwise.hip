@@ -68,35 +68,45 @@ __global__ void __launch_bounds__((ElemShape<TILE, VECTOR>::NT)) k_axpyt(ElemArg
     // every cell of the tile is in the domain
     const bool full = (bj < bi) && (i0 + TILE <= n);
 
-    // X rows of this thread: issued first so that both streams are in flight
-    // while the mirror tile goes through LDS
+    // Every load is unconditional, so that all of them are in flight at once
+    // (a load under a condition is waited for where the branches rejoin).
+    // On tiles that cross the diagonal or the last row the addresses are
+    // clamped into the n x ld matrices; the values read there belong to
+    // cells that are never stored.  X first, then the mirror tile of Y
+    // (rows j0.., columns i0..; Y[j][i] lands in ys[j-j0][i-i0]).
     using V = typename std::conditional<S::VEC == 4, f4, float>::type;
-    V xv[S::PASSES];
+    const int32_t cmax = (int32_t)(ld - S::VEC);  // last column start of a vector
+    V xv[S::PASSES], yv[S::PASSES];
 #pragma unroll
     for (int ps = 0; ps < S::PASSES; ++ps) {
         const int r = tr + ps * S::RPP;
-        const int32_t i = i0 + r, jc = j0 + tc;
-        if (full || (i < n && jc <= i))
-            xv[ps] = __builtin_nontemporal_load((const V *)(X + (int64_t)i * ld + jc));
-        else
-            xv[ps] = V{};
+        int32_t i = i0 + r, jc = j0 + tc;
+        if (!full) {
+            i = i < n ? i : n - 1;
+            jc = jc < cmax ? jc : cmax;
+        }
+        xv[ps] = __builtin_nontemporal_load((const V *)(X + (int64_t)i * ld + jc));
     }
-
-    // mirror tile of Y: rows j0.., columns i0.. ; Y[j][i] lands in ys[j-j0][i-i0]
 #pragma unroll
     for (int ps = 0; ps < S::PASSES; ++ps) {
         const int r = tr + ps * S::RPP;
-        const int32_t jr = j0 + r, ic = i0 + tc;
-        const bool need = full || (ic < n && jr < n && jr <= ic + S::VEC - 1);
+        int32_t jr = j0 + r, ic = i0 + tc;
+        if (!full) {
+            jr = jr < n ? jr : n - 1;
+            ic = ic < cmax ? ic : cmax;
+        }
+        yv[ps] = __builtin_nontemporal_load((const V *)(Y + (int64_t)jr * ld + ic));
+    }
+#pragma unroll
+    for (int ps = 0; ps < S::PASSES; ++ps) {
+        const int r = tr + ps * S::RPP;
         if constexpr (S::VEC == 4) {
-            f4 v = {0.f, 0.f, 0.f, 0.f};
-            if (need) v = __builtin_nontemporal_load((const f4 *)(Y + (int64_t)jr * ld + ic));
-            ys[r][tc + 0] = v.x;
-            ys[r][tc + 1] = v.y;
-            ys[r][tc + 2] = v.z;
-            ys[r][tc + 3] = v.w;
+            ys[r][tc + 0] = yv[ps].x;
+            ys[r][tc + 1] = yv[ps].y;
+            ys[r][tc + 2] = yv[ps].z;
+            ys[r][tc + 3] = yv[ps].w;
         } else {
-            ys[r][tc] = need ? __builtin_nontemporal_load(Y + (int64_t)jr * ld + ic) : 0.f;
+            ys[r][tc] = yv[ps];
         }
     }
     __syncthreads();

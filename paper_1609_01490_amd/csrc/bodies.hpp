@@ -62,7 +62,10 @@ __device__ __forceinline__ uint32_t life_hsum3(uint32_t west, uint32_t w, uint32
     return w + wl + wr;
 }
 
-template <int TILE, int NT>
+// HOIST: issue every staging load before the first is used (more registers;
+// the standalone kernels), else load and store word by word (the batched
+// kernel, whose occupancy is set by its largest body).
+template <int TILE, int NT, bool HOIST = true>
 __device__ __forceinline__ void life_tile_body(const LifeTile &p, int32_t bi, int32_t bj,
                                                uint32_t *lds)
 {
@@ -73,18 +76,39 @@ __device__ __forceinline__ void life_tile_body(const LifeTile &p, int32_t bi, in
     // the halo and the tile lie wholly inside the domain and the square
     const bool interior = (bi != bj) && bj > 0 && (i0 + TILE < n) && (j0 + TILE + 3 < i0);
 
-    // stage rows i0-1 .. i0+TILE, words at columns j0-4 .. j0+TILE
-    for (int idx = threadIdx.x; idx < S::LDS_WORDS; idx += NT) {
-        const int lr = idx / S::LW, lw = idx % S::LW;
-        const int32_t gi = i0 - 1 + lr;
-        const int32_t gj = j0 - 4 + 4 * lw;
-        uint32_t v = 0;
-        if (interior) {
-            v = *(const uint32_t *)(p.cur + (int64_t)gi * ld + gj);
-        } else if (gi >= 0 && gi < n && gj >= 0 && gj <= gi) {
-            v = *(const uint32_t *)(p.cur + (int64_t)gi * ld + gj) & life_domain_mask(gi, gj);
+    // stage rows i0-1 .. i0+TILE, words at columns j0-4 .. j0+TILE.  Every
+    // load is unconditional, from an address clamped into the grid, and
+    // masked afterwards, so that all of a thread's loads are in flight at
+    // once (a load under a condition is waited for where the branches join).
+    auto mask_of = [&](int32_t gi, int32_t gj) -> uint32_t {
+        if (interior) return 0xFFFFFFFFu;
+        return (gi >= 0 && gi < n && gj >= 0 && gj <= gi) ? life_domain_mask(gi, gj) : 0u;
+    };
+    auto clamped = [&](int32_t gi, int32_t gj) -> const uint32_t * {
+        gi = gi < 0 ? 0 : (gi >= n ? n - 1 : gi);
+        gj = gj < 0 ? 0 : (gj > (int32_t)ld - 4 ? (int32_t)ld - 4 : gj);
+        return (const uint32_t *)(p.cur + (int64_t)gi * ld + gj);
+    };
+    if constexpr (HOIST) {
+        constexpr int IT = (S::LDS_WORDS + NT - 1) / NT;
+        uint32_t raw[IT];
+#pragma unroll
+        for (int u = 0; u < IT; ++u) {
+            const int idx = threadIdx.x + u * NT;
+            raw[u] = *clamped(i0 - 1 + idx / S::LW, j0 - 4 + 4 * (idx % S::LW));
         }
-        lds[idx] = v;
+#pragma unroll
+        for (int u = 0; u < IT; ++u) {
+            const int idx = threadIdx.x + u * NT;
+            if (idx >= S::LDS_WORDS) break;
+            lds[idx] = raw[u] & mask_of(i0 - 1 + idx / S::LW, j0 - 4 + 4 * (idx % S::LW));
+        }
+    } else {
+        for (int idx = threadIdx.x; idx < S::LDS_WORDS; idx += NT) {
+            const int32_t gi = i0 - 1 + idx / S::LW, gj = j0 - 4 + 4 * (idx % S::LW);
+            const uint32_t m = mask_of(gi, gj);
+            lds[idx] = m ? *clamped(gi, gj) & m : 0u;
+        }
     }
     __syncthreads();
     if (threadIdx.x >= S::ACTIVE) return;
@@ -311,8 +335,9 @@ __device__ __forceinline__ void life_bits_wave_body(const LifeTile &p, int32_t b
     }
 }
 
-// lds: 2 * LifeMultiShape<TILE>::WORDS words; 256 threads; 1 <= gens <= 4
-template <int TILE>
+// lds: 2 * LifeMultiShape<TILE>::WORDS words; 256 threads; 1 <= gens <= 4;
+// HOIST as for life_tile_body
+template <int TILE, bool HOIST = true>
 __device__ __forceinline__ void life_multi_tile_body(const LifeTile &p, int32_t bi, int32_t bj,
                                                      int gens, uint32_t *lds)
 {
@@ -324,18 +349,39 @@ __device__ __forceinline__ void life_multi_tile_body(const LifeTile &p, int32_t 
     const int K = kLifeMaxGen;
 
     // stage rows i0-K .. i0+TILE+K-1, words at columns j0-4 .. j0+TILE, with
-    // a zero border around the window
-    for (int idx = threadIdx.x; idx < S::WORDS; idx += S::NT) {
-        const int pr = idx / S::PW, pw = idx % S::PW;
-        uint32_t v = 0;
-        if (pr >= 1 && pr <= S::R && pw >= 1 && pw <= S::W) {
-            const int32_t gi = i0 - K + (pr - 1);
-            const int32_t gj = j0 - 4 + 4 * (pw - 1);
-            const uint32_t m = life_window_mask(gi, gj, n);
-            if (m) v = *(const uint32_t *)(p.cur + (int64_t)gi * ld + gj) & m;
+    // a zero border around the window; unconditional loads from clamped
+    // addresses, masked afterwards (as in life_tile_body)
+    auto mask_of = [&](int pr, int pw) -> uint32_t {
+        if (pr < 1 || pr > S::R || pw < 1 || pw > S::W) return 0u;
+        return life_window_mask(i0 - K + (pr - 1), j0 - 4 + 4 * (pw - 1), n);
+    };
+    auto clamped = [&](int pr, int pw) -> const uint32_t * {
+        int32_t gi = i0 - K + (pr - 1), gj = j0 - 4 + 4 * (pw - 1);
+        gi = gi < 0 ? 0 : (gi >= n ? n - 1 : gi);
+        gj = gj < 0 ? 0 : (gj > (int32_t)ld - 4 ? (int32_t)ld - 4 : gj);
+        return (const uint32_t *)(p.cur + (int64_t)gi * ld + gj);
+    };
+    if constexpr (HOIST) {
+        constexpr int IT = (S::WORDS + S::NT - 1) / S::NT;
+        uint32_t raw[IT];
+#pragma unroll
+        for (int u = 0; u < IT; ++u) {
+            const int idx = threadIdx.x + u * S::NT;
+            raw[u] = *clamped(idx / S::PW, idx % S::PW);
         }
-        buf0[idx] = v;
-        buf1[idx] = 0;
+#pragma unroll
+        for (int u = 0; u < IT; ++u) {
+            const int idx = threadIdx.x + u * S::NT;
+            if (idx >= S::WORDS) break;
+            buf0[idx] = raw[u] & mask_of(idx / S::PW, idx % S::PW);
+            buf1[idx] = 0;
+        }
+    } else {
+        for (int idx = threadIdx.x; idx < S::WORDS; idx += S::NT) {
+            const uint32_t m = mask_of(idx / S::PW, idx % S::PW);
+            buf0[idx] = m ? *clamped(idx / S::PW, idx % S::PW) & m : 0u;
+            buf1[idx] = 0;
+        }
     }
     __syncthreads();
 

@@ -262,27 +262,29 @@ def bench_edm(tm, torch, timer):
 
 def bench_edm4(tm, torch, timer, n=32768):
     """Four-feature distances (the global-memory distance test of Section
-    4.1) written to the n x n lower triangle: every map at tiles 16, 32, 64
-    (UTM has no tile), with the improvement factor I = t_BB / t_map at each
-    tile.  HBM-bound: 4 B written per cell; the points (16 B each) stay in
+    4.1) written to the n x n lower triangle: every map at tiles 16, 32, 64,
+    128 (lambda also with the pairs order and the XCD swizzle; UTM has no
+    tile), with the improvement factor I = t_BB / t_map at each tile.  HBM-bound: 4 B written per cell; the points (16 B each) stay in
     cache."""
     from paper_1609_01490_amd import inputs
     P = torch.from_numpy(inputs.points4(n)).cuda()
     c = torch.empty((n, n), dtype=torch.float32, device="cuda")
     E = n * (n + 1) // 2
     ms = {}
-    for t_ in (16, 32, 64):
-        for map_name in ("bb", "rb", "rec", "lambda", "utm"):
+    for t_ in (16, 32, 64, 128):
+        for map_name, fl in (("bb", 0), ("rb", 0), ("rec", 0), ("lambda", 0), ("utm", 0),
+                             ("lambda", tm.FLAG_ORDER_PAIRS), ("lambda", tm.FLAG_XCD_SWIZZLE)):
             if map_name == "utm" and t_ != 16:
                 continue
-            p = tm.Plan(n, t_, map_name)
-            key = "utm" if map_name == "utm" else f"{map_name}/t{t_}"
+            p = tm.Plan(n, t_, map_name, flags=fl)
+            key = "utm" if map_name == "utm" else f"{map_name}/t{t_}" + (f"/f{fl}" if fl else "")
             ms[key] = round(timer.run(lambda: p.elementwise(tm.OP_EDM4_F32, P, None, c, ld=n),
                                       5, 2), 4)
     del P, c
     torch.cuda.empty_cache()
     best = min(ms, key=ms.get)
-    I = {k: round(ms[f"bb/t{k.split('/t')[1]}"] / v, 4) for k, v in ms.items() if "/t" in k}
+    I = {k: round(ms[f"bb/t{k.split('/t')[1].split('/')[0]}"] / v, 4)
+         for k, v in ms.items() if "/t" in k}
     I["utm"] = round(min(v for k, v in ms.items() if k.startswith("bb/")) / ms["utm"], 4)
     return {"n": n, "cells": E, "ms_by_map_tile": ms, "best": best,
             "best_GBps_written": round(4 * E / (ms[best] * 1e-3) / 1e9, 1),

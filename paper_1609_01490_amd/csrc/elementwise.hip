@@ -219,35 +219,35 @@ __global__ void __launch_bounds__((ElemShape<TILE, VECTOR>::NT)) k_edm4(ElemArgs
     float *C = (float *)p.c;
     const bool full = (bj < bi) && (i0 + TILE <= n);
 
+    // the lane's column points (the same for all its rows), read once from
+    // global memory; past n - 1 (the ragged last tile) clamped and unused
+    const int32_t jc = j0 + tc;
+    f4 pj[S::VEC];
+#pragma unroll
+    for (int v = 0; v < S::VEC; ++v) pj[v] = P[jc + v < n ? jc + v : n - 1];
+
 #pragma unroll
     for (int ps = 0; ps < S::PASSES; ++ps) {
         const int r = tr + ps * S::RPP;
-        const int32_t i = i0 + r, jc = j0 + tc;
+        const int32_t i = i0 + r;
         if (!full && (i >= n || jc > i)) continue;
         const f4 pi = P[i];
         float *crow = C + (int64_t)i * ld + jc;
         if constexpr (S::VEC == 4) {
-            // jc + 1 .. jc + 3 may lie past the diagonal (and past n - 1 on
-            // the last tile row): those lanes reuse P[jc] and are not stored
-            const f4 p0 = P[jc];
-            const bool all = full || jc + 3 <= i;
-            const f4 p1 = (all || jc + 1 <= i) ? P[jc + 1] : p0;
-            const f4 p2 = (all || jc + 2 <= i) ? P[jc + 2] : p0;
-            const f4 p3 = all ? P[jc + 3] : p0;
             f4 o;
-            o.x = dist4(pi, p0);
-            o.y = dist4(pi, p1);
-            o.z = dist4(pi, p2);
-            o.w = dist4(pi, p3);
-            if (all) {
+            o.x = dist4(pi, pj[0]);
+            o.y = dist4(pi, pj[1]);
+            o.z = dist4(pi, pj[2]);
+            o.w = dist4(pi, pj[3]);
+            if (full || jc + 3 <= i) {
                 __builtin_nontemporal_store(o, (f4 *)crow);
-            } else {
+            } else {  // the vector straddles the diagonal
                 crow[0] = o.x;
                 if (jc + 1 <= i) crow[1] = o.y;
                 if (jc + 2 <= i) crow[2] = o.z;
             }
         } else {
-            __builtin_nontemporal_store(dist4(pi, P[jc]), crow);
+            __builtin_nontemporal_store(dist4(pi, pj[0]), crow);
         }
     }
 }

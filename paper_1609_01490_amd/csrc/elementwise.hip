@@ -41,7 +41,10 @@ template <int TILE, bool VECTOR>
 struct ElemShape {
     static constexpr int VEC = (VECTOR && TILE >= 16) ? 4 : 1;
     static constexpr int NT_RAW = TILE * TILE / VEC;
-    static constexpr int NT = NT_RAW > 256 ? 256 : NT_RAW;
+    // tile 128 takes 512 threads: its 66 KB transpose buffer holds the CU to
+    // two workgroups, so the extra waves are what keeps more loads in flight
+    static constexpr int NT_MAX = TILE >= 128 ? 512 : 256;
+    static constexpr int NT = NT_RAW > NT_MAX ? NT_MAX : NT_RAW;
     static constexpr int VPR = TILE / VEC;    // vectors per row
     static constexpr int RPP = NT / VPR;      // rows per pass
     static constexpr int PASSES = TILE / RPP;

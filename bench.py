@@ -471,7 +471,8 @@ def profile_target(tm, torch, args):
         X, _ = inputs.points(n, d)
         xd = torch.from_numpy(X).cuda()
         out = torch.empty((n * (n - 1) // 2,), dtype=torch.float32, device="cuda")
-        q = tm.Plan(n, 128, "lambda", include_diag=False, flags=tm.FLAG_XCD_SWIZZLE)
+        q = tm.Plan(n, 128, "lambda", include_diag=False,
+                    flags=args.flags or tm.FLAG_XCD_SWIZZLE)
         ws = torch.empty(q.edm_workspace_size(d, tm.EDM_BF16X3), dtype=torch.uint8,
                          device="cuda")
         for _ in range(reps):

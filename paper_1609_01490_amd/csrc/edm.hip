@@ -212,13 +212,13 @@ struct EdmStage {
 
 template <bool SPLIT>
 __device__ __forceinline__ void edm_stage_load(const EdmMfmaArgs &p, int32_t RW, int32_t CW,
-                                               int32_t k0, EdmStage<SPLIT> &st)
+                                               int32_t k0, EdmStage<SPLIT> &st, int tid)
 {
     const int32_t n = p.n, dp = p.dp;
     const int32_t kn = min(kKC, dp - k0);
 #pragma unroll
     for (int u = 0; u < kVecPerThread; ++u) {
-        const int v = threadIdx.x + 256 * u;
+        const int v = tid + 256 * u;
         const int row = v / (kKC / 8), c8 = (v % (kKC / 8)) * 8;
         const int32_t ra = min(RW + row, n - 1), rb = min(CW + row, n - 1);
         st.ha[u] = st.hb[u] = st.la[u] = st.lb[u] = bf16x8{};
@@ -235,11 +235,11 @@ __device__ __forceinline__ void edm_stage_load(const EdmMfmaArgs &p, int32_t RW,
 
 template <bool SPLIT>
 __device__ __forceinline__ void edm_stage_store(const EdmStage<SPLIT> &st, __bf16 *sAh, __bf16 *sBh,
-                                                __bf16 *sAl, __bf16 *sBl)
+                                                __bf16 *sAl, __bf16 *sBl, int tid)
 {
 #pragma unroll
     for (int u = 0; u < kVecPerThread; ++u) {
-        const int v = threadIdx.x + 256 * u;
+        const int v = tid + 256 * u;
         const int row = v / (kKC / 8), c8 = (v % (kKC / 8)) * 8;
         *(bf16x8 *)&sAh[row * kRS + c8] = st.ha[u];
         *(bf16x8 *)&sBh[row * kRS + c8] = st.hb[u];
@@ -250,78 +250,82 @@ __device__ __forceinline__ void edm_stage_store(const EdmStage<SPLIT> &st, __bf1
     }
 }
 
-template <int MAP, bool SPLIT>
-__global__ void __launch_bounds__(256) k_edm_mfma(EdmMfmaArgs p)
+// One LDS chunk of the Gram products: kn dimensions (a multiple of 16) of
+// the wave's 64 x 64 block as a 2 x 2 grid of 32 x 32 MFMA blocks
+// (hi.hi + hi.lo + lo.hi with the split, hi.hi without).
+template <bool SPLIT>
+__device__ __forceinline__ void edm_mfma_chunk(f32x16 (&acc)[2][2], const __bf16 *sAh,
+                                               const __bf16 *sBh, const __bf16 *sAl,
+                                               const __bf16 *sBl, int32_t kn, int wr, int wc,
+                                               int lr, int lk)
 {
-    constexpr int PLANES = SPLIT ? 4 : 2;
-    __shared__ __attribute__((aligned(16))) unsigned char lds[PLANES * kPlaneBytes];
-    __shared__ __attribute__((aligned(16))) float sN[2 * kEdmTile];
-    __bf16 *sAh = (__bf16 *)lds;
-    __bf16 *sBh = (__bf16 *)(lds + kPlaneBytes);
-    __bf16 *sAl = (__bf16 *)(lds + 2 * kPlaneBytes);  // split only
-    __bf16 *sBl = (__bf16 *)(lds + 3 * kPlaneBytes);
-
-    int32_t bi, bj;
-    if (!tile_of_block<MAP>(p.g, bi, bj)) return;
-    const int t = threadIdx.x, w = t >> 6, l = t & 63;
-    const int32_t n = p.n, dp = p.dp;
-    const int32_t RW = 1 + bi * kEdmTile;  // first row point of the tile
-    const int32_t CW = bj * kEdmTile;      // first column point of the tile
-
-    EdmStage<SPLIT> st;
-    edm_stage_load<SPLIT>(p, RW, CW, 0, st);
-    // norms of the tile's row and column points
-    {
-        const int32_t q = t < kEdmTile ? RW + t : CW + (t - kEdmTile);
-        sN[t] = p.norms[min(q, n - 1)];
+    for (int kk = 0; kk < kn; kk += 16) {
+        bf16x8 Ah[2], Bh[2], Al[2], Bl[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            const int ia = (64 * wr + 32 * a + lr) * kRS + kk + lk;
+            const int ib = (64 * wc + 32 * a + lr) * kRS + kk + lk;
+            Ah[a] = *(const bf16x8 *)&sAh[ia];
+            Bh[a] = *(const bf16x8 *)&sBh[ib];
+            if (SPLIT) {
+                Al[a] = *(const bf16x8 *)&sAl[ia];
+                Bl[a] = *(const bf16x8 *)&sBl[ib];
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah[a], Bh[b], acc[a][b], 0, 0, 0);
+                if (SPLIT) {
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah[a], Bl[b], acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Al[a], Bh[b], acc[a][b], 0, 0, 0);
+                }
+            }
     }
+}
 
-    const int wr = w >> 1, wc = w & 1;
-    const int lr = l & 31, lk = (l >> 5) * 8;
-    f32x16 acc[2][2];
+// Stores a wave's 64 x 64 block of squared distances as distances.  MFMA
+// layout of a 32 x 32 block: lane l holds column l % 32 and, in register
+// 4 q + u, row 8 q + 4 (l / 32) + u.  ob is the start of row R0 in the
+// condensed array and offsets are counted from there in 32 bits.  FULL:
+// every pair is in the domain (no per-store test).
+template <bool FULL>
+__device__ __forceinline__ void edm_store_block(char *ob, const f32x16 (&acc)[2][2], int32_t R0,
+                                                int32_t jl, int32_t n, int l)
+{
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int q = 0; q < 4; ++q) {
+            int32_t i = R0 + 32 * a + 8 * q + 4 * (l >> 5);
+            uint32_t off = (uint32_t)((i - R0) * (i + R0 - 1)) / 2u + (uint32_t)jl;
 #pragma unroll
-            for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
-
-    for (int32_t k0 = 0; k0 < dp; k0 += kKC) {
-        const int32_t kn = min(kKC, dp - k0);  // multiple of 16
-        edm_stage_store<SPLIT>(st, sAh, sBh, sAl, sBl);
-        lds_barrier();
-        if (k0 + kKC < dp) edm_stage_load<SPLIT>(p, RW, CW, k0 + kKC, st);  // in flight
-        for (int kk = 0; kk < kn; kk += 16) {
-            bf16x8 Ah[2], Bh[2], Al[2], Bl[2];
-#pragma unroll
-            for (int a = 0; a < 2; ++a) {
-                const int ia = (64 * wr + 32 * a + lr) * kRS + kk + lk;
-                const int ib = (64 * wc + 32 * a + lr) * kRS + kk + lk;
-                Ah[a] = *(const bf16x8 *)&sAh[ia];
-                Bh[a] = *(const bf16x8 *)&sBh[ib];
-                if (SPLIT) {
-                    Al[a] = *(const bf16x8 *)&sAl[ia];
-                    Bl[a] = *(const bf16x8 *)&sBl[ib];
-                }
-            }
-#pragma unroll
-            for (int a = 0; a < 2; ++a)
+            for (int u = 0; u < 4; ++u) {
 #pragma unroll
                 for (int b = 0; b < 2; ++b) {
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah[a], Bh[b], acc[a][b], 0, 0, 0);
-                    if (SPLIT) {
-                        acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah[a], Bl[b], acc[a][b], 0, 0, 0);
-                        acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Al[a], Bh[b], acc[a][b], 0, 0, 0);
-                    }
+                    // the square root of a negative square (rounding) is NaN,
+                    // which the max turns into 0
+                    const float dd = fmaxf(__builtin_amdgcn_sqrtf(acc[a][b][4 * q + u]), 0.f);
+                    if (FULL || (i < n && jl + 32 * b < i))
+                        *(float *)(ob + ((off + 32u * b) << 2)) = dd;
                 }
+                off += (uint32_t)i;  // start of row i + 1
+                ++i;
+            }
         }
-        lds_barrier();
-    }
+}
 
-    // D[m][n] of a 32 x 32 block: lane l holds column n = l % 32 and, in
-    // register r, row m = 8 (r / 4) + 4 (l / 32) + r % 4.
-    const int32_t R0 = RW + 64 * wr, C0 = CW + 64 * wc;  // this wave's 64 x 64 block
-    if (R0 >= n || C0 >= R0 + 63) return;  // no pair j < i < n here (no barrier follows)
+// The distances of a wave's 64 x 64 block whose first row point is R0 and
+// first column point C0 (R0 < n and C0 < R0 + 63: some pair j < i < n
+// lies in it), from the Gram block in acc and the tile's norms in sN (rows
+// first, then columns).
+__device__ __forceinline__ void edm_epilogue(const EdmMfmaArgs &p, f32x16 (&acc)[2][2],
+                                             const float *sN, int wr, int wc, int32_t R0,
+                                             int32_t C0, int l)
+{
+    const int lr = l & 31;
+    const int32_t n = p.n;
     // d^2 = |x_i|^2 + |x_j|^2 - 2 x_i.x_j, in place
     bool near = false;
 #pragma unroll
@@ -341,42 +345,200 @@ __global__ void __launch_bounds__(256) k_edm_mfma(EdmMfmaArgs p)
                         (v[4 * q + 2] < p.thr) | (v[4 * q + 3] < p.thr);
             }
         }
-    // near-duplicates (rare): recompute those squares directly in FP32
+    // Row i of the condensed array starts at i (i - 1) / 2.  The wave's rows
+    // lie within 64 rows of R0, so each offset from the start of row R0 fits
+    // in 32 bits and every store takes the one wave-uniform base.
+    char *const ob = (char *)(p.out + (uint64_t)R0 * (uint64_t)(R0 - 1) / 2);
+    // every pair of the block is in the domain unless it touches the
+    // diagonal or the last row
+    if ((C0 + 63 < R0) && (R0 + 63 < n))
+        edm_store_block<true>(ob, acc, R0, C0 + lr, n, l);
+    else
+        edm_store_block<false>(ob, acc, R0, C0 + lr, n, l);
+    // near-duplicates (rare): recompute those squares directly in FP32 and
+    // store them over the values just written (same lane, same address)
     if (__any(near)) {
+        uint64_t m = 0;
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
             for (int b = 0; b < 2; ++b)
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int32_t i = R0 + 32 * a + 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
-                    const int32_t j = C0 + 32 * b + lr;
-                    if (acc[a][b][r] < p.thr && i < n && j < i)
-                        acc[a][b][r] = direct_d2(p.x, p.ldx, p.d, i, j);
-                }
+                for (int r = 0; r < 16; ++r)
+                    if (acc[a][b][r] < p.thr) m |= 1ull << (32 * a + 16 * b + r);
+        while (m) {
+            const int k = __builtin_ctzll(m);
+            m &= m - 1;
+            const int a = k >> 5, b = (k >> 4) & 1, r = k & 15;
+            const int32_t i = R0 + 32 * a + 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
+            const int32_t j = C0 + 32 * b + lr;
+            if (i < n && j < i)
+                *(float *)(ob + (((uint32_t)((i - R0) * (i + R0 - 1)) / 2u + (uint32_t)j) << 2)) =
+                    __builtin_amdgcn_sqrtf(direct_d2(p.x, p.ldx, p.d, i, j));
+        }
     }
-    // every pair of the wave's block is in the domain unless the block
-    // touches the diagonal or the last row
-    const bool full = (C0 + 63 < R0) && (R0 + 63 < n);
+}
+
+// Distances of the wave's 64 x 64 block into the tile buffer D (row stride
+// kDStride floats, tile coordinates): d^2 from the Gram block and the norms
+// as in edm_epilogue, near-duplicates recomputed directly in FP32.
+constexpr int kDStride = kEdmTile + 8;  // floats: rows 4 apart fall 32 banks apart
+
+__device__ __forceinline__ void edm_distances_to_lds(const EdmMfmaArgs &p, f32x16 (&acc)[2][2],
+                                                     const float *sN, int wr, int wc, int32_t R0,
+                                                     int32_t C0, int l, float *D)
+{
+    const int lr = l & 31;
+    const int32_t n = p.n;
+    bool near = false;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            int32_t i = R0 + 32 * a + 8 * q + 4 * (l >> 5);
-            uint64_t base = (uint64_t)i * (uint64_t)(i - 1) / 2;  // start of row i
+            const float4 ni = *(const float4 *)&sN[64 * wr + 32 * a + 8 * q + 4 * (l >> 5)];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-#pragma unroll
-                for (int b = 0; b < 2; ++b) {
-                    const int32_t j = C0 + 32 * b + lr;
-                    const float d2 = acc[a][b][4 * q + u];
-                    if (full || (i < n && j < i))
-                        p.out[base + j] = __builtin_amdgcn_sqrtf(fmaxf(d2, 0.f));
-                }
-                base += (uint64_t)i;  // start of row i + 1
-                ++i;
+            for (int b = 0; b < 2; ++b) {
+                const float nj = sN[kEdmTile + 64 * wc + 32 * b + lr];
+                f32x16 &v = acc[a][b];
+                v[4 * q + 0] = __builtin_fmaf(-2.f, v[4 * q + 0], ni.x + nj);
+                v[4 * q + 1] = __builtin_fmaf(-2.f, v[4 * q + 1], ni.y + nj);
+                v[4 * q + 2] = __builtin_fmaf(-2.f, v[4 * q + 2], ni.z + nj);
+                v[4 * q + 3] = __builtin_fmaf(-2.f, v[4 * q + 3], ni.w + nj);
+                near |= (v[4 * q + 0] < p.thr) | (v[4 * q + 1] < p.thr) |
+                        (v[4 * q + 2] < p.thr) | (v[4 * q + 3] < p.thr);
             }
         }
+    float *const Dw = D + (64 * wr + 4 * (l >> 5)) * kDStride + 64 * wc + lr;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                Dw[(32 * a + 8 * (r >> 2) + (r & 3)) * kDStride + 32 * b] =
+                    fmaxf(__builtin_amdgcn_sqrtf(acc[a][b][r]), 0.f);
+    if (__any(near)) {
+        uint64_t m = 0;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int r = 0; r < 16; ++r)
+                    if (acc[a][b][r] < p.thr) m |= 1ull << (32 * a + 16 * b + r);
+        while (m) {
+            const int k = __builtin_ctzll(m);
+            m &= m - 1;
+            const int a = k >> 5, b = (k >> 4) & 1, r = k & 15;
+            const int dr = 32 * a + 8 * (r >> 2) + (r & 3);
+            const int32_t i = R0 + dr + 4 * (l >> 5);
+            const int32_t j = C0 + 32 * b + lr;
+            if (i < n && j < i)
+                Dw[dr * kDStride + 32 * b] = __builtin_amdgcn_sqrtf(direct_d2(p.x, p.ldx, p.d, i, j));
+        }
+    }
+}
+
+// Stores rows 32 w .. 32 w + 31 of the tile's distances from D (row point RW
+// + row, column point CW + column).  A store covers two rows, 32 lanes with
+// four consecutive pairs each: a 512-byte run of the condensed array per
+// row.  Row i starts at i (i - 1) / 2, any word, hence the 4-byte aligned
+// vector type.
+typedef float f32x4u __attribute__((ext_vector_type(4), aligned(4)));
+
+__device__ __forceinline__ void edm_store_tile_rows(const EdmMfmaArgs &p, const float *D,
+                                                    int32_t RW, int32_t CW, int w, int l)
+{
+    const int32_t n = p.n;
+    const int q = l & 31, hl = l >> 5;
+    const int32_t j0 = CW + 4 * q;
+#pragma unroll
+    for (int r = 0; r < 32; r += 8) {
+        f32x4 v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            v[k] = *(const f32x4 *)&D[(32 * w + r + 2 * k + hl) * kDStride + 4 * q];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int32_t i = RW + 32 * w + r + 2 * k + hl;
+            if (i >= n) continue;
+            float *const orow = p.out + (uint64_t)i * (uint64_t)(i - 1) / 2 + j0;
+            if (j0 + 3 < i) {
+                *(f32x4u *)orow = v[k];
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (j0 + e < i) orow[e] = v[k][e];
+            }
+        }
+    }
+}
+
+// One workgroup per tile of the plan's grid (every map).
+template <int MAP, bool SPLIT>
+__global__ void __launch_bounds__(256) k_edm_mfma(EdmMfmaArgs p)
+{
+    constexpr int PLANES = SPLIT ? 4 : 2;
+    // the operand planes, and without the split, after the last product,
+    // the tile's distances
+    constexpr int kLdsBytes = SPLIT ? PLANES * kPlaneBytes : kEdmTile * kDStride * 4;
+    static_assert(kEdmTile * kDStride * 4 >= PLANES * kPlaneBytes || SPLIT, "LDS layout");
+    __shared__ __attribute__((aligned(16))) unsigned char lds[kLdsBytes];
+    __shared__ __attribute__((aligned(16))) float sN[2 * kEdmTile];
+    __bf16 *sAh = (__bf16 *)lds;
+    __bf16 *sBh = (__bf16 *)(lds + kPlaneBytes);
+    __bf16 *sAl = (__bf16 *)(lds + 2 * kPlaneBytes);  // split only
+    __bf16 *sBl = (__bf16 *)(lds + 3 * kPlaneBytes);
+
+    int32_t bi, bj;
+    if (!tile_of_block<MAP>(p.g, bi, bj)) return;
+    const int t = threadIdx.x, l = t & 63;
+    const int w = __builtin_amdgcn_readfirstlane(t >> 6);  // wave-uniform
+    const int32_t n = p.n, dp = p.dp;
+    const int32_t RW = 1 + bi * kEdmTile;  // first row point of the tile
+    const int32_t CW = bj * kEdmTile;      // first column point of the tile
+
+    EdmStage<SPLIT> st;
+    edm_stage_load<SPLIT>(p, RW, CW, 0, st, t);
+    // norms of the tile's row and column points
+    {
+        const int32_t q = t < kEdmTile ? RW + t : CW + (t - kEdmTile);
+        sN[t] = p.norms[min(q, n - 1)];
+    }
+
+    const int wr = w >> 1, wc = w & 1;
+    const int lr = l & 31, lk = (l >> 5) * 8;
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
+
+    for (int32_t k0 = 0; k0 < dp; k0 += kKC) {
+        const int32_t kn = min(kKC, dp - k0);  // multiple of 16
+        edm_stage_store<SPLIT>(st, sAh, sBh, sAl, sBl, t);
+        lds_barrier();
+        if (k0 + kKC < dp) edm_stage_load<SPLIT>(p, RW, CW, k0 + kKC, st, t);  // in flight
+        edm_mfma_chunk<SPLIT>(acc, sAh, sBh, sAl, sBl, kn, wr, wc, lr, lk);
+        lds_barrier();
+    }
+
+    const int32_t R0 = RW + 64 * wr, C0 = CW + 64 * wc;  // this wave's 64 x 64 block
+    if constexpr (SPLIT) {
+        // each wave stores straight from the MFMA layout and ends
+        if (R0 >= n || C0 >= R0 + 63) return;  // no pair j < i < n here (no barrier follows)
+        edm_epilogue(p, acc, sN, wr, wc, R0, C0, l);
+    } else {
+        // distances through LDS (the planes are free after the last barrier),
+        // then stored as row runs; a wave with no pair j < i < n in its block
+        // only takes part in the barrier and the row stores
+        float *const D = (float *)lds;
+        if (R0 < n && C0 < R0 + 63) edm_distances_to_lds(p, acc, sN, wr, wc, R0, C0, l, D);
+        lds_barrier();
+        edm_store_tile_rows(p, D, RW, CW, w, l);
+    }
 }
 
 template <int MAP>

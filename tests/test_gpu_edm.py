@@ -171,16 +171,17 @@ def test_edm_mfma_argument_errors():
 
 
 @pytest.mark.slow
-def test_edm_bf16x3_full_size_sampled_rows():
+@pytest.mark.parametrize("flags", [0, 1])
+def test_edm_bf16x3_full_size_sampled_rows(flags):
     """n = 65536, d = 128 with 1 % near-duplicates: 24 random rows plus the
     rows of 64 duplicate pairs, against the FP64 oracle; max relative error
-    reported and held to 1e-3."""
+    reported and held to 1e-3.  Flags 1: the XCD swizzle."""
     import torch
     tm = _tm()
     n, d = 65536, 128
     X, pairs = inputs.points(n, d)
-    p = tm.Plan(n, 128, "lambda", include_diag=False)
-    note("edm bf16x3 full", n, d)
+    p = tm.Plan(n, 128, "lambda", include_diag=False, flags=flags)
+    note("edm bf16x3 full", n, d, flags)
     out = _edm_mfma(tm, p, X, tm.EDM_BF16X3)
     torch.cuda.synchronize()
     rng = np.random.default_rng(16)

@@ -68,7 +68,8 @@ def test_collide_errors():
 
 @pytest.mark.slow
 @pytest.mark.parametrize("dim", [1, 3])
-@pytest.mark.parametrize("map_name,tile", [("lambda", 64), ("bb", 64), ("rb", 128), ("utm", 16)])
+@pytest.mark.parametrize("map_name,tile", [("lambda", 64), ("bb", 64), ("rb", 128), ("rec", 128),
+                                           ("utm", 16)])
 def test_collide_full_size_sampled(dim, map_name, tile):
     """n = 131072, about 4 overlaps per sphere: counts of sampled spheres
     (ends, tile borders, random) from the oracle one by one, and the total

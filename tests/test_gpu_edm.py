@@ -171,11 +171,12 @@ def test_edm_mfma_argument_errors():
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("flags", [0, 1])
+@pytest.mark.parametrize("flags", [0, 1, 8, 16, 17])
 def test_edm_bf16x3_full_size_sampled_rows(flags):
     """n = 65536, d = 128 with 1 % near-duplicates: 24 random rows plus the
     rows of 64 duplicate pairs, against the FP64 oracle; max relative error
-    reported and held to 1e-3.  Flags 1: the XCD swizzle."""
+    reported and held to 1e-3.  Flags: the lambda variants the autotuner
+    times (plain, XCD swizzle, reverse, pairs, swizzle + pairs)."""
     import torch
     tm = _tm()
     n, d = 65536, 128

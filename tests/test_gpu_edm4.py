@@ -60,8 +60,9 @@ def test_edm4_rejects_unaligned_points():
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("map_name,tile", [("lambda", 64), ("rb", 64), ("utm", 64)])
-def test_edm4_full_size_sampled_rows(map_name, tile):
+@pytest.mark.parametrize("map_name,tile,flags", [("lambda", 128, 16), ("lambda", 64, 0),
+                                                 ("bb", 64, 0), ("rb", 64, 0), ("utm", 64, 0)])
+def test_edm4_full_size_sampled_rows(map_name, tile, flags):
     """n = 32768, the launch the benchmark times: whole rows sampled at the
     start, the end, tile borders and at random, bit-exact; upper cells of the
     sampled rows keep their pre-fill."""
@@ -69,9 +70,9 @@ def test_edm4_full_size_sampled_rows(map_name, tile):
     tm = _tm()
     n = 32768
     P = inputs.points4(n)
-    note("edm4 full", map_name, tile, n)
+    note("edm4 full", map_name, tile, flags, n)
     c = torch.full((n, n), -1.0, device="cuda")
-    tm.Plan(n, tile, map_name).elementwise(tm.OP_EDM4_F32, dev(P), None, c, ld=n)
+    tm.Plan(n, tile, map_name, flags=flags).elementwise(tm.OP_EDM4_F32, dev(P), None, c, ld=n)
     rng = np.random.default_rng(9)
     rows = sorted({0, 1, 63, 64, 65, n // 2, n - 65, n - 2, n - 1,
                    *rng.integers(0, n, 24).tolist()})

@@ -110,18 +110,21 @@ def full_inputs():
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("map_name,tile", [("lambda", 32), ("bb", 32), ("lambda", 16)])
-def test_axpyt_full_size_sampled_rows(full_inputs, map_name, tile):
-    """n = 32768 (12 GiB of operands), the configuration the benchmark times;
-    64 sampled rows plus the first and last rows are checked bit for bit
-    against the oracle, and the upper part of those rows is untouched."""
+@pytest.mark.parametrize("map_name,tile,flags", [("lambda", 128, 16), ("lambda", 64, 16),
+                                                 ("bb", 128, 0), ("lambda", 32, 0), ("bb", 32, 0),
+                                                 ("lambda", 16, 0)])
+def test_axpyt_full_size_sampled_rows(full_inputs, map_name, tile, flags):
+    """n = 32768 (12 GiB of operands), the configuration the benchmark times
+    (lambda, tile 128, pairs order) and its neighbours; 64 sampled rows plus
+    the first and last rows are checked bit for bit against the oracle, and
+    the upper part of those rows is untouched."""
     import torch
     tm = _tm()
     n, a, X, Y, xd, yd = full_inputs
-    note("axpyt full", map_name, tile, n)
+    note("axpyt full", map_name, tile, flags, n)
     fill = np.float32(-7.5)
     c = torch.full((n, n), float(fill), dtype=torch.float32, device="cuda")
-    p = tm.Plan(n, tile, map_name)
+    p = tm.Plan(n, tile, map_name, flags=flags)
     p.elementwise(tm.OP_AXPYT_F32, xd, yd, c, ld=n, a=float(a))
     torch.cuda.synchronize()
     rows = np.concatenate([[0, 1, n - 1], np.random.default_rng(14).choice(n, 64, replace=False)])

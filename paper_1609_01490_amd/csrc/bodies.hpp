@@ -487,7 +487,10 @@ __device__ __forceinline__ void lds_read_rows(const float *src, float (&dst)[RB]
 // condensed out[i (i - 1) / 2 + j] for j < i < n.  Each lane holds an RB x CB
 // block: RB consecutive rows (one vector read from LDS per step) against CB
 // columns TX apart (so that the 16 lanes of a row store consecutive words).
-template <int TILE>
+// HOIST: every staging load of a step is issued before the first is stored
+// (clamped addresses, masked values), so that their latencies overlap; the
+// batched kernel keeps the load-store loop to hold its registers down.
+template <int TILE, bool HOIST = true>
 __device__ __forceinline__ void edm_f32_tile_body(const EdmTile &p, int32_t bi, int32_t bj,
                                                   float *lds)
 {
@@ -507,12 +510,34 @@ __device__ __forceinline__ void edm_f32_tile_body(const EdmTile &p, int32_t bi, 
         for (int c = 0; c < S::CB; ++c) acc[a][c] = 0.f;
 
     for (int32_t k0 = 0; k0 < d; k0 += S::K) {
-        for (int idx = threadIdx.x; idx < TILE * S::K; idx += S::NT) {
-            const int row = idx / S::K, kk = idx % S::K;
-            const int32_t k = k0 + kk;
-            const int32_t gi = ri0 + row, gj = cj0 + row;
-            XI[kk * S::LD + row] = (gi < n && k < d) ? p.x[(int64_t)gi * ldx + k] : 0.f;
-            XJ[kk * S::LD + row] = (gj < n && k < d) ? p.x[(int64_t)gj * ldx + k] : 0.f;
+        if constexpr (HOIST) {
+            constexpr int PER = TILE * S::K / S::NT;  // staged values per lane and block
+            static_assert(PER * S::NT == TILE * S::K, "staging shape");
+            float vi[PER], vj[PER];
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const int idx = threadIdx.x + S::NT * u;
+                const int row = idx / S::K, kk = idx % S::K;
+                const int32_t k = min(k0 + kk, d - 1);
+                vi[u] = p.x[(int64_t)min(ri0 + row, n - 1) * ldx + k];
+                vj[u] = p.x[(int64_t)min(cj0 + row, n - 1) * ldx + k];
+            }
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const int idx = threadIdx.x + S::NT * u;
+                const int row = idx / S::K, kk = idx % S::K;
+                const bool kin = k0 + kk < d;
+                XI[kk * S::LD + row] = (ri0 + row < n && kin) ? vi[u] : 0.f;
+                XJ[kk * S::LD + row] = (cj0 + row < n && kin) ? vj[u] : 0.f;
+            }
+        } else {
+            for (int idx = threadIdx.x; idx < TILE * S::K; idx += S::NT) {
+                const int row = idx / S::K, kk = idx % S::K;
+                const int32_t k = k0 + kk;
+                const int32_t gi = ri0 + row, gj = cj0 + row;
+                XI[kk * S::LD + row] = (gi < n && k < d) ? p.x[(int64_t)gi * ldx + k] : 0.f;
+                XJ[kk * S::LD + row] = (gj < n && k < d) ? p.x[(int64_t)gj * ldx + k] : 0.f;
+            }
         }
         __syncthreads();
 #pragma unroll 4

@@ -199,3 +199,50 @@ def test_edm_bf16x3_full_size_sampled_rows(flags):
     assert worst <= 1e-3
     del out
     torch.cuda.empty_cache()
+
+
+@pytest.mark.slow
+def test_edm_bf16x3_4096_sampled_rows():
+    """The distance-map workload's own accuracy check: n = 65536, d = 128
+    with 1 % near-duplicates (jitter 1e-4), BF16X3 on the matrix cores with
+    the FP32 recompute below d^2 = 1e-2; 4096 seeded random rows plus the
+    row of every near-duplicate pair (all 655), whole rows, against the FP64
+    oracle.  Max relative error printed and held to 1e-3; the near pairs
+    themselves to the FP32 direct bound."""
+    import concurrent.futures as cf
+    import torch
+    tm = _tm()
+    n, d = 65536, 128
+    X, pairs = inputs.points(n, d)
+    p = tm.Plan(n, 128, "lambda", include_diag=False, flags=tm.FLAG_XCD_SWIZZLE)
+    note("edm bf16x3 4096 rows", n, d)
+    out = _edm_mfma(tm, p, X, tm.EDM_BF16X3)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(4096)
+    rows = sorted(set(rng.choice(np.arange(1, n), 4096, replace=False).tolist())
+                  | set(pairs.max(axis=1).tolist()))
+    chunks = [rows[k::16] for k in range(16)]
+    with cf.ThreadPoolExecutor(8) as ex:  # the oracle's C loop runs without the GIL
+        exp = dict(zip([r for c in chunks for r in c],
+                       [e for es in ex.map(lambda c: oracle.edm_rows(X, c), chunks) for e in es]))
+    worst, worst_near = 0.0, 0.0
+    near = {}
+    for a, b in pairs.tolist():
+        near.setdefault(max(a, b), []).append(min(a, b))
+    for k, r in enumerate(rows):
+        g = out[r * (r - 1) // 2: r * (r - 1) // 2 + r].cpu().numpy().astype(np.float64)
+        e = exp[r]
+        nz = e > 0
+        worst = max(worst, float((np.abs(g[nz] - e[nz]) / e[nz]).max()))
+        for j in near.get(r, ()):
+            if e[j] > 0 and e[j] ** 2 < 1e-2:
+                worst_near = max(worst_near, abs(g[j] - e[j]) / e[j])
+        if k % 1024 == 0:
+            print(f"[edm 4096 rows] {k}/{len(rows)} rows checked", flush=True)
+    print(f"[edm bf16x3 n={n} d={d}] max relative error {worst:.3e} over {len(rows)} rows "
+          f"({len(near)} near-duplicate pairs: {worst_near:.3e})", flush=True)
+    assert worst <= 1e-3
+    assert worst_near <= _fp32_bound(d)
+    del out
+    torch.cuda.empty_cache()
+

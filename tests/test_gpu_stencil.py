@@ -204,6 +204,51 @@ def test_life_temporal_full_size_windows():
         assert not got[~dom].any(), (r, c)
 
 
+def _gol_whole(g, n, steps, bands=16):
+    """The oracle's final grid of the whole domain, computed in row bands
+    (each from its light cone: the band plus `steps` rows and columns
+    around it) on a thread pool; the oracle's C loop runs without the GIL."""
+    import concurrent.futures as cf
+    h = -(-n // bands)
+
+    def band(r):
+        hh = min(h, n - r)
+        w = min(n, r + hh)  # columns j <= i < r + hh
+        win = oracle.gol(g, n, steps, r - steps, -steps, hh + 2 * steps, w + 2 * steps)
+        return r, win[steps:steps + hh, steps:steps + w]
+
+    out = np.zeros((n, n), dtype=np.uint8)
+    with cf.ThreadPoolExecutor(16) as ex:
+        for r, blk in ex.map(band, range(0, n, h)):
+            out[r:r + blk.shape[0], :blk.shape[1]] = blk
+            print(f"[life whole grid] rows {r}..{r + blk.shape[0]} from the oracle", flush=True)
+    return out
+
+
+@pytest.mark.slow
+def test_life_temporal_full_size_whole_grid():
+    """The benchmarked launch (n = 16384, density 0.3, 100 generations,
+    lambda tile 64 with the XCD swizzle and temporal blocking: the
+    bit-sliced kernel): the whole final grid, bit for bit, against the
+    oracle's."""
+    import torch
+    tm = _tm()
+    n, steps = 16384, 100
+    g = inputs.life(n, 0.3)
+    note("life temporal whole grid", n, steps)
+    cur = dev(g)
+    nxt = torch.zeros_like(cur)
+    p = tm.Plan(n, 64, "lambda", flags=tm.FLAG_LIFE_TEMPORAL | tm.FLAG_XCD_SWIZZLE)
+    p.stencil(cur, nxt, steps)
+    torch.cuda.synchronize()
+    got = cur.cpu().numpy()
+    del cur, nxt
+    torch.cuda.empty_cache()
+    exp = _gol_whole(g, n, steps)
+    bad = np.argwhere(got != exp)
+    assert bad.shape[0] == 0, (bad.shape[0], bad[:4].tolist())
+
+
 @pytest.mark.parametrize("steps", [1, 4, 7])
 def test_life_bit_sliced_grid_windows(steps):
     """A grid large enough (>= 16384 tiles of 64 x 64) for the bit-sliced

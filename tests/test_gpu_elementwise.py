@@ -143,6 +143,42 @@ def test_axpyt_full_size_sampled_rows(full_inputs, map_name, tile, flags):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.slow
+def test_axpyt_full_size_whole_triangle(full_inputs):
+    """The benchmarked launch (n = 32768, lambda, tile 128, pairs order):
+    every cell of the lower triangle bit for bit against the oracle, which
+    computes 1024-row bands on a thread pool (its C loop runs without the
+    GIL); every cell above the diagonal keeps its pre-fill."""
+    import concurrent.futures as cf
+    import torch
+    tm = _tm()
+    n, a, X, Y, xd, yd = full_inputs
+    note("axpyt whole triangle", n)
+    fill = np.float32(-7.5)
+    c = torch.full((n, n), float(fill), dtype=torch.float32, device="cuda")
+    tm.Plan(n, 128, "lambda", flags=tm.FLAG_ORDER_PAIRS).elementwise(
+        tm.OP_AXPYT_F32, xd, yd, c, ld=n, a=float(a))
+    torch.cuda.synchronize()
+    got = c.cpu().numpy()
+    del c
+    torch.cuda.empty_cache()
+
+    def band(r0):
+        r1 = min(n, r0 + 1024)
+        exp = np.empty((r1 - r0, n), dtype=np.float32)
+        oracle.c1(a, X, Y, exp, r0=r0, r1=r1)
+        low = np.arange(n)[None, :] <= np.arange(r0, r1)[:, None]
+        g = got[r0:r1]
+        bad = int((g.view(np.uint32)[low] != exp.view(np.uint32)[low]).sum())
+        return bad, int((g[~low] != fill).sum())
+
+    with cf.ThreadPoolExecutor(16) as ex:
+        res = list(ex.map(band, range(0, n, 1024)))
+    print(f"[axpyt whole triangle] {len(res)} bands checked", flush=True)
+    assert sum(r[0] for r in res) == 0, [r[0] for r in res]
+    assert sum(r[1] for r in res) == 0, [r[1] for r in res]
+
+
 def test_stream_add_probe_is_exact():
     import torch
     tm = _tm()

@@ -83,3 +83,38 @@ def test_edm4_full_size_sampled_rows(map_name, tile, flags):
         assert (got[r + 1:] == -1.0).all(), r
     del c
     torch.cuda.empty_cache()
+
+
+@pytest.mark.slow
+def test_edm4_full_size_whole_triangle():
+    """The fastest launch of the four-feature benchmark (n = 32768, lambda,
+    tile 128, pairs order): every cell of the triangle bit for bit against
+    the oracle (1024-row bands on a thread pool), every cell above the
+    diagonal keeps its pre-fill."""
+    import concurrent.futures as cf
+    import torch
+    tm = _tm()
+    n = 32768
+    P = inputs.points4(n)
+    note("edm4 whole triangle", n)
+    c = torch.full((n, n), -1.0, device="cuda")
+    tm.Plan(n, 128, "lambda", flags=tm.FLAG_ORDER_PAIRS).elementwise(
+        tm.OP_EDM4_F32, dev(P), None, c, ld=n)
+    torch.cuda.synchronize()
+    got = c.cpu().numpy()
+    del c
+    torch.cuda.empty_cache()
+
+    def band(r0):
+        r1 = min(n, r0 + 1024)
+        exp = oracle.edm4(P, r0=r0, r1=r1)
+        low = np.arange(n)[None, :] <= np.arange(r0, r1)[:, None]
+        g = got[r0:r1]
+        return (int((g.view(np.uint32)[low] != exp.view(np.uint32)[low]).sum()),
+                int((g[~low] != -1.0).sum()))
+
+    with cf.ThreadPoolExecutor(16) as ex:
+        res = list(ex.map(band, range(0, n, 1024)))
+    print(f"[edm4 whole triangle] {len(res)} bands checked", flush=True)
+    assert sum(r[0] for r in res) == 0, [r[0] for r in res]
+    assert sum(r[1] for r in res) == 0, [r[1] for r in res]

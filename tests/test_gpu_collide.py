@@ -87,3 +87,30 @@ def test_collide_full_size_sampled(dim, map_name, tile):
     ks = sorted({0, 1, 63, 64, 65, n // 2, n - 2, n - 1, *rng.integers(0, n, 40).tolist()})
     for k in ks:
         assert got[k] == oracle.collide_one(S, dim, k), k
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("dim", [1, 3])
+def test_collide_full_size_every_sphere(dim):
+    """The fastest launch of the collision benchmark (n = 131072, REC,
+    tile 128): the overlap count of every sphere against the oracle's, which
+    counts sphere by sphere on a thread pool (its C loop runs without the
+    GIL)."""
+    import concurrent.futures as cf
+    import torch
+    tm = _tm()
+    n = 131072
+    S = np.ascontiguousarray(inputs.spheres(n, dim), dtype=np.float32)
+    note("collide every sphere", dim, n)
+    counts = torch.zeros(n, dtype=torch.int32, device="cuda")
+    tm.Plan(n, 128, "rec", include_diag=False).collide(dev(S), counts, dim=dim)
+    got = host(counts)
+
+    def part(k0):
+        return [oracle.collide_one(S, dim, k) for k in range(k0, min(n, k0 + 4096))]
+
+    with cf.ThreadPoolExecutor(16) as ex:
+        exp = np.array([c for cs in ex.map(part, range(0, n, 4096)) for c in cs], dtype=np.int32)
+    print(f"[collide dim {dim}] {n} spheres, {int(exp.sum()) // 2} overlapping pairs", flush=True)
+    bad = np.flatnonzero(got != exp)
+    assert bad.size == 0, (bad.size, bad[:8].tolist())

@@ -367,7 +367,7 @@ def bench_tetra(tm, torch, timer, n=8192):
     total = torch.zeros(1, dtype=torch.int64, device="cuda")
     sink = torch.zeros(1, dtype=torch.int32, device="cuda")
     tri_ms, dummy_us = {}, {}
-    for t_ in (8, 16, 32):
+    for t_ in (8, 16, 32, 64):
         for name, mp, fl in (("bb", "bb", 0), ("lambda", "lambda", 0),
                              ("lambda_f64", "lambda", tm.FLAG_SQRT_F64)):
             p = tm.TetPlan(n, t_, mp, strict=True, flags=fl)

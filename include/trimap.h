@@ -161,7 +161,7 @@ tri_status tri_launch_dummy(const tri_plan *plan, int32_t target, int32_t *sink,
 /* ---- Tetrahedral domains (Section 6) ------------------------------------- */
 
 /* A plan for the tetrahedron of n points tiled in rho^3 tiles (rho in {8,
- * 16, 32}): tiles (i, j, k), 0 <= i <= j <= k < m, m = ceil(n_eff / rho),
+ * 16, 32, 64}): tiles (i, j, k), 0 <= i <= j <= k < m, m = ceil(n_eff / rho),
  * Tet(m) = m(m+1)(m+2)/6 of them.  strict = 1 covers the triples
  * a > b > c of n points (the non-strict tetrahedron of side n_eff = n - 2,
  * shifted: (a, b, c) = (k + 2, j + 1, i) per point), strict = 0 the triples

@@ -19,6 +19,7 @@
 // side n - 2 shifted: (a, b, c) = (k + 2, j + 1, i), as the strict triangle
 // is the non-strict one of side n - 1 shifted by one row.
 #include <new>
+#include <type_traits>
 
 #include "common.hpp"
 #include "maps.hpp"
@@ -195,13 +196,14 @@ struct TriShape {
 template <int MAP, int TILE>
 __global__ void __launch_bounds__((TriShape<TILE>::NT)) k_triangles(TriArgs p, int32_t strict)
 {
-    static_assert(TILE == 8 || TILE == 16 || TILE == 32, "mask width");
+    static_assert(TILE == 8 || TILE == 16 || TILE == 32 || TILE == 64, "mask width");
     constexpr int NT = TriShape<TILE>::NT;
+    using M = typename std::conditional<TILE == 64, uint64_t, uint32_t>::type;  // a row of a relation
     int32_t ti, tj, tk;
     if (!tet_of_block<MAP>(p.g, ti, tj, tk)) return;
 
     __shared__ f4 pts[3][TILE];          // 0: a (tile k), 1: b (tile j), 2: c (tile i)
-    __shared__ uint32_t mask[3][TILE];   // 0: a-b over b, 1: a-c over c, 2: b-c over c
+    __shared__ M mask[3][TILE];          // 0: a-b over b, 1: a-c over c, 2: b-c over c
     const int32_t n = p.n;
     const int32_t a0 = 2 * strict + tk * TILE, b0 = strict + tj * TILE, c0 = ti * TILE;
     const float nan = __builtin_nanf("");
@@ -225,9 +227,10 @@ __global__ void __launch_bounds__((TriShape<TILE>::NT)) k_triangles(TriArgs p, i
         const bool hit = near3(pts[rs][row], pts[cs][col], p.r2);
         const uint64_t bal = __ballot(hit);
         if (l % TILE == 0) {
-            const uint32_t bits = (uint32_t)(bal >> (l - l % TILE)) &
-                                  (TILE == 32 ? 0xFFFFFFFFu : ((1u << TILE) - 1u));
-            mask[s][row] = bits;
+            if constexpr (TILE == 64)
+                mask[s][row] = bal;
+            else
+                mask[s][row] = (M)((bal >> (l - l % TILE)) & ((1ull << TILE) - 1ull));
         }
     }
     __syncthreads();
@@ -240,15 +243,15 @@ __global__ void __launch_bounds__((TriShape<TILE>::NT)) k_triangles(TriArgs p, i
         // (a = tb + 2 + ..., b = tb + 1 + ... on the shifted tetrahedron)
         if (same_kj && ta < tb) continue;
         if (!((mask[0][ta] >> tb) & 1u)) continue;
-        uint32_t m = mask[1][ta] & mask[2][tb];
-        if (same_ji) m &= (tb == 31) ? 0xFFFFFFFFu : ((2u << tb) - 1u);  // c <= b in the tile
+        M m = mask[1][ta] & mask[2][tb];
+        if (same_ji) m &= (tb == TILE - 1) ? ~(M)0 : (((M)2 << tb) - 1);  // c <= b in the tile
         if (!m) continue;
-        const int c = __builtin_popcount(m);
+        const int c = __builtin_popcountll((uint64_t)m);
         atomicAdd(&p.counts[a0 + ta], c);
         atomicAdd(&p.counts[b0 + tb], c);
         atomicAdd(p.total, (unsigned long long)c);
         while (m) {
-            const int tc = __builtin_ctz(m);
+            const int tc = __builtin_ctzll((uint64_t)m);
             m &= m - 1;
             atomicAdd(&p.counts[c0 + tc], 1);
         }
@@ -272,6 +275,7 @@ static bool triangles_tile(const tri_tet *p, const TriArgs &a, hipStream_t s)
     case 8: k_triangles<MAP, 8><<<grid, TriShape<8>::NT, 0, s>>>(a, st); return true;
     case 16: k_triangles<MAP, 16><<<grid, TriShape<16>::NT, 0, s>>>(a, st); return true;
     case 32: k_triangles<MAP, 32><<<grid, TriShape<32>::NT, 0, s>>>(a, st); return true;
+    case 64: k_triangles<MAP, 64><<<grid, TriShape<64>::NT, 0, s>>>(a, st); return true;
     }
     return false;
 }
@@ -310,8 +314,8 @@ tri_status tri_tet_plan(tri_tet **out, int64_t n, int tile, int map, int strict,
     *out = nullptr;
     if (n < 0) return fail(TRI_E_INVAL, "tri_tet_plan: n = %lld < 0", (long long)n);
     if (n >= (1ll << 21)) return fail(TRI_E_RANGE, "tri_tet_plan: n = %lld >= 2^21", (long long)n);
-    if (tile != 8 && tile != 16 && tile != 32)
-        return fail(TRI_E_INVAL, "tri_tet_plan: tile = %d not in {8,16,32}", tile);
+    if (tile != 8 && tile != 16 && tile != 32 && tile != 64)
+        return fail(TRI_E_INVAL, "tri_tet_plan: tile = %d not in {8,16,32,64}", tile);
     if (map != TRI_MAP_BB && map != TRI_MAP_LAMBDA)
         return fail(TRI_E_UNSUPPORTED, "tri_tet_plan: map = %d (BB or lambda)", map);
     if (strict != 0 && strict != 1) return fail(TRI_E_INVAL, "tri_tet_plan: strict = %d", strict);
@@ -441,11 +445,13 @@ tri_status tri_tet_dummy(const tri_tet *p, int32_t target, int32_t *sink, void *
     if (p->map == TRI_MAP_BB) {
         if (p->tile == 8) TET_DUMMY(MAP_BB, 8);
         else if (p->tile == 16) TET_DUMMY(MAP_BB, 16);
-        else TET_DUMMY(MAP_BB, 32);
+        else if (p->tile == 32) TET_DUMMY(MAP_BB, 32);
+        else TET_DUMMY(MAP_BB, 64);
     } else {
         if (p->tile == 8) TET_DUMMY(MAP_LAMBDA, 8);
         else if (p->tile == 16) TET_DUMMY(MAP_LAMBDA, 16);
-        else TET_DUMMY(MAP_LAMBDA, 32);
+        else if (p->tile == 32) TET_DUMMY(MAP_LAMBDA, 32);
+        else TET_DUMMY(MAP_LAMBDA, 64);
     }
 #undef TET_DUMMY
     TRI_HIP(hipGetLastError());

@@ -19,7 +19,7 @@ def _tm():
 
 
 @pytest.mark.parametrize("map_name", ["bb", "lambda"])
-@pytest.mark.parametrize("tile", [8, 16, 32])
+@pytest.mark.parametrize("tile", [8, 16, 32, 64])
 def test_tet_dump_equals_oracle(map_name, tile):
     tm = _tm()
     for n, strict in ((1, False), (tile, False), (5 * tile - 3, False), (13 * tile, False),
@@ -77,11 +77,11 @@ def _lattice(n, seed):
 
 
 @pytest.mark.parametrize("map_name", ["bb", "lambda"])
-@pytest.mark.parametrize("tile", [8, 16, 32])
+@pytest.mark.parametrize("tile", [8, 16, 32, 64])
 def test_triangles_bit_exact(map_name, tile):
     import torch
     tm = _tm()
-    for n in (1, 2, 3, 10, 33, 100, 257, 300):
+    for n in (1, 2, 3, 10, 33, 100, 257, 300, 700):
         p = tm.TetPlan(n, tile, map_name, strict=True)
         P, r2 = inputs.points3(n, mean_degree=12.0, seed=7000 + n)
         for case, (arr, rr) in (("random", (P, r2)), ("lattice", _lattice(n, n))):
@@ -95,7 +95,7 @@ def test_triangles_bit_exact(map_name, tile):
 
 
 @pytest.mark.parametrize("map_name", ["bb", "lambda"])
-@pytest.mark.parametrize("tile", [8, 16])
+@pytest.mark.parametrize("tile", [8, 16, 64])
 def test_tet_dummy_reaches_every_sum(map_name, tile):
     import torch
     tm = _tm()
@@ -111,7 +111,8 @@ def test_tet_dummy_reaches_every_sum(map_name, tile):
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("map_name,tile", [("lambda", 32), ("bb", 32), ("lambda", 16)])
+@pytest.mark.parametrize("map_name,tile", [("lambda", 64), ("bb", 64), ("lambda", 32), ("bb", 32),
+                                           ("lambda", 16)])
 def test_triangles_full_size(map_name, tile):
     """n = 8192 points, about 8 neighbours each: every per-point count and
     the total equal the oracle's."""

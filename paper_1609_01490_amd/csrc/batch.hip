@@ -121,7 +121,7 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch_step(BatchStepArgs a)
             lambda_tile((uint64_t)(g - lo_g), 0u, bi, bj);
             if (D.kind == TRI_KIND_EDM) {
                 const EdmTile t{D.n, D.d, D.ld, (const float *)D.a, (float *)D.b};
-                edm_f32_tile_body<TE, false>(t, bi, bj, (float *)body_lds);
+                edm_f32_tile_body<TE, kEdmStageLoop>(t, bi, bj, (float *)body_lds);
             } else {
                 const bool even = (a.step & 1) == 0;
                 const LifeTile t{D.n, D.ld, (const uint8_t *)(even ? D.a : D.b),

@@ -487,10 +487,17 @@ __device__ __forceinline__ void lds_read_rows(const float *src, float (&dst)[RB]
 // condensed out[i (i - 1) / 2 + j] for j < i < n.  Each lane holds an RB x CB
 // block: RB consecutive rows (one vector read from LDS per step) against CB
 // columns TX apart (so that the 16 lanes of a row store consecutive words).
-// HOIST: every staging load of a step is issued before the first is stored
-// (clamped addresses, masked values), so that their latencies overlap; the
-// batched kernel keeps the load-store loop to hold its registers down.
-template <int TILE, bool HOIST = true>
+// STAGE: how a step's coordinates reach LDS.  kEdmStageLoop: a load-store
+// loop (the batched kernel, to hold its registers down).  kEdmStageScalar:
+// every load of the step issued before the first is stored (clamped
+// addresses, masked values), so that their latencies overlap.
+// kEdmStageVec4: the same with 16-byte loads at 32-bit byte offsets from the
+// base (needs d and ldx multiples of 4, a 16-byte aligned x and
+// n * ldx * 4 < 2^31): a quarter of the loads and of their address
+// registers.
+enum { kEdmStageLoop = 0, kEdmStageScalar = 1, kEdmStageVec4 = 2 };
+
+template <int TILE, int STAGE = kEdmStageScalar>
 __device__ __forceinline__ void edm_f32_tile_body(const EdmTile &p, int32_t bi, int32_t bj,
                                                   float *lds)
 {
@@ -510,7 +517,36 @@ __device__ __forceinline__ void edm_f32_tile_body(const EdmTile &p, int32_t bi, 
         for (int c = 0; c < S::CB; ++c) acc[a][c] = 0.f;
 
     for (int32_t k0 = 0; k0 < d; k0 += S::K) {
-        if constexpr (HOIST) {
+        if constexpr (STAGE == kEdmStageVec4) {
+            typedef float f4v __attribute__((ext_vector_type(4)));
+            constexpr int KQ = S::K / 4;                 // vectors per staged row
+            constexpr int PER = TILE * KQ / S::NT;       // vectors per lane and block
+            static_assert(PER * S::NT == TILE * KQ, "staging shape");
+            const char *xb = (const char *)p.x;
+            const int32_t ld32 = (int32_t)ldx;
+            f4v vi[PER], vj[PER];
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const int idx = threadIdx.x + S::NT * u;
+                const int row = idx / KQ, kq = idx % KQ;
+                const int32_t k = min(k0 + 4 * kq, d - 4);
+                const int32_t ri = min(ri0 + row, n - 1), rj = min(cj0 + row, n - 1);
+                vi[u] = *(const f4v *)(xb + (uint32_t)((ri * ld32 + k) * 4));
+                vj[u] = *(const f4v *)(xb + (uint32_t)((rj * ld32 + k) * 4));
+            }
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const int idx = threadIdx.x + S::NT * u;
+                const int row = idx / KQ, kq = idx % KQ;
+                const bool kin = k0 + 4 * kq < d;
+                const bool iin = kin && ri0 + row < n, jin = kin && cj0 + row < n;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    XI[(4 * kq + e) * S::LD + row] = iin ? vi[u][e] : 0.f;
+                    XJ[(4 * kq + e) * S::LD + row] = jin ? vj[u][e] : 0.f;
+                }
+            }
+        } else if constexpr (STAGE == kEdmStageScalar) {
             constexpr int PER = TILE * S::K / S::NT;  // staged values per lane and block
             static_assert(PER * S::NT == TILE * S::K, "staging shape");
             float vi[PER], vj[PER];

@@ -37,37 +37,51 @@ struct EdmArgs {
     EdmTile t;
 };
 
-template <int MAP, int TILE>
+template <int MAP, int TILE, int STAGE>
 __global__ void __launch_bounds__(256) k_edm_f32(EdmArgs p)
 {
     int32_t bi, bj;
     if (!tile_of_block<MAP>(p.g, bi, bj)) return;
     __shared__ __attribute__((aligned(16))) float lds[EdmF32Shape<TILE>::LDS_FLOATS];
-    edm_f32_tile_body<TILE>(p.t, bi, bj, lds);
+    edm_f32_tile_body<TILE, STAGE>(p.t, bi, bj, lds);
 }
 
-template <int MAP>
+template <int MAP, int STAGE>
 static bool edm_f32_tile(const tri_plan *p, const EdmArgs &a, hipStream_t s)
 {
     const dim3 grid(p->gx, p->gy);
     switch (p->tile) {
-    case 16: k_edm_f32<MAP, 16><<<grid, 256, 0, s>>>(a); return true;
-    case 32: k_edm_f32<MAP, 32><<<grid, 256, 0, s>>>(a); return true;
-    case 64: k_edm_f32<MAP, 64><<<grid, 256, 0, s>>>(a); return true;
-    case 128: k_edm_f32<MAP, 128><<<grid, 256, 0, s>>>(a); return true;
+    case 16: k_edm_f32<MAP, 16, STAGE><<<grid, 256, 0, s>>>(a); return true;
+    case 32: k_edm_f32<MAP, 32, STAGE><<<grid, 256, 0, s>>>(a); return true;
+    case 64: k_edm_f32<MAP, 64, STAGE><<<grid, 256, 0, s>>>(a); return true;
+    case 128: k_edm_f32<MAP, 128, STAGE><<<grid, 256, 0, s>>>(a); return true;
     }
     return false;
 }
 
-static bool edm_f32(const tri_plan *p, const EdmArgs &a, hipStream_t s)
+template <int STAGE>
+static bool edm_f32_map(const tri_plan *p, const EdmArgs &a, hipStream_t s)
 {
     switch (p->map) {
-    case TRI_MAP_BB: return edm_f32_tile<MAP_BB>(p, a, s);
-    case TRI_MAP_RB: return edm_f32_tile<MAP_RB>(p, a, s);
-    case TRI_MAP_REC: return edm_f32_tile<MAP_REC>(p, a, s);
-    case TRI_MAP_LAMBDA: return edm_f32_tile<MAP_LAMBDA>(p, a, s);
+    case TRI_MAP_BB: return edm_f32_tile<MAP_BB, STAGE>(p, a, s);
+    case TRI_MAP_RB: return edm_f32_tile<MAP_RB, STAGE>(p, a, s);
+    case TRI_MAP_REC: return edm_f32_tile<MAP_REC, STAGE>(p, a, s);
+    case TRI_MAP_LAMBDA: return edm_f32_tile<MAP_LAMBDA, STAGE>(p, a, s);
     }
     return false;
+}
+
+// 16-byte staging for tiles of 64 and 128 where the coordinates allow it
+// (see kEdmStageVec4; measured at n = 65536, d = 128: 12.3 -> 11.4 ms at
+// tile 128, where it also lowers the registers from 193 to 126 and so
+// doubles the workgroups per CU; at tile 32 it is slower, 18.7 -> 21.4 ms).
+static bool edm_f32(const tri_plan *p, const EdmArgs &a, hipStream_t s)
+{
+    const EdmTile &t = a.t;
+    const bool vec4 = p->tile >= 64 && t.d % 4 == 0 && t.ldx % 4 == 0 &&
+                      ((uintptr_t)t.x & 15) == 0 &&
+                      (uint64_t)t.n * (uint64_t)t.ldx * 4 < (1ull << 31);
+    return vec4 ? edm_f32_map<kEdmStageVec4>(p, a, s) : edm_f32_map<kEdmStageScalar>(p, a, s);
 }
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -572,9 +586,9 @@ bool launch_edm_f32_lambda(int tile, const TileGrid &g, const EdmTile &t, hipStr
     else { gx = 1u << 16; gy = (uint32_t)((g.T + gx - 1) / gx); }
     const dim3 grid(gx, gy);
     switch (tile) {
-    case 16: k_edm_f32<MAP_LAMBDA, 16><<<grid, 256, 0, s>>>(a); return true;
-    case 32: k_edm_f32<MAP_LAMBDA, 32><<<grid, 256, 0, s>>>(a); return true;
-    case 64: k_edm_f32<MAP_LAMBDA, 64><<<grid, 256, 0, s>>>(a); return true;
+    case 16: k_edm_f32<MAP_LAMBDA, 16, kEdmStageScalar><<<grid, 256, 0, s>>>(a); return true;
+    case 32: k_edm_f32<MAP_LAMBDA, 32, kEdmStageScalar><<<grid, 256, 0, s>>>(a); return true;
+    case 64: k_edm_f32<MAP_LAMBDA, 64, kEdmStageScalar><<<grid, 256, 0, s>>>(a); return true;
     }
     return false;
 }

@@ -59,6 +59,25 @@ def test_edm_fp32_small(map_name, tile):
             _check_rows(X, got, list(range(n)), _fp32_bound(d))
 
 
+@pytest.mark.parametrize("tile", [32, 64, 128])
+def test_edm_fp32_padded_rows(tile):
+    """Coordinates with a leading dimension above d: a multiple of 4 (the
+    16-byte staging of tiles 64 and 128), and not (the scalar staging)."""
+    import torch
+    tm = _tm()
+    n, d = 300, 32
+    for ldx in (32, 36, 37, 40):
+        X, _ = inputs.points(n, d, dup_frac=0.02, seed=4500 + ldx)
+        W = np.full((n, ldx), np.nan, dtype=np.float32)
+        W[:, :d] = X
+        xd = dev(W)[:, :d]
+        assert xd.stride(0) == ldx
+        note("edm fp32 padded", tile, ldx)
+        out = torch.full((n * (n - 1) // 2,), -1.0, dtype=torch.float32, device="cuda")
+        tm.Plan(n, tile, "lambda", include_diag=False).edm(xd, out, mode=tm.EDM_FP32)
+        _check_rows(X, host(out), list(range(n)), _fp32_bound(d))
+
+
 @pytest.mark.slow
 @pytest.mark.parametrize("tile", [64, 128])
 def test_edm_fp32_full_size_sampled_rows(tile):

@@ -129,7 +129,7 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch_step(BatchStepArgs a)
                 bool done = false;
                 if constexpr (TL >= 16) {
                     if (a.gens > 0) {
-                        life_multi_tile_body<TL, false>(t, bi, bj, a.gens, (uint32_t *)body_lds);
+                        life_multi_tile_body<TL, true>(t, bi, bj, a.gens, (uint32_t *)body_lds);
                         done = true;
                     }
                 }

@@ -63,8 +63,10 @@ __device__ __forceinline__ uint32_t life_hsum3(uint32_t west, uint32_t w, uint32
 }
 
 // HOIST: issue every staging load before the first is used (more registers;
-// the standalone kernels), else load and store word by word (the batched
-// kernel, whose occupancy is set by its largest body).
+// the standalone kernels and the batched kernel's multi-generation path,
+// where it measured 10.1 -> 8.9 ms for the Life half of the 512-instance
+// batch), else load and store word by word (the batched kernel's
+// one-generation path).
 template <int TILE, int NT, bool HOIST = true>
 __device__ __forceinline__ void life_tile_body(const LifeTile &p, int32_t bi, int32_t bj,
                                                uint32_t *lds)

@@ -248,18 +248,24 @@ def test_edm_bf16x3_4096_sampled_rows():
     near = {}
     for a, b in pairs.tolist():
         near.setdefault(max(a, b), []).append(min(a, b))
+    rels = []
     for k, r in enumerate(rows):
         g = out[r * (r - 1) // 2: r * (r - 1) // 2 + r].cpu().numpy().astype(np.float64)
         e = exp[r]
         nz = e > 0
-        worst = max(worst, float((np.abs(g[nz] - e[nz]) / e[nz]).max()))
+        rel = np.abs(g[nz] - e[nz]) / e[nz]
+        rels.append(rel.astype(np.float32))
+        worst = max(worst, float(rel.max()))
         for j in near.get(r, ()):
             if e[j] > 0 and e[j] ** 2 < 1e-2:
                 worst_near = max(worst_near, abs(g[j] - e[j]) / e[j])
         if k % 1024 == 0:
             print(f"[edm 4096 rows] {k}/{len(rows)} rows checked", flush=True)
-    print(f"[edm bf16x3 n={n} d={d}] max relative error {worst:.3e} over {len(rows)} rows "
-          f"({len(near)} near-duplicate pairs: {worst_near:.3e})", flush=True)
+    allrel = np.concatenate(rels)
+    p999 = float(np.percentile(allrel, 99.9))
+    print(f"[edm bf16x3 n={n} d={d}] max relative error {worst:.3e}, p99.9 {p999:.3e} over "
+          f"{len(rows)} rows ({allrel.size} pairs; {len(near)} near-duplicate pairs: "
+          f"{worst_near:.3e})", flush=True)
     assert worst <= 1e-3
     assert worst_near <= _fp32_bound(d)
     del out

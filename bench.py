@@ -247,6 +247,12 @@ def bench_edm(tm, torch, timer):
     q = tm.Plan(n, 128, "lambda", include_diag=False, flags=best["flags"])
     res["mfma_map"] = best["map"]
     res["mfma_flags"] = best["flags"]
+    # the autotuner's BF16X3 timings of every map at tile 128, and I = t_BB / t_map
+    res["bf16x3_tune_ms_by_map"] = {f"{c['map']}/f{c['flags']}": round(c["ms"], 4) for c in table}
+    bb = [c["ms"] for c in table if c["map"] == "bb"]
+    if bb:
+        res["bf16x3_I_vs_bb"] = {k: round(bb[0] / v, 4)
+                                 for k, v in res["bf16x3_tune_ms_by_map"].items()}
     for mode, name in ((tm.EDM_BF16X3, "bf16x3"), (tm.EDM_BF16, "bf16")):
         ws = torch.empty(q.edm_workspace_size(d, mode), dtype=torch.uint8, device="cuda")
         ms = timer.run(lambda: q.edm(xd, out, mode=mode, fixup_thr=1e-2, ws=ws), 5, 2)

@@ -347,8 +347,10 @@ tri_status tri_batch_autotune(int32_t count, const int32_t *host_kind, const int
  * m is a power of two) and lambda, the latter plain, with
  * TRI_FLAG_XCD_SWIZZLE, TRI_FLAG_ORDER_REVERSE, TRI_FLAG_ORDER_PAIRS and
  * swizzle + pairs, plus UTM for the elementwise bodies and Life) on this GPU: one warm-up and `reps` timed calls
- * with HIP events on `stream`, on zeroed scratch buffers of the problem's
- * size that it allocates and frees itself (so it is not for graph capture).
+ * with HIP events on `stream`, on scratch buffers of the problem's size that
+ * it allocates and frees itself (so it is not for graph capture): zeroed,
+ * except the distance maps' coordinates, uniform in [0, 1) (all-equal
+ * points would time the near-duplicate recompute of every pair).
  * Life is timed over four generations (also with TRI_FLAG_LIFE_TEMPORAL
  * for BB and lambda at tiles 16..64) and reported per generation.  The
  * fastest candidate goes to *best and into a process-wide cache keyed by GPU

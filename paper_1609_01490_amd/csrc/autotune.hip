@@ -77,6 +77,23 @@ struct Candidate {
     uint32_t flags;
 };
 
+// Distance-map candidates are timed on coordinates uniform in [0, 1) (an
+// integer hash of the index, top 24 bits), not on zeros: with every point
+// equal, every pair falls below the near-duplicate threshold and the
+// timing would be that of the FP32 recompute.
+__global__ void __launch_bounds__(256) k_tune_fill(float *x, int64_t count)
+{
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= count) return;
+    uint32_t h = (uint32_t)q * 0x9E3779B9u + (uint32_t)(q >> 32);
+    h ^= h >> 16;
+    h *= 0x7FEB352Du;
+    h ^= h >> 15;
+    h *= 0x846CA68Bu;
+    h ^= h >> 16;
+    x[q] = (float)(h >> 8) * (1.0f / 16777216.0f);
+}
+
 static std::vector<Candidate> candidates(int workload, int64_t n)
 {
     std::vector<int> tiles;
@@ -146,7 +163,8 @@ tri_status tri_autotune(int workload, int64_t n, int64_t d, int reps, int use_ca
     hipStream_t s = (hipStream_t)stream;
     Scratch sc;
     hipError_t e = hipSuccess;
-    // buffers sized for the workload; contents zeroed (timing only)
+    // buffers sized for the workload; contents zeroed (timing only), the
+    // distance maps' coordinates filled as above
     const int64_t ld = (n + 3) / 4 * 4;
     void *x = nullptr, *y = nullptr, *c = nullptr, *ws = nullptr;
     size_t ws_bytes = 0;
@@ -174,7 +192,11 @@ tri_status tri_autotune(int workload, int64_t n, int64_t d, int reps, int use_ca
     default: {
         x = sc.get(sizeof(float) * n * d, e);
         if (e == hipSuccess) c = sc.get(sizeof(float) * (size_t)(n * (n - 1) / 2), e);
-        if (e == hipSuccess) e = hipMemsetAsync(x, 0, sizeof(float) * n * d, s);
+        if (e == hipSuccess) {
+            const int64_t cnt = n * d;
+            k_tune_fill<<<dim3((uint32_t)((cnt + 255) / 256)), 256, 0, s>>>((float *)x, cnt);
+            e = hipGetLastError();
+        }
         if (e == hipSuccess && workload == TRI_TUNE_EDM_BF16X3) {
             tri_plan *p = nullptr;
             if (tri_map_plan(&p, n, 128, TRI_MAP_LAMBDA, 0, 0) == TRI_OK) {

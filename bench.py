@@ -415,7 +415,7 @@ def bench_batch(tm, torch, timer, steps=20, d=32, tiles=None):
             pairs += n * (n - 1) // 2
             init.append(None)
         else:
-            ld = (n + 3) // 4 * 4
+            ld = (n + 15) // 16 * 16  # 16-byte rows: the bit-sliced body's vector path
             g = inputs.life(n, 0.3, seed=inputs.seed_for(4) * 1000 + k, ld=ld)
             A.append(torch.from_numpy(g).cuda())
             B.append(torch.zeros_like(A[-1]))

@@ -312,8 +312,12 @@ tri_status tri_batch_plan(tri_batch **out, int32_t count, const int32_t *host_ki
  * holding generation 0 on entry, b[k] = the other grid (both uint8, row
  * pitch ld[k] >= n_k, a multiple of 4).  After an even number of
  * generations the Life result is in a[k], after an odd number in b[k].
- * Copies the descriptors to the device (synchronously) and builds and
- * instantiates the graph.  Rebinding replaces both. */
+ * When the plan has life_tile 64 with TRI_FLAG_LIFE_TEMPORAL and every Life
+ * grid has a pitch that is a multiple of 16 and 16-byte aligned buffers,
+ * the bound kernel moves Life tiles bit-sliced, one per wave, with 16-byte
+ * row loads and stores (same results).  Copies the descriptors to the
+ * device (synchronously) and builds and instantiates the graph.  Rebinding
+ * replaces both. */
 tri_status tri_batch_bind(tri_batch *b, void *const *host_a, void *const *host_b,
                           const int64_t *host_ld);
 

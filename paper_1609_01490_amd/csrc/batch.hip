@@ -38,11 +38,13 @@ struct BatchDesc {
     int32_t kind;  // TRI_KIND_*
     int32_t n;
     int32_t d;
-    int32_t pad;
+    int32_t pad;   // kDescVec16: a Life grid whose rows move as 16-byte vectors
     int64_t ld;    // distance map: ldx; Life: row pitch in bytes
     void *a;       // distance map: x; Life: grid of even generations
     void *b;       // distance map: out; Life: grid of odd generations
 };
+
+constexpr int32_t kDescVec16 = 1;  // ld % 16 == 0 and 16-byte aligned grids
 
 struct BatchStepArgs {
     const BatchDesc *desc;
@@ -66,8 +68,12 @@ struct BatchLds {
     static constexpr int EDM_BYTES = EdmF32Shape<TE>::LDS_FLOATS * 4;
     static constexpr int LIFE_BYTES = LifeShape<TL, kBatchThreads>::LDS_WORDS * 4;
     static constexpr int MULTI_BYTES = life_multi_bytes<TL>();
+    // 64 x 64 Life tiles with several generations: one bit-sliced tile per wave
+    static constexpr int BITS_BYTES =
+        TL == 64 ? kBatchThreads / 64 * 2 * LifeBitsShape::WORDS * 4 : 0;
     static constexpr int B1 = EDM_BYTES > LIFE_BYTES ? EDM_BYTES : LIFE_BYTES;
-    static constexpr int BYTES = B1 > MULTI_BYTES ? B1 : MULTI_BYTES;
+    static constexpr int B2 = B1 > MULTI_BYTES ? B1 : MULTI_BYTES;
+    static constexpr int BYTES = B2 > BITS_BYTES ? B2 : BITS_BYTES;
 };
 
 // Items are taken kChunk at a time (one atomic per chunk) and the next
@@ -76,7 +82,9 @@ struct BatchLds {
 // same instance: its range and descriptor are kept until an item leaves it.
 constexpr int kChunk = 4;
 
-template <int TE, int TL>
+// BITS (64 x 64 Life tiles, every Life grid of the batch with 16-byte rows):
+// chunks of Life items go one per wave through the bit-sliced body.
+template <int TE, int TL, bool BITS>
 __global__ void __launch_bounds__(kBatchThreads) k_batch_step(BatchStepArgs a)
 {
     __shared__ __attribute__((aligned(16))) unsigned char body_lds[BatchLds<TE, TL>::BYTES];
@@ -100,6 +108,47 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch_step(BatchStepArgs a)
         __syncthreads();
         const int64_t g0 = slot;
         if (g0 >= a.total) return;  // uniform over the workgroup
+        if constexpr (BITS && TL == 64 && kChunk == kBatchThreads / 64) {
+            // A chunk of Life items only, several generations, grids whose
+            // rows move as 16-byte vectors: each wave takes one item with the
+            // bit-sliced body, instead of the workgroup taking the four in
+            // turn with the byte-sliced one (which other grids keep: moved
+            // byte by byte, the bit-sliced body is slower at these sizes).
+            if (a.gens > 0) {
+                const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+                const int64_t g = g0 + wv;
+                int64_t wlo = 0;
+                BatchDesc W{};
+                if (g < a.total) {
+                    int lo = 0, hi = a.count;
+                    while (hi - lo > 1) {
+                        const int mid = (lo + hi) >> 1;
+                        const int64_t pm = in_lds ? pfx[mid] : a.prefix[mid];
+                        if (pm <= g) lo = mid;
+                        else hi = mid;
+                    }
+                    lo = __builtin_amdgcn_readfirstlane(lo);  // wave-uniform: scalar loads
+                    wlo = in_lds ? pfx[lo] : a.prefix[lo];
+                    wlo = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(
+                                         (int32_t)((uint64_t)wlo >> 32)) << 32) |
+                                    (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)wlo));
+                    W = a.desc[a.idx ? __builtin_amdgcn_readfirstlane(a.idx[lo]) : lo];
+                }
+                const bool life = g >= a.total || (W.kind == TRI_KIND_LIFE && (W.pad & kDescVec16));
+                if (__syncthreads_and(life)) {
+                    if (g < a.total) {
+                        int32_t bi, bj;
+                        lambda_tile((uint64_t)(g - wlo), 0u, bi, bj);
+                        const bool even = (a.step & 1) == 0;
+                        const LifeTile t{W.n, W.ld, (const uint8_t *)(even ? W.a : W.b),
+                                         (uint8_t *)(even ? W.b : W.a)};
+                        uint32_t *wl = (uint32_t *)body_lds + wv * 2 * LifeBitsShape::WORDS;
+                        life_bits_wave_body<true>(t, bi, bj, a.gens, wl);
+                    }
+                    continue;  // the loop's barrier precedes the next claim
+                }
+            }
+        }
         for (int c = 0; c < kChunk; ++c) {
             const int64_t g = g0 + c;
             if (g >= a.total) break;
@@ -129,7 +178,7 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch_step(BatchStepArgs a)
                 bool done = false;
                 if constexpr (TL >= 16) {
                     if (a.gens > 0) {
-                        life_multi_tile_body<TL, true>(t, bi, bj, a.gens, (uint32_t *)body_lds);
+                        life_multi_tile_body<TL, !BITS>(t, bi, bj, a.gens, (uint32_t *)body_lds);
                         done = true;
                     }
                 }
@@ -146,27 +195,26 @@ __global__ void k_batch_reset(uint32_t *heads, int32_t count)
 
 typedef void (*StepKernel)(BatchStepArgs);
 
-template <int TE, int TL>
-static StepKernel step_kernel_tl() { return k_batch_step<TE, TL>; }
-
 template <int TE>
-static StepKernel step_kernel_te(int tl)
+static StepKernel step_kernel_te(int tl, bool bits)
 {
     switch (tl) {
-    case 8: return step_kernel_tl<TE, 8>();
-    case 16: return step_kernel_tl<TE, 16>();
-    case 32: return step_kernel_tl<TE, 32>();
-    case 64: return step_kernel_tl<TE, 64>();
+    case 8: return k_batch_step<TE, 8, false>;
+    case 16: return k_batch_step<TE, 16, false>;
+    case 32: return k_batch_step<TE, 32, false>;
+    case 64: return bits ? k_batch_step<TE, 64, true> : k_batch_step<TE, 64, false>;
     }
     return nullptr;
 }
 
-static StepKernel step_kernel(int te, int tl)
+// bits: the bit-sliced variant (tile 64 only; null otherwise)
+static StepKernel step_kernel(int te, int tl, bool bits = false)
 {
+    if (bits && tl != 64) return nullptr;
     switch (te) {
-    case 16: return step_kernel_te<16>(tl);
-    case 32: return step_kernel_te<32>(tl);
-    case 64: return step_kernel_te<64>(tl);
+    case 16: return step_kernel_te<16>(tl, bits);
+    case 32: return step_kernel_te<32>(tl, bits);
+    case 64: return step_kernel_te<64>(tl, bits);
     }
     return nullptr;
 }
@@ -187,7 +235,10 @@ struct tri_batch {
     std::vector<BatchDesc> desc;        // host copy (per-instance mode)
     int device = 0;
     uint32_t grid = 0;                  // persistent workgroups
-    StepKernel kernel = nullptr;
+    StepKernel kernel = nullptr;        // the kernel bound (one of the two below)
+    StepKernel kernel_bytes = nullptr;  // Life tiles byte-sliced
+    StepKernel kernel_bits = nullptr;   // 64 x 64 Life tiles bit-sliced (or null)
+    uint32_t grid_bytes = 0, grid_bits = 0;
     // device memory owned by the plan
     BatchDesc *d_desc = nullptr;
     int64_t *d_prefix0 = nullptr, *d_prefix1 = nullptr;
@@ -319,7 +370,8 @@ tri_status tri_batch_plan(tri_batch **out, int32_t count, const int32_t *host_ki
     b->steps = life_steps;
     b->temporal = (flags & TRI_FLAG_LIFE_TEMPORAL) != 0;
     if (b->temporal && life_steps > 0) b->sched = life_multi_schedule(life_steps);
-    b->kernel = step_kernel(edm_tile, life_tile);
+    b->kernel = b->kernel_bytes = step_kernel(edm_tile, life_tile);
+    b->kernel_bits = step_kernel(edm_tile, life_tile, true);
     b->prefix0.push_back(0);
     b->prefix1.push_back(0);
     for (int32_t k = 0; k < count; ++k) {
@@ -359,16 +411,20 @@ tri_status tri_batch_plan(tri_batch **out, int32_t count, const int32_t *host_ki
     }
 
     hipError_t e = hipGetDevice(&b->device);
-    int cus = 0, per_cu = 0;
+    int cus = 0, per_cu = 0, per_cu_bits = 0;
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
     if (e == hipSuccess)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)b->kernel,
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)b->kernel_bytes,
+                                                         kBatchThreads, 0);
+    if (e == hipSuccess && b->kernel_bits)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_bits, (const void *)b->kernel_bits,
                                                          kBatchThreads, 0);
     if (e != hipSuccess) {
         batch_free(b);
         return hip_fail(e, "tri_batch_plan: device query");
     }
-    b->grid = (uint32_t)std::max(1, cus * std::max(1, per_cu));
+    b->grid = b->grid_bytes = (uint32_t)std::max(1, cus * std::max(1, per_cu));
+    b->grid_bits = (uint32_t)std::max(1, cus * std::max(1, per_cu_bits));
 
     const size_t nl = b->idx1.size();
     const int S = batch_nodes(b);
@@ -417,11 +473,19 @@ tri_status tri_batch_bind(tri_batch *b, void *const *host_a, void *const *host_b
             if (D.ld < D.n || D.ld % 4 || (((uintptr_t)D.a | (uintptr_t)D.b) & 3))
                 return fail(TRI_E_INVAL,
                             "tri_batch_bind: instance %d: ld must be >= n, a multiple of 4", k);
+            if (D.ld % 16 == 0 && (((uintptr_t)D.a | (uintptr_t)D.b) & 15) == 0) D.pad = kDescVec16;
         }
     }
     TRI_HIP(hipMemcpy(b->d_desc, desc.data(), sizeof(BatchDesc) * b->count,
                       hipMemcpyHostToDevice));
     b->desc = desc;
+    // the bit-sliced kernel when every Life grid has 16-byte rows and the
+    // nodes advance several generations
+    bool bits = b->kernel_bits != nullptr && b->temporal;
+    for (const BatchDesc &D : desc)
+        if (D.kind == TRI_KIND_LIFE && !(D.pad & kDescVec16)) bits = false;
+    b->kernel = bits ? b->kernel_bits : b->kernel_bytes;
+    b->grid = bits ? b->grid_bits : b->grid_bytes;
     if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
     if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
     tri_status st = batch_build_graph(b);

@@ -214,11 +214,36 @@ __device__ __forceinline__ uint32_t life_bits_mask(int32_t gi, int32_t jb, int32
     return upto & (0xFFFFFFFFu << lo);
 }
 
+// Four cells (bytes, nonzero = alive) to four bits, cell k to bit k: each
+// byte's bits are ORed into its bit 0, then one multiply gathers bit 0 of
+// byte k at bit 24 + k with no carries (the other partial products land
+// below bit 24 or beyond bit 31).
+__device__ __forceinline__ uint32_t life_cells4_to_bits(uint32_t x)
+{
+    x |= x >> 4;
+    x |= x >> 2;
+    x |= x >> 1;
+    x &= 0x01010101u;
+    return (x * 0x01020408u) >> 24;
+}
+
+// The inverse for four bits: bit k to byte k (0 or 1); the four shifted
+// copies of the nibble overlap only away from bits 0, 8, 16 and 24.
+__device__ __forceinline__ uint32_t life_bits4_to_cells(uint32_t b)
+{
+    return (b * 0x00204081u) & 0x01010101u;
+}
+
 // The update run by one wave per tile (64 threads): no workgroup barriers,
 // and four times as many tiles in flight per CU as with 256 threads, which
 // is what the load-then-compute pattern needs to keep HBM busy on large
 // grids (on small grids the byte-sliced body, whose tile finishes sooner,
 // is faster).  lds: at least 2 * LifeBitsShape::WORDS words.
+// VEC (ld a multiple of 16, 16-byte aligned grids): rows are staged with
+// 16-byte loads, four lanes per row, and written back with 16-byte stores:
+// 5 loads and 4 stores per lane and tile instead of 72 single-byte loads and
+// 64 single-byte stores, whose instruction count bounds the byte path.
+template <bool VEC = false>
 __device__ __forceinline__ void life_bits_wave_body(const LifeTile &p, int32_t bi, int32_t bj,
                                                     int gens, uint32_t *lds)
 {
@@ -233,12 +258,76 @@ __device__ __forceinline__ void life_bits_wave_body(const LifeTile &p, int32_t b
     const int32_t n = p.n;
     const int64_t ld = p.ld;
     const int32_t i0 = bi * T, j0 = bj * T;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;  // any wave of the workgroup runs its own tile
 
     if (lane < S::WPR) {
         A[lane] = A[(S::PR - 1) * S::WPR + lane] = 0u;
         B[lane] = B[(S::PR - 1) * S::WPR + lane] = 0u;
     }
+    const int32_t gj = j0 + lane;
+    uint32_t msk[WPL];
+#pragma unroll
+    for (int k = 0; k < WPL; ++k) {
+        const int w = lane + 64 * k;
+        msk[k] = w < NWORD ? life_bits_mask(i0 - K + (w >> 2), j0 - 32 + 32 * (w & 3), n) : 0u;
+    }
+    if constexpr (VEC) {
+        typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+        constexpr int RND = (S::R + 15) / 16;   // rounds of 16 rows
+        constexpr int HR = (2 * S::R + 63) / 64;  // rounds of 64 halo words
+        const int q = lane & 3, rr = lane >> 2;  // chunk q (16 cells) of row rr
+        const int32_t ldi = (int32_t)ld;
+        const int32_t col = j0 + 16 * q < ldi - 16 ? j0 + 16 * q : ldi - 16;
+        // every load from a clamped address first, masked afterwards
+        u32x4 cv[RND];
+        uint32_t hv[HR];
+#pragma unroll
+        for (int r = 0; r < RND; ++r) {
+            const int32_t gi = i0 - K + 16 * r + rr;
+            const int32_t gic = gi < 0 ? 0 : (gi >= n ? n - 1 : gi);
+            cv[r] = *(const u32x4 *)(p.cur + (int64_t)gic * ld + col);
+        }
+#pragma unroll
+        for (int k = 0; k < HR; ++k) {
+            const int t = lane + 64 * k;  // halo word t: row t / 2, west or east
+            const int row = (t >> 1) < S::R ? (t >> 1) : S::R - 1;
+            const int32_t gi = i0 - K + row;
+            const int32_t gic = gi < 0 ? 0 : (gi >= n ? n - 1 : gi);
+            int32_t hc = (t & 1) ? j0 + T : j0 - 4;
+            hc = hc < 0 ? 0 : (hc > ldi - 4 ? ldi - 4 : hc);
+            hv[k] = *(const uint32_t *)(p.cur + (int64_t)gic * ld + hc);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        uint16_t *A16 = (uint16_t *)A;
+#pragma unroll
+        for (int r = 0; r < RND; ++r) {
+            const int row = 16 * r + rr;
+            if (row < S::R) {
+                const uint32_t b16 = life_cells4_to_bits(cv[r].x) |
+                                     (life_cells4_to_bits(cv[r].y) << 4) |
+                                     (life_cells4_to_bits(cv[r].z) << 8) |
+                                     (life_cells4_to_bits(cv[r].w) << 12);
+                A16[((row + 1) * S::WPR + 1 + (q >> 1)) * 2 + (q & 1)] = (uint16_t)b16;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < HR; ++k) {
+            const int t = lane + 64 * k;
+            if (t < 2 * S::R) {
+                const uint32_t nib = life_cells4_to_bits(hv[k]);
+                A[((t >> 1) + 1) * S::WPR + ((t & 1) ? 3 : 0)] = (t & 1) ? nib : nib << 28;
+            }
+        }
+        // then clear every staged bit outside the domain (rows beyond the
+        // grid, cells above the diagonal or left of column 0, clamped loads)
+        __builtin_amdgcn_s_waitcnt(0xc07f);
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int k = 0; k < WPL; ++k) {
+            const int w = lane + 64 * k;
+            if (w < NWORD) A[S::WPR + w] &= msk[k];
+        }
+    } else {
     // halo cells of all rows: lane covers row 8 q + lane / 8, cell lane % 8
     uint64_t hb[HG];
     {
@@ -261,7 +350,6 @@ __device__ __forceinline__ void life_bits_wave_body(const LifeTile &p, int32_t b
         for (int q = 0; q < HG; ++q) hb[q] = __ballot(hok[q] && hv[q] != 0u);
     }
     // the 64 cells of each row, CH rows per batch of loads
-    const int32_t gj = j0 + lane;
 #pragma unroll
     for (int b0 = 0; b0 < S::R; b0 += CH) {
         uint32_t cv[CH];
@@ -288,11 +376,6 @@ __device__ __forceinline__ void life_bits_wave_body(const LifeTile &p, int32_t b
             }
         }
     }
-    uint32_t msk[WPL];
-#pragma unroll
-    for (int k = 0; k < WPL; ++k) {
-        const int w = lane + 64 * k;
-        msk[k] = w < NWORD ? life_bits_mask(i0 - K + (w >> 2), j0 - 32 + 32 * (w & 3), n) : 0u;
     }
     // LDS operations of one wave complete in order; the wait and the
     // barrier keep the compiler from moving reads of other lanes' words
@@ -329,11 +412,38 @@ __device__ __forceinline__ void life_bits_wave_body(const LifeTile &p, int32_t b
         B = t;
     }
 
-    for (int tr = 0; tr < T; ++tr) {
-        const int32_t gi = i0 + tr;
-        if (gi >= n) break;
-        const uint32_t wv = A[(K + tr + 1) * S::WPR + 1 + (lane >> 5)];
-        if (gj <= gi) p.nxt[(int64_t)gi * ld + gj] = (uint8_t)((wv >> (lane & 31)) & 1u);
+    if constexpr (VEC) {
+        typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+        const int q = lane & 3, rr = lane >> 2;
+        const int32_t jc = j0 + 16 * q;
+#pragma unroll
+        for (int r0 = 0; r0 < T; r0 += 16) {
+            const int tr = r0 + rr;
+            const int32_t gi = i0 + tr;
+            if (gi >= n) continue;
+            const uint32_t b16 =
+                (A[(K + tr + 1) * S::WPR + 1 + (q >> 1)] >> (16 * (q & 1))) & 0xFFFFu;
+            u32x4 o;
+            o.x = life_bits4_to_cells(b16 & 0xFu);
+            o.y = life_bits4_to_cells((b16 >> 4) & 0xFu);
+            o.z = life_bits4_to_cells((b16 >> 8) & 0xFu);
+            o.w = life_bits4_to_cells(b16 >> 12);
+            uint8_t *dst = p.nxt + (int64_t)gi * ld + jc;
+            if (jc + 15 <= gi) {
+                *(u32x4 *)dst = o;
+            } else {  // the chunk meets the diagonal: cells jc .. gi only
+#pragma unroll
+                for (int e = 0; e < 16; ++e)
+                    if (jc + e <= gi) dst[e] = (uint8_t)((b16 >> e) & 1u);
+            }
+        }
+    } else {
+        for (int tr = 0; tr < T; ++tr) {
+            const int32_t gi = i0 + tr;
+            if (gi >= n) break;
+            const uint32_t wv = A[(K + tr + 1) * S::WPR + 1 + (lane >> 5)];
+            if (gj <= gi) p.nxt[(int64_t)gi * ld + gj] = (uint8_t)((wv >> (lane & 31)) & 1u);
+        }
     }
 }
 

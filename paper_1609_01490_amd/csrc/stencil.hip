@@ -86,31 +86,42 @@ __global__ void __launch_bounds__(256) k_life_multi(LifeArgs p, int gens)
     life_multi_tile_body<TILE>(p.t, bi, bj, gens, buf);
 }
 
-// 64 x 64 tiles, bit-sliced, one wave per tile
-template <int MAP>
+// 64 x 64 tiles, bit-sliced, one wave per tile; VEC: 16-byte row loads and
+// stores (ld a multiple of 16, 16-byte aligned grids)
+template <int MAP, bool VEC>
 __global__ void __launch_bounds__(64) k_life_bits(LifeArgs p, int gens)
 {
     int32_t bi, bj;
     if (!tile_of_block<MAP>(p.g, bi, bj)) return;
-    __shared__ uint32_t buf[2 * LifeBitsShape::WORDS];
-    life_bits_wave_body(p.t, bi, bj, gens, buf);
+    __shared__ __attribute__((aligned(16))) uint32_t buf[2 * LifeBitsShape::WORDS];
+    life_bits_wave_body<VEC>(p.t, bi, bj, gens, buf);
+}
+
+// whether the bit-sliced kernel may move rows as 16-byte vectors
+static bool life_vec16(const LifeTile &t)
+{
+    return t.ld % 16 == 0 && (((uintptr_t)t.cur | (uintptr_t)t.nxt) & 15) == 0;
 }
 
 // 64 x 64 tiles take the bit-sliced one-wave kernel on grids of at least
-// this many tiles, the byte-sliced 256-thread one below (measured: the
-// former wins at n = 16384, the latter on the batched workload's n <= 8192)
+// this many tiles, the byte-sliced 256-thread one below (measured, 20
+// generations: with 16-byte rows the bit-sliced kernel wins from n = 2048,
+// 0.055 vs 0.061 ms, to n = 8192, 0.151 vs 0.332 ms, and ties at n = 1024;
+// moving rows byte by byte it wins only at n = 16384)
 constexpr uint64_t kLifeBitsMinTiles = 16384;
+constexpr uint64_t kLifeBitsMinTilesVec = 512;
 
 template <int MAP>
-static bool life_multi_kernel_tile(int tile, uint64_t tiles, const void *&fn, int &threads)
+static bool life_multi_kernel_tile(int tile, uint64_t tiles, bool vec, const void *&fn,
+                                   int &threads)
 {
     threads = 256;
     switch (tile) {
     case 16: fn = (const void *)k_life_multi<MAP, 16>; return true;
     case 32: fn = (const void *)k_life_multi<MAP, 32>; return true;
     case 64:
-        if (tiles >= kLifeBitsMinTiles) {
-            fn = (const void *)k_life_bits<MAP>;
+        if (tiles >= (vec ? kLifeBitsMinTilesVec : kLifeBitsMinTiles)) {
+            fn = vec ? (const void *)k_life_bits<MAP, true> : (const void *)k_life_bits<MAP, false>;
             threads = 64;
         } else {
             fn = (const void *)k_life_multi<MAP, 64>;
@@ -120,14 +131,14 @@ static bool life_multi_kernel_tile(int tile, uint64_t tiles, const void *&fn, in
     return false;
 }
 
-static bool life_multi_kernel(const tri_plan *p, const void *&fn, int &threads)
+static bool life_multi_kernel(const tri_plan *p, bool vec, const void *&fn, int &threads)
 {
     const uint64_t T = (uint64_t)p->T;
     switch (p->map) {
-    case TRI_MAP_BB: return life_multi_kernel_tile<MAP_BB>(p->tile, T, fn, threads);
-    case TRI_MAP_RB: return life_multi_kernel_tile<MAP_RB>(p->tile, T, fn, threads);
-    case TRI_MAP_REC: return life_multi_kernel_tile<MAP_REC>(p->tile, T, fn, threads);
-    case TRI_MAP_LAMBDA: return life_multi_kernel_tile<MAP_LAMBDA>(p->tile, T, fn, threads);
+    case TRI_MAP_BB: return life_multi_kernel_tile<MAP_BB>(p->tile, T, vec, fn, threads);
+    case TRI_MAP_RB: return life_multi_kernel_tile<MAP_RB>(p->tile, T, vec, fn, threads);
+    case TRI_MAP_REC: return life_multi_kernel_tile<MAP_REC>(p->tile, T, vec, fn, threads);
+    case TRI_MAP_LAMBDA: return life_multi_kernel_tile<MAP_LAMBDA>(p->tile, T, vec, fn, threads);
     }
     return false;
 }
@@ -155,7 +166,10 @@ bool launch_life_multi_lambda(int tile, const TileGrid &g, const LifeTile &t, in
     case 16: k_life_multi<MAP_LAMBDA, 16><<<grid, 256, 0, s>>>(a, gens); return true;
     case 32: k_life_multi<MAP_LAMBDA, 32><<<grid, 256, 0, s>>>(a, gens); return true;
     case 64:
-        if (g.T >= kLifeBitsMinTiles) k_life_bits<MAP_LAMBDA><<<grid, 64, 0, s>>>(a, gens);
+        if (life_vec16(t) && g.T >= kLifeBitsMinTilesVec)
+            k_life_bits<MAP_LAMBDA, true><<<grid, 64, 0, s>>>(a, gens);
+        else if (!life_vec16(t) && g.T >= kLifeBitsMinTiles)
+            k_life_bits<MAP_LAMBDA, false><<<grid, 64, 0, s>>>(a, gens);
         else k_life_multi<MAP_LAMBDA, 64><<<grid, 256, 0, s>>>(a, gens);
         return true;
     }
@@ -289,7 +303,7 @@ extern "C" tri_status tri_launch_stencil(const tri_plan *p, uint8_t *cur, uint8_
             return fail(TRI_E_UNSUPPORTED, "tri_launch_stencil: graphs of the temporal kernel are not built");
         const void *fn = nullptr;
         int threads = 256;
-        if (!life_multi_kernel(p, fn, threads))
+        if (!life_multi_kernel(p, life_vec16(a.t), fn, threads))
             return fail(TRI_E_UNSUPPORTED, "tri_launch_stencil: temporal blocking needs tile 16, 32 or 64");
         const std::vector<int> sched = life_multi_schedule(steps);
         for (size_t k = 0; k < sched.size(); ++k) {

@@ -18,7 +18,7 @@ def _tm():
     return trimap
 
 
-def _make(tm, spec, d, steps, edm_tile, life_tile, seed, flags=0):
+def _make(tm, spec, d, steps, edm_tile, life_tile, seed, flags=0, all16=False):
     import torch
     kinds, ns, ds, host_in, A, B = [], [], [], [], [], []
     for k, (kind, n) in enumerate(spec):
@@ -29,7 +29,9 @@ def _make(tm, spec, d, steps, edm_tile, life_tile, seed, flags=0):
             B.append(torch.full((n * (n - 1) // 2,), -1.0, dtype=torch.float32, device="cuda"))
             kinds.append(tm.KIND_EDM)
         else:
-            ld = padded_ld(n)
+            # every other Life grid with rows padded to 16 bytes (the
+            # bit-sliced body moves those rows as 16-byte vectors)
+            ld = padded_ld(n, 16 if all16 or k % 4 == 1 else 4)
             g = inputs.life(n, 0.3, seed=seed + k, ld=ld)
             host_in.append(g)
             A.append(dev(g))
@@ -68,18 +70,24 @@ def _check_oracle(spec, host_in, res, d, steps):
             assert (r[low] == exp[low]).all(), n
 
 
-@pytest.mark.parametrize("edm_tile,life_tile,flags", [(16, 8, 0), (32, 16, 0), (32, 32, 0),
-                                                       (64, 64, 0), (32, 16, 32), (64, 64, 32)])
-def test_batch_matches_oracle_and_modes(edm_tile, life_tile, flags):
+@pytest.mark.parametrize("edm_tile,life_tile,flags,all16", [
+    (16, 8, 0, False), (32, 16, 0, False), (32, 32, 0, False), (64, 64, 0, False),
+    (32, 16, 32, False), (64, 64, 32, False), (64, 64, 32, True), (16, 64, 32, True)])
+def test_batch_matches_oracle_and_modes(edm_tile, life_tile, flags, all16):
+    """all16: every Life grid with 16-byte rows, so that tile 64 with several
+    generations per node binds the bit-sliced kernel (one tile per wave)."""
     tm = _tm()
     rng = np.random.default_rng(edm_tile + life_tile)
     spec = [("edm" if k % 2 == 0 else "life", int(n)) for k, n in
-            enumerate(rng.integers(2, 260, size=14))] + [("edm", 2), ("life", 1), ("life", 3)]
+            enumerate(rng.integers(2, 260, size=14))] + [("edm", 2), ("life", 1), ("life", 3),
+                                                          ("life", 33 * 64 + 5), ("edm", 70),
+                                                          ("life", 33 * 64 + 5)]
     d, steps = 32, 5
     outs = {}
     for how in (tm.BATCH_GRAPH, tm.BATCH_STREAM, tm.BATCH_PER_INSTANCE):
-        note("batch", edm_tile, life_tile, flags, how)
-        b, host_in, A, B = _make(tm, spec, d, steps, edm_tile, life_tile, seed=70, flags=flags)
+        note("batch", edm_tile, life_tile, flags, all16, how)
+        b, host_in, A, B = _make(tm, spec, d, steps, edm_tile, life_tile, seed=70, flags=flags,
+                                 all16=all16)
         b.launch(how)
         outs[how] = _results(spec, A, B, steps)
         if how == tm.BATCH_GRAPH:

@@ -250,29 +250,29 @@ def test_life_temporal_full_size_whole_grid():
 
 
 @pytest.mark.parametrize("steps", [1, 4, 7])
-def test_life_bit_sliced_grid_windows(steps):
-    """A grid large enough (>= 16384 tiles of 64 x 64) for the bit-sliced
-    one-wave kernel, with a ragged last tile row (n = 181 * 64 + 3): 64 x 64
-    windows recomputed by the oracle from their light cones at the diagonal,
-    the ragged bottom rows, the left edge, a corner and inside."""
+@pytest.mark.parametrize("multiple", [4, 16])
+@pytest.mark.parametrize("n", [181 * 64 + 3, 33 * 64 + 5])
+def test_life_bit_sliced_whole_grid(steps, multiple, n):
+    """Grids with a ragged last tile row: n = 181 * 64 + 3 (>= 16384 tiles:
+    the bit-sliced one-wave kernel for either row padding) and
+    n = 33 * 64 + 5 (595 tiles: bit-sliced with 16-byte rows, byte-sliced
+    otherwise), the leading dimension padded to a multiple of 4 (rows moved
+    byte by byte) or of 16 (16-byte row loads and stores): the whole final
+    grid against the oracle's, and nothing written above the diagonal or in
+    the padding."""
     import torch
     tm = _tm()
-    n = 181 * 64 + 3
-    ld = padded_ld(n)
+    ld = padded_ld(n, multiple)
     g = inputs.life(n, 0.3, seed=900 + steps, ld=ld)
+    g[:, n:] = 0
     p = tm.Plan(n, 64, "lambda", flags=tm.FLAG_LIFE_TEMPORAL | tm.FLAG_XCD_SWIZZLE)
-    assert p.info.tiles >= 16384
-    note("life bit-sliced windows", n, steps)
+    assert p.info.tiles >= 512
+    note("life bit-sliced whole grid", n, ld, steps)
     cur = dev(g)
     nxt = torch.zeros_like(cur)
     p.stencil(cur, nxt, steps, ld=ld)
-    res = cur if steps % 2 == 0 else nxt
-    torch.cuda.synchronize()
-    for (r, c) in [(6000, 5970), (n - 64, 4000), (7000, 0), (n - 64, n - 64), (9000, 2500),
-                   (64, 0), (n - 3, n - 67)]:
-        h = min(64, n - r)
-        win = oracle.gol(g, n, steps, r - steps, c - steps, h + 2 * steps, 64 + 2 * steps)
-        exp = win[steps:steps + h, steps:steps + 64]
-        got = res[r:r + h, c:c + 64].cpu().numpy()
-        dom = np.arange(c, c + 64)[None, :] <= np.arange(r, r + h)[:, None]
-        assert (got[dom] == exp[dom]).all(), (r, c)
+    res = (cur if steps % 2 == 0 else nxt).cpu().numpy()
+    exp = _gol_whole(g, n, steps)
+    bad = np.argwhere(res[:, :n] != exp)
+    assert bad.shape[0] == 0, (bad.shape[0], bad[:4].tolist())
+    assert not res[:, n:].any()

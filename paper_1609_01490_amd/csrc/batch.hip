@@ -70,7 +70,7 @@ struct BatchLds {
     static constexpr int MULTI_BYTES = life_multi_bytes<TL>();
     // 64 x 64 Life tiles with several generations: one bit-sliced tile per wave
     static constexpr int BITS_BYTES =
-        TL == 64 ? kBatchThreads / 64 * 2 * LifeBitsShape::WORDS * 4 : 0;
+        TL == 64 ? kBatchThreads / 64 * 2 * LifeBitsShape<>::WORDS * 4 : 0;
     static constexpr int B1 = EDM_BYTES > LIFE_BYTES ? EDM_BYTES : LIFE_BYTES;
     static constexpr int B2 = B1 > MULTI_BYTES ? B1 : MULTI_BYTES;
     static constexpr int BYTES = B2 > BITS_BYTES ? B2 : BITS_BYTES;
@@ -142,7 +142,7 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch_step(BatchStepArgs a)
                         const bool even = (a.step & 1) == 0;
                         const LifeTile t{W.n, W.ld, (const uint8_t *)(even ? W.a : W.b),
                                          (uint8_t *)(even ? W.b : W.a)};
-                        uint32_t *wl = (uint32_t *)body_lds + wv * 2 * LifeBitsShape::WORDS;
+                        uint32_t *wl = (uint32_t *)body_lds + wv * 2 * LifeBitsShape<>::WORDS;
                         life_bits_wave_body<true>(t, bi, bj, a.gens, wl);
                     }
                     continue;  // the loop's barrier precedes the next claim

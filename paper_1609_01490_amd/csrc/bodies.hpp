@@ -193,9 +193,10 @@ __device__ __forceinline__ uint32_t life_window_mask(int32_t gi, int32_t gj, int
 // staged window are not loaded; like cells beyond the byte-sliced window
 // they only reach the tile after more than four generations.
 // ---------------------------------------------------------------------------
+template <int KH = kLifeMaxGen>
 struct LifeBitsShape {
     static constexpr int TILE = 64;
-    static constexpr int K = kLifeMaxGen;    // halo rows and cells
+    static constexpr int K = KH;             // halo rows (generations per launch at most)
     static constexpr int R = TILE + 2 * K;   // staged rows
     static constexpr int PR = R + 2;         // plus a zero row above and below
     static constexpr int WPR = 4;            // words per row
@@ -238,22 +239,26 @@ __device__ __forceinline__ uint32_t life_bits4_to_cells(uint32_t b)
 // and four times as many tiles in flight per CU as with 256 threads, which
 // is what the load-then-compute pattern needs to keep HBM busy on large
 // grids (on small grids the byte-sliced body, whose tile finishes sooner,
-// is faster).  lds: at least 2 * LifeBitsShape::WORDS words.
+// is faster).  lds: at least 2 * LifeBitsShape<KH>::WORDS words.
 // VEC (ld a multiple of 16, 16-byte aligned grids): rows are staged with
 // 16-byte loads, four lanes per row, and written back with 16-byte stores:
 // 5 loads and 4 stores per lane and tile instead of 72 single-byte loads and
 // 64 single-byte stores, whose instruction count bounds the byte path.
-template <bool VEC = false>
+// KH: halo rows above and below the tile (and at most that many
+// generations); KH < 4 only with VEC (4 halo cells are staged left and right
+// of each row whatever KH is).
+template <bool VEC = false, int KH = kLifeMaxGen>
 __device__ __forceinline__ void life_bits_wave_body(const LifeTile &p, int32_t bi, int32_t bj,
                                                     int gens, uint32_t *lds)
 {
-    using S = LifeBitsShape;
+    static_assert(VEC || KH == kLifeMaxGen, "byte row moves stage a 4-row halo");
+    using S = LifeBitsShape<KH>;
     constexpr int T = S::TILE, K = S::K;
     constexpr int NWORD = S::R * S::WPR;       // 288 words per generation
     constexpr int WPL = (NWORD + 63) / 64;     // words per lane
     constexpr int CH = 18;                     // rows per load batch
     constexpr int HG = S::R / 8;               // halo groups of eight rows
-    static_assert(S::R % CH == 0 && S::R % 8 == 0, "row batches");
+    static_assert(VEC || (S::R % CH == 0 && S::R % 8 == 0), "row batches");
     uint32_t *A = lds, *B = lds + S::WORDS;
     const int32_t n = p.n;
     const int64_t ld = p.ld;

@@ -65,17 +65,7 @@ __global__ void __launch_bounds__(kUtmThreads) k_life_utm(LifeArgs p)
 }
 
 template <int MAP>
-static bool life_tile(const tri_plan *p, const LifeArgs &a, hipStream_t s)
-{
-    const dim3 grid(p->gx, p->gy);
-    switch (p->tile) {
-    case 8: k_life<MAP, 8><<<grid, life_threads<8>(), 0, s>>>(a); return true;
-    case 16: k_life<MAP, 16><<<grid, life_threads<16>(), 0, s>>>(a); return true;
-    case 32: k_life<MAP, 32><<<grid, life_threads<32>(), 0, s>>>(a); return true;
-    case 64: k_life<MAP, 64><<<grid, life_threads<64>(), 0, s>>>(a); return true;
-    }
-    return false;
-}
+static bool life_tile(const tri_plan *p, const LifeArgs &a, hipStream_t s);
 
 template <int MAP, int TILE>
 __global__ void __launch_bounds__(256) k_life_multi(LifeArgs p, int gens)
@@ -93,14 +83,43 @@ __global__ void __launch_bounds__(64) k_life_bits(LifeArgs p, int gens)
 {
     int32_t bi, bj;
     if (!tile_of_block<MAP>(p.g, bi, bj)) return;
-    __shared__ __attribute__((aligned(16))) uint32_t buf[2 * LifeBitsShape::WORDS];
+    __shared__ __attribute__((aligned(16))) uint32_t buf[2 * LifeBitsShape<>::WORDS];
     life_bits_wave_body<VEC>(p.t, bi, bj, gens, buf);
+}
+
+// One generation of 64 x 64 tiles with the 1-cell halo of the paper's tiles,
+// bit-sliced, one wave per tile, 16-byte row moves
+template <int MAP>
+__global__ void __launch_bounds__(64) k_life_bits1(LifeArgs p)
+{
+    int32_t bi, bj;
+    if (!tile_of_block<MAP>(p.g, bi, bj)) return;
+    __shared__ __attribute__((aligned(16))) uint32_t buf[2 * LifeBitsShape<1>::WORDS];
+    life_bits_wave_body<true, 1>(p.t, bi, bj, 1, buf);
 }
 
 // whether the bit-sliced kernel may move rows as 16-byte vectors
 static bool life_vec16(const LifeTile &t)
 {
     return t.ld % 16 == 0 && (((uintptr_t)t.cur | (uintptr_t)t.nxt) & 15) == 0;
+}
+
+// One generation of a plan's tiles (64 x 64 tiles with 16-byte rows:
+// bit-sliced)
+template <int MAP>
+static bool life_tile(const tri_plan *p, const LifeArgs &a, hipStream_t s)
+{
+    const dim3 grid(p->gx, p->gy);
+    switch (p->tile) {
+    case 8: k_life<MAP, 8><<<grid, life_threads<8>(), 0, s>>>(a); return true;
+    case 16: k_life<MAP, 16><<<grid, life_threads<16>(), 0, s>>>(a); return true;
+    case 32: k_life<MAP, 32><<<grid, life_threads<32>(), 0, s>>>(a); return true;
+    case 64:
+        if (life_vec16(a.t)) k_life_bits1<MAP><<<grid, 64, 0, s>>>(a);
+        else k_life<MAP, 64><<<grid, life_threads<64>(), 0, s>>>(a);
+        return true;
+    }
+    return false;
 }
 
 // 64 x 64 tiles take the bit-sliced one-wave kernel on grids of at least
@@ -178,25 +197,28 @@ bool launch_life_multi_lambda(int tile, const TileGrid &g, const LifeTile &t, in
 
 // kernel address and block size of the one-step kernel of a plan
 template <int MAP>
-static bool life_kernel_tile(int tile, const void *&fn, int &threads)
+static bool life_kernel_tile(int tile, bool vec, const void *&fn, int &threads)
 {
     switch (tile) {
     case 8: fn = (const void *)k_life<MAP, 8>; threads = life_threads<8>(); return true;
     case 16: fn = (const void *)k_life<MAP, 16>; threads = life_threads<16>(); return true;
     case 32: fn = (const void *)k_life<MAP, 32>; threads = life_threads<32>(); return true;
-    case 64: fn = (const void *)k_life<MAP, 64>; threads = life_threads<64>(); return true;
+    case 64:
+        if (vec) { fn = (const void *)k_life_bits1<MAP>; threads = 64; }
+        else { fn = (const void *)k_life<MAP, 64>; threads = life_threads<64>(); }
+        return true;
     }
     return false;
 }
 
-static bool life_kernel(const tri_plan *p, const void *&fn, int &threads)
+static bool life_kernel(const tri_plan *p, bool vec, const void *&fn, int &threads)
 {
     switch (p->map) {
     case TRI_MAP_UTM: fn = (const void *)k_life_utm; threads = kUtmThreads; return true;
-    case TRI_MAP_BB: return life_kernel_tile<MAP_BB>(p->tile, fn, threads);
-    case TRI_MAP_RB: return life_kernel_tile<MAP_RB>(p->tile, fn, threads);
-    case TRI_MAP_REC: return life_kernel_tile<MAP_REC>(p->tile, fn, threads);
-    case TRI_MAP_LAMBDA: return life_kernel_tile<MAP_LAMBDA>(p->tile, fn, threads);
+    case TRI_MAP_BB: return life_kernel_tile<MAP_BB>(p->tile, vec, fn, threads);
+    case TRI_MAP_RB: return life_kernel_tile<MAP_RB>(p->tile, vec, fn, threads);
+    case TRI_MAP_REC: return life_kernel_tile<MAP_REC>(p->tile, vec, fn, threads);
+    case TRI_MAP_LAMBDA: return life_kernel_tile<MAP_LAMBDA>(p->tile, vec, fn, threads);
     }
     return false;
 }
@@ -228,7 +250,10 @@ bool launch_life_lambda(int tile, const TileGrid &g, const LifeTile &t, hipStrea
     case 8: k_life<MAP_LAMBDA, 8><<<grid, life_threads<8>(), 0, s>>>(a); return true;
     case 16: k_life<MAP_LAMBDA, 16><<<grid, life_threads<16>(), 0, s>>>(a); return true;
     case 32: k_life<MAP_LAMBDA, 32><<<grid, life_threads<32>(), 0, s>>>(a); return true;
-    case 64: k_life<MAP_LAMBDA, 64><<<grid, life_threads<64>(), 0, s>>>(a); return true;
+    case 64:
+        if (life_vec16(t)) k_life_bits1<MAP_LAMBDA><<<grid, 64, 0, s>>>(a);
+        else k_life<MAP_LAMBDA, 64><<<grid, life_threads<64>(), 0, s>>>(a);
+        return true;
     }
     return false;
 }
@@ -248,7 +273,8 @@ static tri_status life_graph(const tri_plan *p, const LifeArgs &a0, int steps,
     }
     const void *fn = nullptr;
     int threads = 0;
-    if (!life_kernel(p, fn, threads)) return fail(TRI_E_UNSUPPORTED, "tri_launch_stencil: tile");
+    if (!life_kernel(p, life_vec16(a0.t), fn, threads))
+        return fail(TRI_E_UNSUPPORTED, "tri_launch_stencil: tile");
     hipGraph_t g = nullptr;
     TRI_HIP(hipGraphCreate(&g, 0));
     hipGraphNode_t prev = nullptr;

@@ -42,14 +42,16 @@ def _run(tm, p, g, steps, garbage_seed=None):
 
 
 @pytest.mark.parametrize("map_name", MAPS)
-@pytest.mark.parametrize("tile", [8, 16, 32, 64])
-def test_life_bit_exact(map_name, tile):
+@pytest.mark.parametrize("tile,multiple", [(8, 4), (16, 4), (32, 4), (64, 4), (64, 16)])
+def test_life_bit_exact(map_name, tile, multiple):
+    """One generation per launch; rows padded to 4 bytes, and for tile 64
+    also to 16 (the bit-sliced one-generation kernel with 16-byte rows)."""
     tm = _tm()
-    for n in (1, 2, 5, 33, 100, 257):
+    for n in (1, 2, 5, 33, 100, 257) + ((1000,) if multiple == 16 else ()):
         m = -(-n // tile)
         if map_name == "rec" and (m & (m - 1)):
             continue
-        ld = padded_ld(n)
+        ld = padded_ld(n, multiple)
         g = inputs.life(n, 0.3, seed=3000 + n, ld=ld)
         p = tm.Plan(n, tile, map_name)
         for steps in (1, 2, 7):
@@ -137,17 +139,19 @@ def test_life_full_size_windows(map_name, tile):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("map_name", ["lambda", "utm"])
-def test_life_graph_mode_matches_eager_and_replays(map_name):
+@pytest.mark.parametrize("map_name,tile,multiple", [("lambda", 32, 4), ("utm", 32, 4),
+                                                    ("lambda", 64, 16), ("bb", 64, 16)])
+def test_life_graph_mode_matches_eager_and_replays(map_name, tile, multiple):
     """use_graph builds the generations into a hipGraph once per (buffers,
     steps) and replays it; every replay, with eager work in between, equals
-    the eager launches and the oracle."""
+    the eager launches and the oracle (tile 64 with 16-byte rows: the
+    bit-sliced one-generation kernel in the graph)."""
     import torch
     tm = _tm()
     n, steps = 200, 6
-    ld = padded_ld(n)
+    ld = padded_ld(n, multiple)
     g = inputs.life(n, 0.3, seed=5, ld=ld)
-    p = tm.Plan(n, 32, map_name)
+    p = tm.Plan(n, tile, map_name)
     eager = _run(tm, p, g, steps)
     cur, nxt = dev(g), torch.zeros((n, ld), dtype=torch.uint8, device="cuda")
     state = g.copy()

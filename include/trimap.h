@@ -57,7 +57,7 @@ enum {
     TRI_FLAG_SQRT_F64 = 4u,    /* lambda: FP64 square root                             */
     TRI_FLAG_ORDER_REVERSE = 8u, /* lambda: dispatch omega from T-1 down to 0            */
     TRI_FLAG_ORDER_PAIRS = 16u,  /* lambda: alternate omega from the front and the back  */
-    TRI_FLAG_LIFE_TEMPORAL = 32u, /* stencil: up to 4 generations per launch (4-cell halo) */
+    TRI_FLAG_LIFE_TEMPORAL = 32u, /* stencil: several generations per launch (wider halo) */
     TRI_FLAG_SQRT_NEWTON = 64u,  /* lambda: bit-trick rsqrt + 3 Newton steps (lambda_N)  */
     /* lambda, for the square-root study only: the paper's inexact row
      * floor(sqrt(1/4 + 2 omega) + 1e-4 - 1/2) without the integer
@@ -213,7 +213,11 @@ tri_status tri_tet_dummy(const tri_tet *plan, int32_t target, int32_t *sink, voi
  * odd.  Requires ld % 4 == 0, ld >= n, 4-byte aligned pointers, steps >= 0.
  * With TRI_FLAG_LIFE_TEMPORAL in the plan (tiles 16, 32, 64; no graph) one
  * launch advances up to four generations from a tile staged with a 4-cell
- * halo, the number of launches keeping the parity of `steps`.  Otherwise
+ * halo (up to eight with an 8-cell halo for 64 x 64 tiles on grids of at
+ * least 512 tiles whose ld is a multiple of 16 and whose buffers are
+ * 16-byte aligned), the number of launches keeping the parity of `steps`.
+ * Tile 64 with ld a multiple of 16 and 16-byte aligned buffers also runs
+ * bit-sliced without the flag (same results).  Otherwise
  * each generation is one kernel launch; when use_graph is non-zero the
  * generations are built once into a hipGraph of kernel nodes for this
  * (cur, nxt, ld, steps), kept with the plan and replayed by every later call
@@ -355,7 +359,7 @@ tri_status tri_batch_autotune(int32_t count, const int32_t *host_kind, const int
  * it allocates and frees itself (so it is not for graph capture): zeroed,
  * except the distance maps' coordinates, uniform in [0, 1) (all-equal
  * points would time the near-duplicate recompute of every pair).
- * Life is timed over four generations (also with TRI_FLAG_LIFE_TEMPORAL
+ * Life is timed over eight generations (also with TRI_FLAG_LIFE_TEMPORAL
  * for BB and lambda at tiles 16..64) and reported per generation.  The
  * fastest candidate goes to *best and into a process-wide cache keyed by GPU
  * architecture, CU count, workload, floor(log2 n) and d (distance maps); with

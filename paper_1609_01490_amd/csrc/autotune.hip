@@ -164,8 +164,9 @@ tri_status tri_autotune(int workload, int64_t n, int64_t d, int reps, int use_ca
     Scratch sc;
     hipError_t e = hipSuccess;
     // buffers sized for the workload; contents zeroed (timing only), the
-    // distance maps' coordinates filled as above
-    const int64_t ld = (n + 3) / 4 * 4;
+    // distance maps' coordinates filled as above; Life rows padded to 16
+    // bytes (the layout the bit-sliced kernel moves as vectors)
+    const int64_t ld = workload == TRI_TUNE_LIFE ? (n + 15) / 16 * 16 : (n + 3) / 4 * 4;
     void *x = nullptr, *y = nullptr, *c = nullptr, *ws = nullptr;
     size_t ws_bytes = 0;
     switch (workload) {
@@ -229,7 +230,7 @@ tri_status tri_autotune(int workload, int64_t n, int64_t d, int reps, int use_ca
             case TRI_TUNE_ELEMENTWISE_I32:
                 return tri_launch_elementwise(p, TRI_OP_XORMUL_I32, x, y, c, ld, 0.f, s);
             case TRI_TUNE_LIFE:
-                return tri_launch_stencil(p, (uint8_t *)x, (uint8_t *)y, ld, 4, 0, s);
+                return tri_launch_stencil(p, (uint8_t *)x, (uint8_t *)y, ld, 8, 0, s);
             case TRI_TUNE_EDM_FP32:
                 return tri_edm(p, (const float *)x, d, d, (float *)c, TRI_EDM_FP32, 1e-2f, nullptr, 0, s);
             default:
@@ -255,7 +256,7 @@ tri_status tri_autotune(int workload, int64_t n, int64_t d, int reps, int use_ca
         float ms = 0.f;
         (void)hipEventElapsedTime(&ms, e0, e1);
         ms /= (float)reps;
-        if (workload == TRI_TUNE_LIFE) ms *= 0.25f;  // per generation
+        if (workload == TRI_TUNE_LIFE) ms *= 0.125f;  // per generation
         const tri_tune_choice ch{cd.tile, cd.map, cd.flags, ms};
         if (all && nall < all_cap) all[nall] = ch;
         ++nall;

@@ -32,7 +32,7 @@ bool launch_edm_f32_lambda(int tile, const TileGrid &g, const EdmTile &t, hipStr
 bool launch_life_lambda(int tile, const TileGrid &g, const LifeTile &t, hipStream_t s);
 bool launch_life_multi_lambda(int tile, const TileGrid &g, const LifeTile &t, int gens,
                               hipStream_t s);
-std::vector<int> life_multi_schedule(int steps);
+std::vector<int> life_multi_schedule(int steps, int maxgen);
 
 struct BatchDesc {
     int32_t kind;  // TRI_KIND_*
@@ -369,7 +369,7 @@ tri_status tri_batch_plan(tri_batch **out, int32_t count, const int32_t *host_ki
     b->life_tile = life_tile;
     b->steps = life_steps;
     b->temporal = (flags & TRI_FLAG_LIFE_TEMPORAL) != 0;
-    if (b->temporal && life_steps > 0) b->sched = life_multi_schedule(life_steps);
+    if (b->temporal && life_steps > 0) b->sched = life_multi_schedule(life_steps, kLifeMaxGen);
     b->kernel = b->kernel_bytes = step_kernel(edm_tile, life_tile);
     b->kernel_bits = step_kernel(edm_tile, life_tile, true);
     b->prefix0.push_back(0);

@@ -245,13 +245,14 @@ __device__ __forceinline__ uint32_t life_bits4_to_cells(uint32_t b)
 // 5 loads and 4 stores per lane and tile instead of 72 single-byte loads and
 // 64 single-byte stores, whose instruction count bounds the byte path.
 // KH: halo rows above and below the tile (and at most that many
-// generations); KH < 4 only with VEC (4 halo cells are staged left and right
-// of each row whatever KH is).
+// generations); other than 4 only with VEC, which stages 4 halo cells left
+// and right of each row for KH <= 4 and 8 for KH <= 8.
 template <bool VEC = false, int KH = kLifeMaxGen>
 __device__ __forceinline__ void life_bits_wave_body(const LifeTile &p, int32_t bi, int32_t bj,
                                                     int gens, uint32_t *lds)
 {
     static_assert(VEC || KH == kLifeMaxGen, "byte row moves stage a 4-row halo");
+    static_assert(KH >= 1 && KH <= 8, "halo");
     using S = LifeBitsShape<KH>;
     constexpr int T = S::TILE, K = S::K;
     constexpr int NWORD = S::R * S::WPR;       // 288 words per generation
@@ -284,8 +285,10 @@ __device__ __forceinline__ void life_bits_wave_body(const LifeTile &p, int32_t b
         const int32_t ldi = (int32_t)ld;
         const int32_t col = j0 + 16 * q < ldi - 16 ? j0 + 16 * q : ldi - 16;
         // every load from a clamped address first, masked afterwards
+        constexpr int HW = K > 4 ? 8 : 4;        // halo cells left and right
+        typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
         u32x4 cv[RND];
-        uint32_t hv[HR];
+        u32x2 hv[HR];
 #pragma unroll
         for (int r = 0; r < RND; ++r) {
             const int32_t gi = i0 - K + 16 * r + rr;
@@ -298,9 +301,14 @@ __device__ __forceinline__ void life_bits_wave_body(const LifeTile &p, int32_t b
             const int row = (t >> 1) < S::R ? (t >> 1) : S::R - 1;
             const int32_t gi = i0 - K + row;
             const int32_t gic = gi < 0 ? 0 : (gi >= n ? n - 1 : gi);
-            int32_t hc = (t & 1) ? j0 + T : j0 - 4;
-            hc = hc < 0 ? 0 : (hc > ldi - 4 ? ldi - 4 : hc);
-            hv[k] = *(const uint32_t *)(p.cur + (int64_t)gic * ld + hc);
+            int32_t hc = (t & 1) ? j0 + T : j0 - HW;
+            hc = hc < 0 ? 0 : (hc > ldi - HW ? ldi - HW : hc);
+            if constexpr (HW == 8) {
+                hv[k] = *(const u32x2 *)(p.cur + (int64_t)gic * ld + hc);
+            } else {
+                hv[k].x = *(const uint32_t *)(p.cur + (int64_t)gic * ld + hc);
+                hv[k].y = 0u;
+            }
         }
         __builtin_amdgcn_sched_barrier(0);
         uint16_t *A16 = (uint16_t *)A;
@@ -319,8 +327,11 @@ __device__ __forceinline__ void life_bits_wave_body(const LifeTile &p, int32_t b
         for (int k = 0; k < HR; ++k) {
             const int t = lane + 64 * k;
             if (t < 2 * S::R) {
-                const uint32_t nib = life_cells4_to_bits(hv[k]);
-                A[((t >> 1) + 1) * S::WPR + ((t & 1) ? 3 : 0)] = (t & 1) ? nib : nib << 28;
+                // west cells end at bit 31 of word 0, east cells start at
+                // bit 0 of word 3
+                const uint32_t hb8 = life_cells4_to_bits(hv[k].x) |
+                                     (HW == 8 ? life_cells4_to_bits(hv[k].y) << 4 : 0u);
+                A[((t >> 1) + 1) * S::WPR + ((t & 1) ? 3 : 0)] = (t & 1) ? hb8 : hb8 << (32 - HW);
             }
         }
         // then clear every staged bit outside the domain (rows beyond the

@@ -76,15 +76,22 @@ __global__ void __launch_bounds__(256) k_life_multi(LifeArgs p, int gens)
     life_multi_tile_body<TILE>(p.t, bi, bj, gens, buf);
 }
 
+// Generations per launch of the bit-sliced kernel with 16-byte rows (an
+// 8-row, 8-cell halo: its 80 staged rows take the same five 16-row rounds of
+// loads as the 72 of a 4-row halo)
+constexpr int kLifeBitsMaxGen = 8;
+
 // 64 x 64 tiles, bit-sliced, one wave per tile; VEC: 16-byte row loads and
-// stores (ld a multiple of 16, 16-byte aligned grids)
+// stores (ld a multiple of 16, 16-byte aligned grids) and up to
+// kLifeBitsMaxGen generations, else up to kLifeMaxGen
 template <int MAP, bool VEC>
 __global__ void __launch_bounds__(64) k_life_bits(LifeArgs p, int gens)
 {
+    constexpr int KH = VEC ? kLifeBitsMaxGen : kLifeMaxGen;
     int32_t bi, bj;
     if (!tile_of_block<MAP>(p.g, bi, bj)) return;
-    __shared__ __attribute__((aligned(16))) uint32_t buf[2 * LifeBitsShape<>::WORDS];
-    life_bits_wave_body<VEC>(p.t, bi, bj, gens, buf);
+    __shared__ __attribute__((aligned(16))) uint32_t buf[2 * LifeBitsShape<KH>::WORDS];
+    life_bits_wave_body<VEC, KH>(p.t, bi, bj, gens, buf);
 }
 
 // One generation of 64 x 64 tiles with the 1-cell halo of the paper's tiles,
@@ -132,9 +139,10 @@ constexpr uint64_t kLifeBitsMinTilesVec = 512;
 
 template <int MAP>
 static bool life_multi_kernel_tile(int tile, uint64_t tiles, bool vec, const void *&fn,
-                                   int &threads)
+                                   int &threads, int &maxgen)
 {
     threads = 256;
+    maxgen = kLifeMaxGen;
     switch (tile) {
     case 16: fn = (const void *)k_life_multi<MAP, 16>; return true;
     case 32: fn = (const void *)k_life_multi<MAP, 32>; return true;
@@ -142,6 +150,7 @@ static bool life_multi_kernel_tile(int tile, uint64_t tiles, bool vec, const voi
         if (tiles >= (vec ? kLifeBitsMinTilesVec : kLifeBitsMinTiles)) {
             fn = vec ? (const void *)k_life_bits<MAP, true> : (const void *)k_life_bits<MAP, false>;
             threads = 64;
+            if (vec) maxgen = kLifeBitsMaxGen;
         } else {
             fn = (const void *)k_life_multi<MAP, 64>;
         }
@@ -150,21 +159,26 @@ static bool life_multi_kernel_tile(int tile, uint64_t tiles, bool vec, const voi
     return false;
 }
 
-static bool life_multi_kernel(const tri_plan *p, bool vec, const void *&fn, int &threads)
+static bool life_multi_kernel(const tri_plan *p, bool vec, const void *&fn, int &threads,
+                              int &maxgen)
 {
     const uint64_t T = (uint64_t)p->T;
     switch (p->map) {
-    case TRI_MAP_BB: return life_multi_kernel_tile<MAP_BB>(p->tile, T, vec, fn, threads);
-    case TRI_MAP_RB: return life_multi_kernel_tile<MAP_RB>(p->tile, T, vec, fn, threads);
-    case TRI_MAP_REC: return life_multi_kernel_tile<MAP_REC>(p->tile, T, vec, fn, threads);
-    case TRI_MAP_LAMBDA: return life_multi_kernel_tile<MAP_LAMBDA>(p->tile, T, vec, fn, threads);
+    case TRI_MAP_BB: return life_multi_kernel_tile<MAP_BB>(p->tile, T, vec, fn, threads, maxgen);
+    case TRI_MAP_RB: return life_multi_kernel_tile<MAP_RB>(p->tile, T, vec, fn, threads, maxgen);
+    case TRI_MAP_REC: return life_multi_kernel_tile<MAP_REC>(p->tile, T, vec, fn, threads, maxgen);
+    case TRI_MAP_LAMBDA:
+        return life_multi_kernel_tile<MAP_LAMBDA>(p->tile, T, vec, fn, threads, maxgen);
     }
     return false;
 }
 
-std::vector<int> life_multi_schedule(int steps)
+// Generations of each launch for `steps` generations, at most maxgen each,
+// with as many launches as the parity of steps allows (the result lands in
+// cur for even steps, in nxt for odd).
+std::vector<int> life_multi_schedule(int steps, int maxgen)
 {
-    int L = (steps + kLifeMaxGen - 1) / kLifeMaxGen;
+    int L = (steps + maxgen - 1) / maxgen;
     if ((L & 1) != (steps & 1)) ++L;
     std::vector<int> g(L, steps / L);
     for (int k = 0; k < steps % L; ++k) ++g[k];
@@ -328,10 +342,10 @@ extern "C" tri_status tri_launch_stencil(const tri_plan *p, uint8_t *cur, uint8_
         if (use_graph)
             return fail(TRI_E_UNSUPPORTED, "tri_launch_stencil: graphs of the temporal kernel are not built");
         const void *fn = nullptr;
-        int threads = 256;
-        if (!life_multi_kernel(p, life_vec16(a.t), fn, threads))
+        int threads = 256, maxgen = kLifeMaxGen;
+        if (!life_multi_kernel(p, life_vec16(a.t), fn, threads, maxgen))
             return fail(TRI_E_UNSUPPORTED, "tri_launch_stencil: temporal blocking needs tile 16, 32 or 64");
-        const std::vector<int> sched = life_multi_schedule(steps);
+        const std::vector<int> sched = life_multi_schedule(steps, maxgen);
         for (size_t k = 0; k < sched.size(); ++k) {
             a.t.cur = (k & 1) ? nxt : cur;
             a.t.nxt = (k & 1) ? cur : nxt;

@@ -70,7 +70,7 @@ struct BatchLds {
     static constexpr int MULTI_BYTES = life_multi_bytes<TL>();
     // 64 x 64 Life tiles with several generations: one bit-sliced tile per wave
     static constexpr int BITS_BYTES =
-        TL == 64 ? kBatchThreads / 64 * 2 * LifeBitsShape<>::WORDS * 4 : 0;
+        TL == 64 ? kBatchThreads / 64 * 2 * LifeBitsShape<kLifeBitsMaxGen>::WORDS * 4 : 0;
     static constexpr int B1 = EDM_BYTES > LIFE_BYTES ? EDM_BYTES : LIFE_BYTES;
     static constexpr int B2 = B1 > MULTI_BYTES ? B1 : MULTI_BYTES;
     static constexpr int BYTES = B2 > BITS_BYTES ? B2 : BITS_BYTES;
@@ -142,8 +142,9 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch_step(BatchStepArgs a)
                         const bool even = (a.step & 1) == 0;
                         const LifeTile t{W.n, W.ld, (const uint8_t *)(even ? W.a : W.b),
                                          (uint8_t *)(even ? W.b : W.a)};
-                        uint32_t *wl = (uint32_t *)body_lds + wv * 2 * LifeBitsShape<>::WORDS;
-                        life_bits_wave_body<true>(t, bi, bj, a.gens, wl);
+                        uint32_t *wl = (uint32_t *)body_lds +
+                                       wv * 2 * LifeBitsShape<kLifeBitsMaxGen>::WORDS;
+                        life_bits_wave_body<true, kLifeBitsMaxGen>(t, bi, bj, a.gens, wl);
                     }
                     continue;  // the loop's barrier precedes the next claim
                 }
@@ -176,9 +177,20 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch_step(BatchStepArgs a)
                 const LifeTile t{D.n, D.ld, (const uint8_t *)(even ? D.a : D.b),
                                  (uint8_t *)(even ? D.b : D.a)};
                 bool done = false;
-                if constexpr (TL >= 16) {
+                if constexpr (BITS && TL == 64) {
+                    // a Life item in a chunk that also holds distance items:
+                    // the first wave takes it (nodes may advance up to
+                    // kLifeBitsMaxGen generations, beyond the byte-sliced body)
                     if (a.gens > 0) {
-                        life_multi_tile_body<TL, !BITS>(t, bi, bj, a.gens, (uint32_t *)body_lds);
+                        if (threadIdx.x < 64)
+                            life_bits_wave_body<true, kLifeBitsMaxGen>(t, bi, bj, a.gens,
+                                                                       (uint32_t *)body_lds);
+                        done = true;
+                    }
+                }
+                if constexpr (TL >= 16 && !BITS) {
+                    if (a.gens > 0) {
+                        life_multi_tile_body<TL, true>(t, bi, bj, a.gens, (uint32_t *)body_lds);
                         done = true;
                     }
                 }
@@ -486,6 +498,10 @@ tri_status tri_batch_bind(tri_batch *b, void *const *host_a, void *const *host_b
         if (D.kind == TRI_KIND_LIFE && !(D.pad & kDescVec16)) bits = false;
     b->kernel = bits ? b->kernel_bits : b->kernel_bytes;
     b->grid = bits ? b->grid_bits : b->grid_bytes;
+    // the bit-sliced kernel advances up to kLifeBitsMaxGen generations per
+    // node (fewer nodes than the plan's schedule, whose counters it reuses)
+    if (b->temporal && b->steps > 0)
+        b->sched = life_multi_schedule(b->steps, bits ? kLifeBitsMaxGen : kLifeMaxGen);
     if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
     if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
     tri_status st = batch_build_graph(b);
@@ -517,7 +533,8 @@ tri_status tri_batch_launch(tri_batch *b, int how, void *stream)
             if (b->tiles[k] == 0) continue;
             if (D.kind == TRI_KIND_EDM) {
                 const EdmTile t{D.n, D.d, D.ld, (const float *)D.a, (float *)D.b};
-                launch_edm_f32_lambda(tile, g, t, s);
+                if (!launch_edm_f32_lambda(tile, g, t, s))
+                    return fail(TRI_E_UNSUPPORTED, "tri_batch_launch: distance instance %d", k);
                 TRI_HIP(hipGetLastError());
             } else {
                 const int nodes = b->temporal ? (int)b->sched.size() : b->steps;
@@ -525,8 +542,10 @@ tri_status tri_batch_launch(tri_batch *b, int how, void *stream)
                     const bool even = (st & 1) == 0;
                     const LifeTile t{D.n, D.ld, (const uint8_t *)(even ? D.a : D.b),
                                      (uint8_t *)(even ? D.b : D.a)};
-                    if (b->temporal) launch_life_multi_lambda(tile, g, t, b->sched[st], s);
-                    else launch_life_lambda(tile, g, t, s);
+                    const bool ok = b->temporal ? launch_life_multi_lambda(tile, g, t, b->sched[st], s)
+                                                : launch_life_lambda(tile, g, t, s);
+                    if (!ok)
+                        return fail(TRI_E_UNSUPPORTED, "tri_batch_launch: Life instance %d", k);
                     TRI_HIP(hipGetLastError());
                 }
             }

@@ -193,6 +193,11 @@ __device__ __forceinline__ uint32_t life_window_mask(int32_t gi, int32_t gj, int
 // staged window are not loaded; like cells beyond the byte-sliced window
 // they only reach the tile after more than four generations.
 // ---------------------------------------------------------------------------
+// Generations per launch of the bit-sliced body with 16-byte rows (an
+// 8-row, 8-cell halo: its 80 staged rows take the same five 16-row rounds of
+// loads as the 72 of a 4-row halo)
+constexpr int kLifeBitsMaxGen = 8;
+
 template <int KH = kLifeMaxGen>
 struct LifeBitsShape {
     static constexpr int TILE = 64;

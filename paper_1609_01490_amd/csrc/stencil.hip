@@ -76,11 +76,6 @@ __global__ void __launch_bounds__(256) k_life_multi(LifeArgs p, int gens)
     life_multi_tile_body<TILE>(p.t, bi, bj, gens, buf);
 }
 
-// Generations per launch of the bit-sliced kernel with 16-byte rows (an
-// 8-row, 8-cell halo: its 80 staged rows take the same five 16-row rounds of
-// loads as the 72 of a 4-row halo)
-constexpr int kLifeBitsMaxGen = 8;
-
 // 64 x 64 tiles, bit-sliced, one wave per tile; VEC: 16-byte row loads and
 // stores (ld a multiple of 16, 16-byte aligned grids) and up to
 // kLifeBitsMaxGen generations, else up to kLifeMaxGen
@@ -195,11 +190,15 @@ bool launch_life_multi_lambda(int tile, const TileGrid &g, const LifeTile &t, in
     if (g.T <= (1ull << 24)) { gx = (uint32_t)g.T; gy = 1; }
     else { gx = 1u << 16; gy = (uint32_t)((g.T + gx - 1) / gx); }
     const dim3 grid(gx, gy);
+    if (gens > kLifeMaxGen && tile != 64) return false;
     switch (tile) {
     case 16: k_life_multi<MAP_LAMBDA, 16><<<grid, 256, 0, s>>>(a, gens); return true;
     case 32: k_life_multi<MAP_LAMBDA, 32><<<grid, 256, 0, s>>>(a, gens); return true;
     case 64:
-        if (life_vec16(t) && g.T >= kLifeBitsMinTilesVec)
+        if (gens > kLifeMaxGen) {  // only the bit-sliced kernel with 16-byte rows goes beyond 4
+            if (!life_vec16(t)) return false;
+            k_life_bits<MAP_LAMBDA, true><<<grid, 64, 0, s>>>(a, gens);
+        } else if (life_vec16(t) && g.T >= kLifeBitsMinTilesVec)
             k_life_bits<MAP_LAMBDA, true><<<grid, 64, 0, s>>>(a, gens);
         else if (!life_vec16(t) && g.T >= kLifeBitsMinTiles)
             k_life_bits<MAP_LAMBDA, false><<<grid, 64, 0, s>>>(a, gens);

@@ -342,10 +342,15 @@ class Batch:
                                   self.ds.ctypes.data, int(edm_tile), int(life_tile),
                                   int(life_steps), int(flags)))
         self._h = h
-        info = tri_batch_info()
-        _check(lib.tri_batch_query(h, ctypes.byref(info)))
-        self.info = {f: getattr(info, f) for f, _ in tri_batch_info._fields_}
         self._keep = None
+
+    @property
+    def info(self) -> dict:
+        """tri_batch_query now (binding picks the kernel, its workgroups and,
+        for the bit-sliced Life kernel, fewer graph nodes)."""
+        info = tri_batch_info()
+        _check(lib.tri_batch_query(self._h, ctypes.byref(info)))
+        return {f: getattr(info, f) for f, _ in tri_batch_info._fields_}
 
     def bind(self, a_list, b_list):
         import numpy as np

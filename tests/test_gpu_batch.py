@@ -167,3 +167,22 @@ def test_batch_autotune_choice_is_valid_and_exact():
     b, host_in, A2, B2 = _make(tm, spec, d, steps, te, tl, seed=300, flags=fl)
     b.launch(tm.BATCH_GRAPH)
     _check_oracle(spec, host_in, _results(spec, A2, B2, steps), d, steps)
+
+
+@pytest.mark.parametrize("all16,nodes", [(True, 4), (False, 6)])
+def test_batch_binding_picks_the_life_kernel(all16, nodes):
+    """20 generations with tile 64 and temporal blocking: Life grids all with
+    16-byte rows bind the bit-sliced kernel (up to 8 generations per node: 4
+    nodes), otherwise the byte-sliced one (up to 4: 6 nodes); both equal the
+    oracle."""
+    tm = _tm()
+    spec = [("life", 300), ("edm", 90), ("life", 2117), ("life", 65)]
+    d, steps = 16, 20
+    b, host_in, A, B = _make(tm, spec, d, steps, 32, 64, seed=81, flags=tm.FLAG_LIFE_TEMPORAL,
+                             all16=all16)
+    note("batch binding", all16)
+    if not all16:
+        assert any(a.stride(0) % 16 for a, (k, _) in zip(A, spec) if k == "life")
+    assert b.info["graph_nodes"] == nodes
+    b.launch(tm.BATCH_GRAPH)
+    _check_oracle(spec, host_in, _results(spec, A, B, steps), d, steps)

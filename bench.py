@@ -483,6 +483,14 @@ def profile_target(tm, torch, args):
                          device="cuda")
         for _ in range(reps):
             q.edm(xd, out, mode=tm.EDM_BF16X3, fixup_thr=1e-2, ws=ws)
+    elif t == "edm_fp32":
+        n, d = 65536, 128
+        X, _ = inputs.points(n, d)
+        xd = torch.from_numpy(X).cuda()
+        out = torch.empty((n * (n - 1) // 2,), dtype=torch.float32, device="cuda")
+        q = tm.Plan(n, args.tile or 128, "lambda", include_diag=False, flags=args.flags)
+        for _ in range(reps):
+            q.edm(xd, out, mode=tm.EDM_FP32)
     elif t == "life":
         n = 16384
         cur = torch.from_numpy(inputs.life(n, 0.3)).cuda()
@@ -510,7 +518,7 @@ def main():
     ap.add_argument("--flags", type=int, default=0)
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--profile-target", choices=["elementwise", "edm", "life", "int", "copy"],
+    ap.add_argument("--profile-target", choices=["elementwise", "edm", "edm_fp32", "life", "int", "copy"],
                     help="only launch this workload's kernels a few times (for rocprofv3 runs); "
                          "prints no JSON line")
     args = ap.parse_args()

@@ -215,22 +215,27 @@ __global__ void __launch_bounds__((TriShape<TILE>::NT)) k_triangles(TriArgs p, i
     }
     __syncthreads();
 
-    // masks: relation s pairs rows of set r(s) with columns of set c(s)
-    constexpr int RPB = 64 / TILE;           // rows per ballot
-    constexpr int BALLOTS = 3 * TILE / RPB;  // over the three relations
+    // masks: relation s pairs rows of set r(s) with columns of set c(s); a
+    // lane keeps its column point in registers through a relation's rows
+    constexpr int RPB = 64 / TILE;     // rows per ballot
+    constexpr int BPR = TILE / RPB;    // ballots per relation
+    constexpr int NW = NT / 64;        // waves
     const int w = t >> 6, l = t & 63;
-    for (int b = w; b < BALLOTS; b += NT / 64) {
-        const int s = b / (TILE / RPB);
-        const int row = (b % (TILE / RPB)) * RPB + l / TILE;
-        const int col = l % TILE;
+    const int col = l % TILE;
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
         const int rs = s == 2 ? 1 : 0, cs = s == 0 ? 1 : 2;
-        const bool hit = near3(pts[rs][row], pts[cs][col], p.r2);
-        const uint64_t bal = __ballot(hit);
-        if (l % TILE == 0) {
-            if constexpr (TILE == 64)
-                mask[s][row] = bal;
-            else
-                mask[s][row] = (M)((bal >> (l - l % TILE)) & ((1ull << TILE) - 1ull));
+        const f4 pc = pts[cs][col];
+        for (int k = w; k < BPR; k += NW) {
+            const int row = k * RPB + l / TILE;
+            const bool hit = near3(pts[rs][row], pc, p.r2);
+            const uint64_t bal = __ballot(hit);
+            if (l % TILE == 0) {
+                if constexpr (TILE == 64)
+                    mask[s][row] = bal;
+                else
+                    mask[s][row] = (M)((bal >> (l - l % TILE)) & ((1ull << TILE) - 1ull));
+            }
         }
     }
     __syncthreads();

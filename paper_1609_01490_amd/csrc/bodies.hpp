@@ -181,17 +181,19 @@ __device__ __forceinline__ uint32_t life_window_mask(int32_t gi, int32_t gj, int
 
 // ---------------------------------------------------------------------------
 // Bit-sliced variant for 64 x 64 tiles: one bit per cell, 32 cells per word.
-// The staged window (rows i0-4 .. i0+67, cells j0-4 .. j0+67) is kept as four
-// words per row covering cells j0-32 .. j0+95: word 0 holds the left halo in
-// its top four bits, words 1 and 2 the tile's 64 cells, word 3 the right halo
-// in its low four bits.  Bytes are packed with one wave ballot per 64 cells
-// and unpacked one cell per lane.  Per generation a word's eight neighbour
+// The staged window (rows i0-K .. i0+63+K, cells j0-H .. j0+63+H for a halo
+// of K rows and H = 4 or 8 cells) is kept as four words per row covering
+// cells j0-32 .. j0+95: word 0 holds the left halo in its top H bits, words
+// 1 and 2 the tile's 64 cells, word 3 the right halo in its low H bits.
+// Rows moved byte by byte are packed with one wave ballot per 64 cells and
+// unpacked one cell per lane; rows moved as 16-byte vectors are packed and
+// unpacked four cells at a time by multiplies.  Per generation a word's eight neighbour
 // planes are summed with bitwise adders: the row above and the row below as
 // 2-bit horizontal sums (west, self, east), the own row without the cell;
 // with s = their total, a cell lives next iff (s >> 1) == 1 and (s & 1 or it
 // lives now), i.e. s = 3, or s = 2 and alive (B3/S23).  Cells outside the
 // staged window are not loaded; like cells beyond the byte-sliced window
-// they only reach the tile after more than four generations.
+// they only reach the tile after more generations than the halo is deep.
 // ---------------------------------------------------------------------------
 // Generations per launch of the bit-sliced body with 16-byte rows (an
 // 8-row, 8-cell halo: its 80 staged rows take the same five 16-row rounds of

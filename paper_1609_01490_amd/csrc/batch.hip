@@ -84,8 +84,12 @@ constexpr int kChunk = 4;
 
 // BITS (64 x 64 Life tiles, every Life grid of the batch with 16-byte rows):
 // chunks of Life items go one per wave through the bit-sliced body.
+// Four waves per SIMD bound the registers at 128 (the bit-sliced body alone
+// would take about 160, three waves) with no spills; the grid is sized from
+// the occupancy this gives, and the extra resident wave hides more of the
+// memory latency of the persistent loop.
 template <int TE, int TL, bool BITS>
-__global__ void __launch_bounds__(kBatchThreads) k_batch_step(BatchStepArgs a)
+__global__ void __launch_bounds__(kBatchThreads, 4) k_batch_step(BatchStepArgs a)
 {
     __shared__ __attribute__((aligned(16))) unsigned char body_lds[BatchLds<TE, TL>::BYTES];
     __shared__ int64_t pfx[kPrefixLds];

@@ -262,8 +262,7 @@ __device__ __forceinline__ void life_bits_wave_body(const LifeTile &p, int32_t b
     static_assert(KH >= 1 && KH <= 8, "halo");
     using S = LifeBitsShape<KH>;
     constexpr int T = S::TILE, K = S::K;
-    constexpr int NWORD = S::R * S::WPR;       // 288 words per generation
-    constexpr int WPL = (NWORD + 63) / 64;     // words per lane
+    constexpr int RB = (S::R + 15) / 16;       // staged rows per lane in the update
     constexpr int CH = 18;                     // rows per load batch
     constexpr int HG = S::R / 8;               // halo groups of eight rows
     static_assert(VEC || (S::R % CH == 0 && S::R % 8 == 0), "row batches");
@@ -278,11 +277,14 @@ __device__ __forceinline__ void life_bits_wave_body(const LifeTile &p, int32_t b
         B[lane] = B[(S::PR - 1) * S::WPR + lane] = 0u;
     }
     const int32_t gj = j0 + lane;
-    uint32_t msk[WPL];
+    // the update's word layout: lane = 4 * band + column, and band b owns
+    // staged rows b * RB .. b * RB + RB - 1 of one word column
+    const int wc = lane & 3, rb0 = (lane >> 2) * RB;
+    uint32_t msk[RB];
 #pragma unroll
-    for (int k = 0; k < WPL; ++k) {
-        const int w = lane + 64 * k;
-        msk[k] = w < NWORD ? life_bits_mask(i0 - K + (w >> 2), j0 - 32 + 32 * (w & 3), n) : 0u;
+    for (int k = 0; k < RB; ++k) {
+        const int r = rb0 + k;
+        msk[k] = r < S::R ? life_bits_mask(i0 - K + r, j0 - 32 + 32 * wc, n) : 0u;
     }
     if constexpr (VEC) {
         typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
@@ -346,10 +348,8 @@ __device__ __forceinline__ void life_bits_wave_body(const LifeTile &p, int32_t b
         __builtin_amdgcn_s_waitcnt(0xc07f);
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
-        for (int k = 0; k < WPL; ++k) {
-            const int w = lane + 64 * k;
-            if (w < NWORD) A[S::WPR + w] &= msk[k];
-        }
+        for (int k = 0; k < RB; ++k)
+            if (rb0 + k < S::R) A[(rb0 + k + 1) * S::WPR + wc] &= msk[k];
     } else {
     // halo cells of all rows: lane covers row 8 q + lane / 8, cell lane % 8
     uint64_t hb[HG];
@@ -406,27 +406,44 @@ __device__ __forceinline__ void life_bits_wave_body(const LifeTile &p, int32_t b
     __builtin_amdgcn_s_waitcnt(0xc07f);
     __builtin_amdgcn_wave_barrier();
 
+    // Neighbour sums of staged row r (A's row r + 1; rows -1 and R are the
+    // zero rows): the west and east neighbours of each cell as a 2-bit sum
+    // (h0, h1) and with the cell itself (s0, s1).  A lane walks its band
+    // downwards and computes each row's sums once for the three rows that
+    // use them.
+    const auto row_sums = [&](const uint32_t *src, int r, uint32_t &s0, uint32_t &s1,
+                              uint32_t &h0, uint32_t &h1, uint32_t &x) {
+        const uint32_t *row = src + (r + 1) * S::WPR;
+        const uint32_t w = wc > 0 ? row[wc - 1] : 0u, e = wc < 3 ? row[wc + 1] : 0u;
+        x = row[wc];
+        const uint32_t W = __builtin_amdgcn_alignbit(x, w, 31), E = __builtin_amdgcn_alignbit(e, x, 1);
+        h0 = W ^ E;
+        h1 = W & E;
+        s0 = h0 ^ x;
+        s1 = h1 | (x & h0);
+    };
     for (int g = 0; g < gens; ++g) {
+        if (rb0 < S::R) {
+            uint32_t u0, u1, m0, m1, mc, q0, q1, z0, z1, z2;
+            row_sums(A, rb0 - 1, u0, u1, z0, z1, z2);
+            row_sums(A, rb0, q0, q1, m0, m1, mc);
 #pragma unroll
-        for (int k = 0; k < WPL; ++k) {
-            const int w = lane + 64 * k;
-            if (w >= NWORD) break;
-            const int r = w >> 2, c = w & 3;
-            const uint32_t *up = A + r * S::WPR, *md = up + S::WPR, *dn = md + S::WPR;
-            const uint32_t uw = c > 0 ? up[c - 1] : 0u, uc = up[c], ue = c < 3 ? up[c + 1] : 0u;
-            const uint32_t mw = c > 0 ? md[c - 1] : 0u, mc = md[c], me = c < 3 ? md[c + 1] : 0u;
-            const uint32_t dw = c > 0 ? dn[c - 1] : 0u, dc = dn[c], de = c < 3 ? dn[c + 1] : 0u;
-            const uint32_t uW = __builtin_amdgcn_alignbit(uc, uw, 31), uE = __builtin_amdgcn_alignbit(ue, uc, 1);
-            const uint32_t mW = __builtin_amdgcn_alignbit(mc, mw, 31), mE = __builtin_amdgcn_alignbit(me, mc, 1);
-            const uint32_t dW = __builtin_amdgcn_alignbit(dc, dw, 31), dE = __builtin_amdgcn_alignbit(de, dc, 1);
-            const uint32_t u0 = uW ^ uc ^ uE, u1 = (uW & uc) | (uE & (uW ^ uc));
-            const uint32_t d0 = dW ^ dc ^ dE, d1 = (dW & dc) | (dE & (dW ^ dc));
-            const uint32_t m0 = mW ^ mE, m1 = mW & mE;
-            const uint32_t t0 = u0 ^ d0 ^ m0;
-            const uint32_t c0 = (u0 & d0) | (m0 & (u0 ^ d0));
-            const uint32_t x1 = u1 ^ d1 ^ m1 ^ c0;
-            const uint32_t h2 = ((u1 & d1) | (m1 & (u1 ^ d1))) | (c0 & (u1 | d1 | m1));
-            B[(r + 1) * S::WPR + c] = x1 & ~h2 & (t0 | mc) & msk[k];
+            for (int k = 0; k < RB; ++k) {
+                const int r = rb0 + k;
+                if (r < S::R) {
+                    uint32_t d0, d1, n0, n1, nc;
+                    row_sums(A, r + 1, d0, d1, n0, n1, nc);
+                    // 0..8 live neighbours: bit 0 t0, bit 1 x1, 4 or more h2
+                    const uint32_t t0 = u0 ^ d0 ^ m0;
+                    const uint32_t c0 = (u0 & d0) | (m0 & (u0 ^ d0));
+                    const uint32_t x1 = u1 ^ d1 ^ m1 ^ c0;
+                    const uint32_t h2 = ((u1 & d1) | (m1 & (u1 ^ d1))) | (c0 & (u1 | d1 | m1));
+                    B[(r + 1) * S::WPR + wc] = x1 & ~h2 & (t0 | mc) & msk[k];
+                    u0 = q0; u1 = q1;
+                    q0 = d0; q1 = d1;
+                    m0 = n0; m1 = n1; mc = nc;
+                }
+            }
         }
         __builtin_amdgcn_s_waitcnt(0xc07f);
         __builtin_amdgcn_wave_barrier();

@@ -207,7 +207,9 @@ struct LifeBitsShape {
     static constexpr int R = TILE + 2 * K;   // staged rows
     static constexpr int PR = R + 2;         // plus a zero row above and below
     static constexpr int WPR = 4;            // words per row
-    static constexpr int WORDS = PR * WPR;   // one buffer; the body uses two
+    // one buffer and a guard word (the body uses two buffers between three
+    // zero guard words)
+    static constexpr int WORDS = PR * WPR + 2;
 };
 
 // bits b of word c (cells jb + b, jb = j0 - 32 + 32 c) of staged row gi that
@@ -266,7 +268,8 @@ __device__ __forceinline__ void life_bits_wave_body(const LifeTile &p, int32_t b
     constexpr int CH = 18;                     // rows per load batch
     constexpr int HG = S::R / 8;               // halo groups of eight rows
     static_assert(VEC || (S::R % CH == 0 && S::R % 8 == 0), "row batches");
-    uint32_t *A = lds, *B = lds + S::WORDS;
+    constexpr int BUF = S::PR * S::WPR;
+    uint32_t *A = lds + 1, *B = lds + 2 + BUF;  // lds[0], A[BUF] = B[-1], B[BUF]: zero
     const int32_t n = p.n;
     const int64_t ld = p.ld;
     const int32_t i0 = bi * T, j0 = bj * T;
@@ -275,6 +278,7 @@ __device__ __forceinline__ void life_bits_wave_body(const LifeTile &p, int32_t b
     if (lane < S::WPR) {
         A[lane] = A[(S::PR - 1) * S::WPR + lane] = 0u;
         B[lane] = B[(S::PR - 1) * S::WPR + lane] = 0u;
+        if (lane < 3) lds[lane * (BUF + 1)] = 0u;
     }
     const int32_t gj = j0 + lane;
     // the update's word layout: lane = 4 * band + column, and band b owns
@@ -410,11 +414,15 @@ __device__ __forceinline__ void life_bits_wave_body(const LifeTile &p, int32_t b
     // zero rows): the west and east neighbours of each cell as a 2-bit sum
     // (h0, h1) and with the cell itself (s0, s1).  A lane walks its band
     // downwards and computes each row's sums once for the three rows that
-    // use them.
+    // use them.  The shifts take only bit 31 of the west word and bit 0 of
+    // the east word, so the edge columns read across the row boundary (or
+    // into a guard word) without a test: bit 31 of word 3 and bit 0 of
+    // word 0 are never set, since the staged halo cells fill at most the
+    // low and the high 8 bits and a generation spreads life by one bit.
     const auto row_sums = [&](const uint32_t *src, int r, uint32_t &s0, uint32_t &s1,
                               uint32_t &h0, uint32_t &h1, uint32_t &x) {
         const uint32_t *row = src + (r + 1) * S::WPR;
-        const uint32_t w = wc > 0 ? row[wc - 1] : 0u, e = wc < 3 ? row[wc + 1] : 0u;
+        const uint32_t w = row[wc - 1], e = row[wc + 1];
         x = row[wc];
         const uint32_t W = __builtin_amdgcn_alignbit(x, w, 31), E = __builtin_amdgcn_alignbit(e, x, 1);
         h0 = W ^ E;
@@ -422,15 +430,16 @@ __device__ __forceinline__ void life_bits_wave_body(const LifeTile &p, int32_t b
         s0 = h0 ^ x;
         s1 = h1 | (x & h0);
     };
+    constexpr bool FULL = S::R % 16 == 0;  // every band holds RB rows
     for (int g = 0; g < gens; ++g) {
-        if (rb0 < S::R) {
+        if (FULL || rb0 < S::R) {
             uint32_t u0, u1, m0, m1, mc, q0, q1, z0, z1, z2;
             row_sums(A, rb0 - 1, u0, u1, z0, z1, z2);
             row_sums(A, rb0, q0, q1, m0, m1, mc);
 #pragma unroll
             for (int k = 0; k < RB; ++k) {
                 const int r = rb0 + k;
-                if (r < S::R) {
+                if (FULL || r < S::R) {
                     uint32_t d0, d1, n0, n1, nc;
                     row_sums(A, r + 1, d0, d1, n0, n1, nc);
                     // 0..8 live neighbours: bit 0 t0, bit 1 x1, 4 or more h2

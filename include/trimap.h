@@ -213,7 +213,7 @@ tri_status tri_tet_dummy(const tri_tet *plan, int32_t target, int32_t *sink, voi
  * odd.  Requires ld % 4 == 0, ld >= n, 4-byte aligned pointers, steps >= 0.
  * With TRI_FLAG_LIFE_TEMPORAL in the plan (tiles 16, 32, 64; no graph) one
  * launch advances up to four generations from a tile staged with a 4-cell
- * halo (up to eight with an 8-cell halo for 64 x 64 tiles on grids of at
+ * halo (up to sixteen with a 16-cell halo for 64 x 64 tiles on grids of at
  * least 512 tiles whose ld is a multiple of 16 and whose buffers are
  * 16-byte aligned), the number of launches keeping the parity of `steps`.
  * Tile 64 with ld a multiple of 16 and 16-byte aligned buffers also runs

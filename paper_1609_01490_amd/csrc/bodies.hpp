@@ -182,7 +182,7 @@ __device__ __forceinline__ uint32_t life_window_mask(int32_t gi, int32_t gj, int
 // ---------------------------------------------------------------------------
 // Bit-sliced variant for 64 x 64 tiles: one bit per cell, 32 cells per word.
 // The staged window (rows i0-K .. i0+63+K, cells j0-H .. j0+63+H for a halo
-// of K rows and H = 4 or 8 cells) is kept as four words per row covering
+// of K rows and H = 4, 8 or 16 cells) is kept as four words per row covering
 // cells j0-32 .. j0+95: word 0 holds the left halo in its top H bits, words
 // 1 and 2 the tile's 64 cells, word 3 the right halo in its low H bits.
 // Rows moved byte by byte are packed with one wave ballot per 64 cells and
@@ -195,10 +195,15 @@ __device__ __forceinline__ uint32_t life_window_mask(int32_t gi, int32_t gj, int
 // staged window are not loaded; like cells beyond the byte-sliced window
 // they only reach the tile after more generations than the halo is deep.
 // ---------------------------------------------------------------------------
-// Generations per launch of the bit-sliced body with 16-byte rows (an
-// 8-row, 8-cell halo: its 80 staged rows take the same five 16-row rounds of
-// loads as the 72 of a 4-row halo)
+// Generations per launch of the bit-sliced body with 16-byte rows in the
+// batched kernel (an 8-row, 8-cell halo: its 80 staged rows take the same
+// five 16-row rounds of loads as the 72 of a 4-row halo; a deeper halo does
+// not fit that kernel's 128 registers)
 constexpr int kLifeBitsMaxGen = 8;
+// The same in the stencil kernel: a 16-row, 16-cell halo (96 staged rows)
+// halves the launches, and so the round trips of the grid through HBM, for
+// a fifth more arithmetic per useful generation than the 8-row halo
+constexpr int kLifeBitsStencilGen = 16;
 
 template <int KH = kLifeMaxGen>
 struct LifeBitsShape {
@@ -255,13 +260,13 @@ __device__ __forceinline__ uint32_t life_bits4_to_cells(uint32_t b)
 // 64 single-byte stores, whose instruction count bounds the byte path.
 // KH: halo rows above and below the tile (and at most that many
 // generations); other than 4 only with VEC, which stages 4 halo cells left
-// and right of each row for KH <= 4 and 8 for KH <= 8.
+// and right of each row for KH <= 4, 8 for KH <= 8 and 16 for KH <= 16.
 template <bool VEC = false, int KH = kLifeMaxGen>
 __device__ __forceinline__ void life_bits_wave_body(const LifeTile &p, int32_t bi, int32_t bj,
                                                     int gens, uint32_t *lds)
 {
     static_assert(VEC || KH == kLifeMaxGen, "byte row moves stage a 4-row halo");
-    static_assert(KH >= 1 && KH <= 8, "halo");
+    static_assert(KH >= 1 && KH <= 16, "halo");
     using S = LifeBitsShape<KH>;
     constexpr int T = S::TILE, K = S::K;
     constexpr int RB = (S::R + 15) / 16;       // staged rows per lane in the update
@@ -298,10 +303,10 @@ __device__ __forceinline__ void life_bits_wave_body(const LifeTile &p, int32_t b
         const int32_t ldi = (int32_t)ld;
         const int32_t col = j0 + 16 * q < ldi - 16 ? j0 + 16 * q : ldi - 16;
         // every load from a clamped address first, masked afterwards
-        constexpr int HW = K > 4 ? 8 : 4;        // halo cells left and right
+        constexpr int HW = K > 8 ? 16 : (K > 4 ? 8 : 4);  // halo cells left and right
         typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
         u32x4 cv[RND];
-        u32x2 hv[HR];
+        u32x4 hv[HR];
 #pragma unroll
         for (int r = 0; r < RND; ++r) {
             const int32_t gi = i0 - K + 16 * r + rr;
@@ -316,11 +321,13 @@ __device__ __forceinline__ void life_bits_wave_body(const LifeTile &p, int32_t b
             const int32_t gic = gi < 0 ? 0 : (gi >= n ? n - 1 : gi);
             int32_t hc = (t & 1) ? j0 + T : j0 - HW;
             hc = hc < 0 ? 0 : (hc > ldi - HW ? ldi - HW : hc);
-            if constexpr (HW == 8) {
-                hv[k] = *(const u32x2 *)(p.cur + (int64_t)gic * ld + hc);
+            if constexpr (HW == 16) {
+                hv[k] = *(const u32x4 *)(p.cur + (int64_t)gic * ld + hc);
+            } else if constexpr (HW == 8) {
+                const u32x2 v = *(const u32x2 *)(p.cur + (int64_t)gic * ld + hc);
+                hv[k] = u32x4{v.x, v.y, 0u, 0u};
             } else {
-                hv[k].x = *(const uint32_t *)(p.cur + (int64_t)gic * ld + hc);
-                hv[k].y = 0u;
+                hv[k] = u32x4{*(const uint32_t *)(p.cur + (int64_t)gic * ld + hc), 0u, 0u, 0u};
             }
         }
         __builtin_amdgcn_sched_barrier(0);
@@ -342,9 +349,12 @@ __device__ __forceinline__ void life_bits_wave_body(const LifeTile &p, int32_t b
             if (t < 2 * S::R) {
                 // west cells end at bit 31 of word 0, east cells start at
                 // bit 0 of word 3
-                const uint32_t hb8 = life_cells4_to_bits(hv[k].x) |
-                                     (HW == 8 ? life_cells4_to_bits(hv[k].y) << 4 : 0u);
-                A[((t >> 1) + 1) * S::WPR + ((t & 1) ? 3 : 0)] = (t & 1) ? hb8 : hb8 << (32 - HW);
+                const uint32_t hb = life_cells4_to_bits(hv[k].x) |
+                                    (HW >= 8 ? life_cells4_to_bits(hv[k].y) << 4 : 0u) |
+                                    (HW == 16 ? life_cells4_to_bits(hv[k].z) << 8 |
+                                                    life_cells4_to_bits(hv[k].w) << 12
+                                              : 0u);
+                A[((t >> 1) + 1) * S::WPR + ((t & 1) ? 3 : 0)] = (t & 1) ? hb : hb << (32 - HW);
             }
         }
         // then clear every staged bit outside the domain (rows beyond the
@@ -416,9 +426,10 @@ __device__ __forceinline__ void life_bits_wave_body(const LifeTile &p, int32_t b
     // downwards and computes each row's sums once for the three rows that
     // use them.  The shifts take only bit 31 of the west word and bit 0 of
     // the east word, so the edge columns read across the row boundary (or
-    // into a guard word) without a test: bit 31 of word 3 and bit 0 of
-    // word 0 are never set, since the staged halo cells fill at most the
-    // low and the high 8 bits and a generation spreads life by one bit.
+    // into a guard word) without a test: generation g reads bit 31 of
+    // word 3 and bit 0 of word 0 clear, since the staged halo cells fill at
+    // most the low and the high 16 bits and the g - 1 <= 15 generations
+    // before it spread life by at most one bit each.
     const auto row_sums = [&](const uint32_t *src, int r, uint32_t &s0, uint32_t &s1,
                               uint32_t &h0, uint32_t &h1, uint32_t &x) {
         const uint32_t *row = src + (r + 1) * S::WPR;

@@ -77,12 +77,11 @@ __global__ void __launch_bounds__(256) k_life_multi(LifeArgs p, int gens)
 }
 
 // 64 x 64 tiles, bit-sliced, one wave per tile; VEC: 16-byte row loads and
-// stores (ld a multiple of 16, 16-byte aligned grids) and up to
-// kLifeBitsMaxGen generations, else up to kLifeMaxGen
-template <int MAP, bool VEC>
+// stores (ld a multiple of 16, 16-byte aligned grids) and up to KH
+// (kLifeBitsStencilGen by default) generations, else up to kLifeMaxGen
+template <int MAP, bool VEC, int KH = (VEC ? kLifeBitsStencilGen : kLifeMaxGen)>
 __global__ void __launch_bounds__(64) k_life_bits(LifeArgs p, int gens)
 {
-    constexpr int KH = VEC ? kLifeBitsMaxGen : kLifeMaxGen;
     int32_t bi, bj;
     if (!tile_of_block<MAP>(p.g, bi, bj)) return;
     __shared__ __attribute__((aligned(16))) uint32_t buf[2 * LifeBitsShape<KH>::WORDS];
@@ -145,7 +144,7 @@ static bool life_multi_kernel_tile(int tile, uint64_t tiles, bool vec, const voi
         if (tiles >= (vec ? kLifeBitsMinTilesVec : kLifeBitsMinTiles)) {
             fn = vec ? (const void *)k_life_bits<MAP, true> : (const void *)k_life_bits<MAP, false>;
             threads = 64;
-            if (vec) maxgen = kLifeBitsMaxGen;
+            if (vec) maxgen = kLifeBitsStencilGen;
         } else {
             fn = (const void *)k_life_multi<MAP, 64>;
         }
@@ -191,15 +190,21 @@ bool launch_life_multi_lambda(int tile, const TileGrid &g, const LifeTile &t, in
     else { gx = 1u << 16; gy = (uint32_t)((g.T + gx - 1) / gx); }
     const dim3 grid(gx, gy);
     if (gens > kLifeMaxGen && tile != 64) return false;
+    if (gens > kLifeBitsStencilGen) return false;
     switch (tile) {
     case 16: k_life_multi<MAP_LAMBDA, 16><<<grid, 256, 0, s>>>(a, gens); return true;
     case 32: k_life_multi<MAP_LAMBDA, 32><<<grid, 256, 0, s>>>(a, gens); return true;
     case 64:
+        // the bit-sliced kernel with 16-byte rows: the shallower halo where
+        // it suffices (the batch's launches advance up to kLifeBitsMaxGen)
         if (gens > kLifeMaxGen) {  // only the bit-sliced kernel with 16-byte rows goes beyond 4
             if (!life_vec16(t)) return false;
-            k_life_bits<MAP_LAMBDA, true><<<grid, 64, 0, s>>>(a, gens);
+            if (gens <= kLifeBitsMaxGen)
+                k_life_bits<MAP_LAMBDA, true, kLifeBitsMaxGen><<<grid, 64, 0, s>>>(a, gens);
+            else
+                k_life_bits<MAP_LAMBDA, true><<<grid, 64, 0, s>>>(a, gens);
         } else if (life_vec16(t) && g.T >= kLifeBitsMinTilesVec)
-            k_life_bits<MAP_LAMBDA, true><<<grid, 64, 0, s>>>(a, gens);
+            k_life_bits<MAP_LAMBDA, true, kLifeBitsMaxGen><<<grid, 64, 0, s>>>(a, gens);
         else if (!life_vec16(t) && g.T >= kLifeBitsMinTiles)
             k_life_bits<MAP_LAMBDA, false><<<grid, 64, 0, s>>>(a, gens);
         else k_life_multi<MAP_LAMBDA, 64><<<grid, 256, 0, s>>>(a, gens);

@@ -253,7 +253,7 @@ def test_life_temporal_full_size_whole_grid():
     assert bad.shape[0] == 0, (bad.shape[0], bad[:4].tolist())
 
 
-@pytest.mark.parametrize("steps", [1, 4, 7, 16])
+@pytest.mark.parametrize("steps", [1, 4, 7, 15, 16, 32])
 @pytest.mark.parametrize("multiple", [4, 16])
 @pytest.mark.parametrize("n", [181 * 64 + 3, 33 * 64 + 5])
 def test_life_bit_sliced_whole_grid(steps, multiple, n):
@@ -262,7 +262,8 @@ def test_life_bit_sliced_whole_grid(steps, multiple, n):
     n = 33 * 64 + 5 (595 tiles: bit-sliced with 16-byte rows, byte-sliced
     otherwise), the leading dimension padded to a multiple of 4 (rows moved
     byte by byte, up to 4 generations per launch) or of 16 (16-byte row
-    loads and stores, up to 8 generations per launch): the whole final
+    loads and stores, up to 16 generations per launch: 15 steps are one
+    launch of 15, 32 steps two of 16): the whole final
     grid against the oracle's, and nothing written above the diagonal or in
     the padding."""
     import torch

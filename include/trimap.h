@@ -359,7 +359,7 @@ tri_status tri_batch_autotune(int32_t count, const int32_t *host_kind, const int
  * it allocates and frees itself (so it is not for graph capture): zeroed,
  * except the distance maps' coordinates, uniform in [0, 1) (all-equal
  * points would time the near-duplicate recompute of every pair).
- * Life is timed over eight generations (also with TRI_FLAG_LIFE_TEMPORAL
+ * Life is timed over 32 generations (also with TRI_FLAG_LIFE_TEMPORAL
  * for BB and lambda at tiles 16..64) and reported per generation.  The
  * fastest candidate goes to *best and into a process-wide cache keyed by GPU
  * architecture, CU count, workload, floor(log2 n) and d (distance maps); with

@@ -134,6 +134,11 @@ using namespace trimap;
 
 extern "C" {
 
+// Generations per Life timing: two launches of the deepest temporal kernel
+// (the step count's parity fixes the number of launches), so that the
+// dispatch orders are ranked as long runs use them
+constexpr int kTuneLifeGens = 32;
+
 tri_status tri_autotune(int workload, int64_t n, int64_t d, int reps, int use_cache, void *stream,
                         tri_tune_choice *best, tri_tune_choice *all, int32_t all_cap,
                         int32_t *all_count)
@@ -230,7 +235,7 @@ tri_status tri_autotune(int workload, int64_t n, int64_t d, int reps, int use_ca
             case TRI_TUNE_ELEMENTWISE_I32:
                 return tri_launch_elementwise(p, TRI_OP_XORMUL_I32, x, y, c, ld, 0.f, s);
             case TRI_TUNE_LIFE:
-                return tri_launch_stencil(p, (uint8_t *)x, (uint8_t *)y, ld, 8, 0, s);
+                return tri_launch_stencil(p, (uint8_t *)x, (uint8_t *)y, ld, kTuneLifeGens, 0, s);
             case TRI_TUNE_EDM_FP32:
                 return tri_edm(p, (const float *)x, d, d, (float *)c, TRI_EDM_FP32, 1e-2f, nullptr, 0, s);
             default:
@@ -256,7 +261,7 @@ tri_status tri_autotune(int workload, int64_t n, int64_t d, int reps, int use_ca
         float ms = 0.f;
         (void)hipEventElapsedTime(&ms, e0, e1);
         ms /= (float)reps;
-        if (workload == TRI_TUNE_LIFE) ms *= 0.125f;  // per generation
+        if (workload == TRI_TUNE_LIFE) ms /= (float)kTuneLifeGens;  // per generation
         const tri_tune_choice ch{cd.tile, cd.map, cd.flags, ms};
         if (all && nall < all_cap) all[nall] = ch;
         ++nall;

@@ -360,7 +360,8 @@ tri_status tri_batch_autotune(int32_t count, const int32_t *host_kind, const int
  * except the distance maps' coordinates, uniform in [0, 1) (all-equal
  * points would time the near-duplicate recompute of every pair).
  * Life is timed over 32 generations (also with TRI_FLAG_LIFE_TEMPORAL
- * for BB and lambda at tiles 16..64) and reported per generation.  The
+ * for BB and lambda at tiles 16..64, lambda plain, swizzled, or swizzled
+ * in the pairs order) and reported per generation.  The
  * fastest candidate goes to *best and into a process-wide cache keyed by GPU
  * architecture, CU count, workload, floor(log2 n) and d (distance maps); with
  * use_cache non-zero a cached entry is returned without timing.  When `all`

@@ -123,6 +123,8 @@ static std::vector<Candidate> candidates(int workload, int64_t n)
             c.push_back({t, TRI_MAP_BB, (uint32_t)TRI_FLAG_LIFE_TEMPORAL});
             c.push_back({t, TRI_MAP_LAMBDA, (uint32_t)TRI_FLAG_LIFE_TEMPORAL});
             c.push_back({t, TRI_MAP_LAMBDA, (uint32_t)(TRI_FLAG_LIFE_TEMPORAL | TRI_FLAG_XCD_SWIZZLE)});
+            c.push_back({t, TRI_MAP_LAMBDA, (uint32_t)(TRI_FLAG_LIFE_TEMPORAL | TRI_FLAG_XCD_SWIZZLE |
+                                                       TRI_FLAG_ORDER_PAIRS)});
         }
     (void)n;
     return c;

@@ -55,6 +55,21 @@ class Timer:
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / steps  # ms per call
 
+    def median(self, fn, reps, warmup):
+        """Median over `reps` calls, each between its own pair of events."""
+        torch = self.torch
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        s = torch.cuda.current_stream()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+        ev[0].record(s)
+        for r in range(reps):
+            fn()
+            ev[r + 1].record(s)
+        torch.cuda.synchronize()
+        return float(np.median([ev[r].elapsed_time(ev[r + 1]) for r in range(reps)]))
+
 
 def src_digest(*names):
     h = hashlib.sha256()
@@ -64,11 +79,12 @@ def src_digest(*names):
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(kernel_tag: str, digest: str):
-    """HBM bytes per launch measured with rocprofv3 --pmc (FETCH_SIZE and
-    WRITE_SIZE, scaled by a plain copy of known size), recorded under
-    profiles/ with the digest of the kernel sources they were taken on.
-    None when no record matches the current sources."""
+def profile_value(kernel_tag: str, field: str, digest: str):
+    """A figure measured with rocprofv3 counters (e.g. hbm_bytes_per_launch:
+    FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known size;
+    mfma_busy: the matrix cores' busy fraction), recorded under profiles/
+    with the digest of the kernel sources it was taken on.  None when no
+    record matches the current sources."""
     pdir = os.path.join(ROOT, "profiles")
     if not os.path.isdir(pdir):
         return None
@@ -79,32 +95,71 @@ def traffic_from_profiles(kernel_tag: str, digest: str):
         if f"traffic_kernel: {kernel_tag}" not in txt:
             continue
         m_d = re.search(r"src_digest: (\w+)", txt)
-        m_b = re.search(r"hbm_bytes_per_launch: ([0-9.eE+]+)", txt)
+        m_b = re.search(field + r": ([0-9.eE+]+)", txt)
         if m_d and m_b and m_d.group(1) == digest:
             return float(m_b.group(1))
     return None
 
 
-def cpu_baseline_elementwise(a, X, Y, budget_s=12.0):
-    """The oracle (single-threaded C) on a bounded sample of rows of the same
-    workload: bands of 64 rows spread over the matrix, until budget_s."""
+def traffic_from_profiles(kernel_tag: str, digest: str):
+    return profile_value(kernel_tag, "hbm_bytes_per_launch", digest)
+
+
+def host_threads():
+    """Worker threads for the oracle on this host: the CPUs this process may
+    run on, at most 16 (one GPU's share of a shared host)."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return max(1, min(16, avail))
+
+
+def host_cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline_elementwise(a, X, Y, passes=3):
+    """The oracle (plain C, no GIL while it runs) on the whole workload: the
+    triangle split into bands of 64 rows handed to a pool of host threads,
+    each band written to the thread's own buffer; `passes` passes, the
+    median reported."""
+    import concurrent.futures as cf
+    import threading
     import oracle
     n = X.shape[0]
-    rng = np.random.default_rng(5)
-    starts = rng.permutation(n // 64) * 64
-    out = np.empty((64, n), dtype=np.float32)
-    done_el, t0 = 0, time.perf_counter()
-    bands = 0
-    for r0 in starts.tolist():
-        oracle.c1(a, X, Y, out, r0=r0, r1=r0 + 64)
-        done_el += sum(i + 1 for i in range(r0, r0 + 64))
-        bands += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": done_el / dt, "unit": "elements/s", "cores": 1, "kind": "oracle",
-            "sample": f"{bands} bands of 64 rows ({done_el} cells) of the n=32768 fp32 "
-                      f"elementwise workload, {dt:.1f} s"}
+    threads = host_threads()
+    local = threading.local()
+
+    def band(r0):
+        out = getattr(local, "out", None)
+        if out is None:
+            out = local.out = np.empty((64, n), dtype=np.float32)
+        oracle.c1(a, X, Y, out, r0=r0, r1=min(n, r0 + 64))
+
+    # heaviest bands first, so the last ones to finish are short
+    starts = list(range(0, n, 64))[::-1]
+    times = []
+    with cf.ThreadPoolExecutor(threads) as ex:
+        list(ex.map(band, starts[:threads]))  # first touch of the thread buffers
+        for _ in range(passes):
+            t0 = time.perf_counter()
+            list(ex.map(band, starts))
+            times.append(time.perf_counter() - t0)
+    dt = float(np.median(times))
+    E = n * (n + 1) // 2
+    return {"value": E / dt, "unit": "elements/s", "cores": threads, "kind": "oracle",
+            "host_cpus": os.cpu_count(), "cpu_model": host_cpu_model(),
+            "sample": f"the whole n={n} fp32 elementwise triangle ({E} cells) in "
+                      f"{len(starts)} bands of 64 rows on {threads} threads, median of "
+                      f"{passes} passes ({dt:.2f} s each)"}
 
 
 def tune_table(tm, workload, n, d=0, reps=3):
@@ -147,10 +202,47 @@ def bench_elementwise(tm, torch, args, timer):
     res["stream_add_GBps"] = 12 * n * n / (ms_add * 1e-3) / 1e9
     log(f"stream add (12 B per element over {n}x{n}): {ms_add:.4f} ms, "
         f"{res['stream_add_GBps']:.0f} GB/s")
+    if not args.no_extra:
+        res["probes"] = bench_probes(tm, torch, timer, c, xd, yd)
     cpu = None if args.no_cpu else cpu_baseline_elementwise(a, X, Y)
     del xd, yd, c
     torch.cuda.empty_cache()
     return n, E, res, cpu, table
+
+
+def bench_probes(tm, torch, timer, c, x, y):
+    """The bandwidth a plain streaming kernel reaches for each access mix
+    (read, two reads and one write, write, copy) over the same 4 GiB
+    buffers as the elementwise workload: a sweep of vectors in flight per
+    thread, workgroup size, cache policy and grid (one chunk per workgroup,
+    or 8 persistent workgroups per CU), each timed as the median of 5
+    launches.  Bytes counted: 4 GiB per read or written buffer."""
+    flat = [t.view(-1) for t in (c, x, y)]
+    nbytes = flat[0].numel() * 4
+    streams = {tm.PROBE_READ: 1, tm.PROBE_ADD: 3, tm.PROBE_FILL: 1, tm.PROBE_COPY: 2}
+    names = {tm.PROBE_READ: "read", tm.PROBE_ADD: "add_2r1w", tm.PROBE_FILL: "fill",
+             tm.PROBE_COPY: "copy_1r1w"}
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    out = {}
+    for kind in (tm.PROBE_READ, tm.PROBE_ADD, tm.PROBE_FILL, tm.PROBE_COPY):
+        table = {}
+        for unroll in (1, 2, 4, 8):
+            for threads in (256, 512, 1024):
+                for nt in (False, True):
+                    for wg in (0, 8 * cus):
+                        fn = lambda: tm.stream_probe(kind, flat[0], flat[1], flat[2],
+                                                     unroll=unroll, threads=threads,
+                                                     nontemporal=nt, workgroups=wg)
+                        ms = timer.median(fn, 5, 1)
+                        key = f"u{unroll}/t{threads}/{'nt' if nt else 'c'}/" + \
+                              ("persistent" if wg else "chunked")
+                        table[key] = round(streams[kind] * nbytes / (ms * 1e-3) / 1e9, 1)
+        best = max(table, key=table.get)
+        out[names[kind]] = {"best": best, "best_GBps": table[best],
+                            "best_frac_of_hbm": round(table[best] / HBM_PEAK_GBS, 4),
+                            "GBps": table}
+        log(f"probe {names[kind]}: best {best} {table[best]:.0f} GB/s")
+    return out
 
 
 def graph_time(torch, timer, fn, launches):
@@ -201,13 +293,17 @@ def bench_int_elementwise(tm, torch, timer, tile=16, launches=200):
             "I_lambda_vs_bb": round(out[f"bb/t{tile}"] / out[f"lambda/t{tile}"], 4)}
 
 
-def bench_life(tm, torch, timer, steps=100):
-    """Life n = 16384, 100 generations: lambda and BB each at the tile (and,
-    for lambda, swizzle) the autotuner finds fastest; the per-generation
-    table of every map x tile is reported too."""
+def bench_life(tm, torch, timer, steps=100, reps=7):
+    """Life n = 16384, 100 generations.  The autotuner ranks every map x tile
+    (x temporal blocking) candidate on that same schedule (one timed call =
+    100 generations, median of 5 calls); lambda and BB then each run at
+    their best candidate, timed as the median of `reps` calls of 100
+    generations.  The paper's form (one generation per launch, 1-cell halo)
+    is timed the same way at each map's best one-generation candidate."""
     from paper_1609_01490_amd import inputs
     n = 16384
-    _, table = tune_table(tm, tm.TUNE_LIFE, n, reps=2)
+    tm.tune_cache_clear()
+    _, table = tm.autotune(tm.TUNE_LIFE, n, steps, reps=5, use_cache=False)
     g = inputs.life(n, 0.3)
     cur = torch.from_numpy(g).cuda()
     nxt = torch.zeros_like(cur)
@@ -216,31 +312,83 @@ def bench_life(tm, torch, timer, steps=100):
     for map_name in ("lambda", "bb"):
         ch = best_of(table, map_name)
         p = tm.Plan(n, ch["tile"], map_name, flags=ch["flags"])
-        ms = timer.run(lambda: p.stencil(cur, nxt, steps), 3, 1)
-        out[map_name] = {"ms": round(ms, 4), "tile": ch["tile"], "flags": ch["flags"]}
+        ms = timer.median(lambda: p.stencil(cur, nxt, steps), reps, 1)
+        out[map_name] = {"ms": round(ms, 4), "tile": ch["tile"], "flags": ch["flags"],
+                         "tuned_ms_per_generation": round(ch["ms"], 5)}
         # the paper's form: one generation per launch, tiles with a 1-cell halo
         c1 = best_of(one_gen, map_name)
         q = tm.Plan(n, c1["tile"], map_name, flags=c1["flags"])
-        ms1 = timer.run(lambda: q.stencil(cur, nxt, steps), 3, 1)
+        ms1 = timer.median(lambda: q.stencil(cur, nxt, steps), reps, 1)
         one[map_name] = {"ms": round(ms1, 4), "tile": c1["tile"], "flags": c1["flags"]}
     cells = n * (n + 1) // 2
     del cur, nxt
     torch.cuda.empty_cache()
     lam = out["lambda"]["ms"]
-    return {"n": n, "steps": steps, "ms_100_steps": out,
+    lam1 = one["lambda"]["ms"]
+    return {"n": n, "steps": steps, "timing": f"median of {reps} calls of {steps} generations",
+            "ms_100_steps": out,
             "cell_updates_per_s": round(cells * steps / (lam * 1e-3), 1),
-            "GBps_algorithmic": round(2 * cells * steps / (lam * 1e-3) / 1e9, 1),
+            "generation_work_GBps": round(2 * cells * steps / (lam * 1e-3) / 1e9, 1),
             "I_lambda_vs_bb": round(out["bb"]["ms"] / lam, 4),
             "one_generation_per_launch_ms_100_steps": one,
-            "one_generation_I_lambda_vs_bb": round(one["bb"]["ms"] / one["lambda"]["ms"], 4),
+            "one_generation_I_lambda_vs_bb": round(one["bb"]["ms"] / lam1, 4),
+            # one generation per launch moves 2 B per cell (read + write):
+            # that is a true HBM figure, unlike the temporal path's
+            "one_generation_GBps": round(2 * cells * steps / (lam1 * 1e-3) / 1e9, 1),
+            "one_generation_frac_of_hbm": round(2 * cells * steps / (lam1 * 1e-3) / 1e9
+                                                / HBM_PEAK_GBS, 4),
             "per_generation_ms_by_map_tile": {f"{c['map']}/t{c['tile']}/f{c['flags']}":
-                                              round(c["ms"], 4) for c in table}}
+                                              round(c["ms"], 5) for c in table}}
 
 
-def bench_edm(tm, torch, timer):
+def edm_sample_rows(n, pairs):
+    """4096 seeded random rows plus the row of every near-duplicate pair."""
+    rng = np.random.default_rng(4096)
+    return sorted(set(rng.choice(np.arange(1, n), 4096, replace=False).tolist())
+                  | set(pairs.max(axis=1).tolist()))
+
+
+def edm_oracle_rows(X, rows):
+    """FP64 oracle distances of whole rows, on the host's threads (the
+    oracle's C loop runs without the GIL)."""
+    import concurrent.futures as cf
+    import oracle
+    oracle.lib()
+    threads = host_threads()
+    chunks = [rows[k::4 * threads] for k in range(4 * threads)]
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(threads) as ex:
+        res = list(ex.map(lambda c: oracle.edm_rows(X, c), chunks))
+    dt = time.perf_counter() - t0
+    exp = {}
+    for c, es in zip(chunks, res):
+        exp.update(zip(c, es))
+    return exp, dt, threads
+
+
+def edm_rows_error(torch, out, rows, exp):
+    """Max and 99.9th-percentile relative error of the device distances of
+    the given whole rows against the oracle's."""
+    offs = [r * (r - 1) // 2 for r in rows]
+    got = torch.cat([out[o:o + r] for o, r in zip(offs, rows)]).cpu().numpy()
+    rels, worst, k = [], 0.0, 0
+    for r in rows:
+        g = got[k:k + r].astype(np.float64)
+        k += r
+        e = exp[r]
+        nz = e > 0
+        rel = np.abs(g[nz] - e[nz]) / e[nz]
+        if rel.size:
+            worst = max(worst, float(rel.max()))
+            rels.append(rel.astype(np.float32))
+    allrel = np.concatenate(rels)
+    return worst, float(np.percentile(allrel, 99.9)), int(allrel.size)
+
+
+def bench_edm(tm, torch, timer, check=True):
     from paper_1609_01490_amd import inputs
     n, d = 65536, 128
-    X, _ = inputs.points(n, d)
+    X, dup_pairs = inputs.points(n, d)
     xd = torch.from_numpy(X).cuda()
     out = torch.empty((n * (n - 1) // 2,), dtype=torch.float32, device="cuda")
     pairs = n * (n - 1) // 2
@@ -250,7 +398,7 @@ def bench_edm(tm, torch, timer):
     res["fp32_tile"] = 128
     res["fp32_ms"] = round(ms, 4)
     res["fp32_pairs_per_s"] = round(pairs / (ms * 1e-3), 1)
-    _, table = tune_table(tm, tm.TUNE_EDM_BF16X3, n, d, reps=2)
+    _, table = tune_table(tm, tm.TUNE_EDM_BF16X3, n, d, reps=3)
     best = best_of(table, "lambda")  # the lambda variant (swizzle, order) the autotuner finds fastest
     q = tm.Plan(n, 128, "lambda", include_diag=False, flags=best["flags"])
     res["mfma_map"] = best["map"]
@@ -261,14 +409,36 @@ def bench_edm(tm, torch, timer):
     if bb:
         res["bf16x3_I_vs_bb"] = {k: round(bb[0] / v, 4)
                                  for k, v in res["bf16x3_tune_ms_by_map"].items()}
+    rows = exp = None
+    if check:
+        rows = edm_sample_rows(n, dup_pairs)
+        exp, dt, thr = edm_oracle_rows(X, rows)
+        res["accuracy_rows"] = (f"{len(rows)} whole rows: 4096 seeded random rows and the row "
+                                f"of every one of the {len(dup_pairs)} near-duplicate pairs; "
+                                f"FP64 oracle on {thr} host threads, {dt:.1f} s")
+    digest = src_digest("edm.hip", "maps.hpp")
     for mode, name in ((tm.EDM_BF16X3, "bf16x3"), (tm.EDM_BF16, "bf16")):
         ws = torch.empty(q.edm_workspace_size(d, mode), dtype=torch.uint8, device="cuda")
         ms = timer.run(lambda: q.edm(xd, out, mode=mode, fixup_thr=1e-2, ws=ws), 5, 2)
         res[f"{name}_ms"] = round(ms, 4)
         res[f"{name}_pairs_per_s"] = round(pairs / (ms * 1e-3), 1)
         res[f"{name}_write_GBps"] = round(4 * pairs / (ms * 1e-3) / 1e9, 1)
+        res[f"{name}_frac_of_hbm_write"] = round(4 * pairs / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
         res[f"{name}_speedup_vs_fp32"] = round(res["fp32_ms"] / ms, 3)
+        if check:
+            # the output of the timed launches (the last one is still in out)
+            torch.cuda.synchronize()
+            worst, p999, cnt = edm_rows_error(torch, out, rows, exp)
+            res[f"{name}_max_rel_err"] = worst
+            res[f"{name}_p999_rel_err"] = p999
+            res[f"{name}_err_pairs"] = cnt
+        tag = f"edm_{name}_n{n}_d{d}_lambda_t128_f{best['flags']}"
+        res[f"{name}_mfma_busy"] = profile_value(tag, "mfma_busy", digest)
         del ws
+    res["bf16x3_meets_1e-3"] = None if not check else res["bf16x3_max_rel_err"] <= 1e-3
+    res["bf16_note"] = ("single BF16 rounds each centred coordinate to 8 significant bits: "
+                        "its error is absolute, 2^-8 (|x_i| + |x_j|) per distance, and it is "
+                        "not held to the 1e-3 relative target")
     del xd, out
     torch.cuda.empty_cache()
     return {"n": n, "d": d, **res}
@@ -311,7 +481,7 @@ VALU_LANE_OPS = 256 * 128 * 2.4e9
 
 
 def bench_map_study(tm, torch, timer, sizes=(4096, 32768), tile=16):
-    """The square-root study of Section 5.1 on the dummy kernel (the map, the
+    """The square-root study of Section 4.1 on the dummy kernel (the map, the
     per-cell test, no stores): BB, RB, REC, UTM and lambda with each square
     root (FP32 root / x rsq / bit-trick + 3 Newton steps / FP64, all with the
     integer correction, and the paper's +1e-4 forms without it), as
@@ -334,7 +504,7 @@ def bench_map_study(tm, torch, timer, sizes=(4096, 32768), tile=16):
 
 
 def bench_collide(tm, torch, timer, n=131072):
-    """Sphere collision counts (the shared-memory test of Section 4.1), 1-D
+    """Sphere collision counts (the shared-memory test of Section 5), 1-D
     and 3-D, every map at tiles 16, 32, 64, 128 (UTM: thread space), with the
     improvement factor over BB at the same tile.  Vector-ALU-bound: 11 VALU
     operations per pair test in 3-D, 5 in 1-D, against 256 CUs x 128 FP32
@@ -446,15 +616,26 @@ def bench_batch(tm, torch, timer, steps=20, d=32, tiles=None):
     for how, name in ((tm.BATCH_GRAPH, "graph"), (tm.BATCH_STREAM, "stream"),
                       (tm.BATCH_PER_INSTANCE, "per_instance")):
         res[name] = round(timer.run(lambda: b.launch(how), 3, 1), 4)
-    alg_bytes = 4 * pairs + 2 * cells * steps
+    info = b.info
+    nodes = info["graph_nodes"]
+    n_edm = sum(1 for k in kinds if k == tm.KIND_EDM)
+    # per-instance mode: one launch per distance map, and per Life instance
+    # one launch per graph node (each node advances Life by its share of the
+    # generations: `steps` nodes of one generation, or fewer temporally
+    # blocked ones)
+    launches = n_edm + (len(kinds) - n_edm) * nodes
+    work_bytes = 4 * pairs + 2 * cells * steps
     out = {"instances": len(spec), "edm_tile": te, "life_tile": tl, "flags": fl,
-           "graph_nodes": b.info["graph_nodes"], "tiles_from": (
+           "graph_nodes": nodes, "tiles_from": (
                "tri_batch_autotune" if tiles is None else "given"),
            "life_steps": steps, "d": d, "edm_pairs": pairs, "life_cells": cells,
-           "launches_per_instance_mode": sum(1 if k == tm.KIND_EDM else steps for k in kinds),
+           "launches_per_instance_mode": launches,
            "ms": res, "speedup_graph_vs_per_instance": round(res["per_instance"] / res["graph"], 3),
-           "GBps_algorithmic_graph": round(alg_bytes / (res["graph"] * 1e-3) / 1e9, 1),
-           "persistent_workgroups": b.info["persistent_workgroups"]}
+           # 4 B per distance plus 2 B per cell and generation: the work as if
+           # every generation went through HBM, not a bandwidth (temporal
+           # blocking moves a Life cell through HBM once per node)
+           "generation_work_GBps_graph": round(work_bytes / (res["graph"] * 1e-3) / 1e9, 1),
+           "persistent_workgroups": info["persistent_workgroups"]}
     b.close()
     del A, B
     torch.cuda.empty_cache()
@@ -554,6 +735,9 @@ def main():
 
     extra = {"stream_add_ceiling_GBps": round(res["stream_add_GBps"], 1),
              "frac_of_stream_add": round(achieved / res["stream_add_GBps"], 4),
+             "probes": res.get("probes"),
+             "frac_of_best_2r1w_probe": (round(achieved / res["probes"]["add_2r1w"]["best_GBps"], 4)
+                                         if res.get("probes") else None),
              "I_lambda_vs_bb_elementwise": round(res["bb"][0] / ms, 4),
              "bb_ms": round(res["bb"][0], 4), "bb_tile": res["bb"][1], "src_digest": digest,
              "elementwise_ms_by_map_tile": {f"{c['map']}/t{c['tile']}/f{c['flags']}":

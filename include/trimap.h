@@ -69,13 +69,13 @@ enum {
 /* Elementwise bodies. */
 enum {
     /* C[i][j] = (A[i] XOR B[j]) + i*j, uint32 wrap-around; x = A (uint32[n]),
-     * y = B (uint32[n]), c = C (int32 n x ld).  Dummy-kernel role, Section 4.1. */
+     * y = B (uint32[n]), c = C (int32 n x ld).  Dummy-kernel role, Sections 4.1 and 5. */
     TRI_OP_XORMUL_I32 = 0,
     /* C[i][j] = fl(fl(a * X[i][j]) + Y[j][i]), two binary32 roundings, no
      * fused multiply-add; x = X, y = Y, c = C (float n x ld each). */
     TRI_OP_AXPYT_F32 = 1,
     /* Euclidean distance of four features, the global-memory distance test
-     * of Section 4.1: x = P (float[n][4], 16-byte aligned), y unused (may be
+     * of Section 5: x = P (float[n][4], 16-byte aligned), y unused (may be
      * NULL), c = C (float n x ld).  With p = P[i], q = P[j] and every step
      * rounded to binary32 (no fused multiply-add):
      * C[i][j] = sqrt(((dx*dx + dy*dy) + dz*dz) + dw*dw), d. = p. - q.,
@@ -149,7 +149,7 @@ tri_status tri_lambda_eval(const uint64_t *dev_omega, int64_t count, int include
 tri_status tri_launch_elementwise(const tri_plan *plan, int op, const void *x, const void *y,
                                   void *c, int64_t ld, float a, void *stream);
 
-/* The dummy kernel of the square-root study (Section 5.1): every cell
+/* The dummy kernel of the square-root study (Section 4.1): every cell
  * (i, j) of the plan's domain (any map, tile 8 to 64, with or without the
  * diagonal) forms its coordinates through the map and computes i + j; cells
  * with i + j == target store that sum to sink[0] (device int32).  A target
@@ -202,7 +202,11 @@ tri_status tri_triangles(const tri_tet *plan, const float *points, float r2, int
  * with a + b + c == target store it to sink[0] (device int32). */
 tri_status tri_tet_dummy(const tri_tet *plan, int32_t target, int32_t *sink, void *stream);
 
-/* Game of Life B3/S23 on the lower triangle (include_diag must be 1).  The
+/* Game of Life B3/S23 on the lower triangle (include_diag must be 1): the
+ * cellular automaton on a triangular domain that the Introduction (Section
+ * 1) names among the problems the map serves, run with the shared-memory
+ * tile pattern of the collision test of Section 5 (each tile and its halo
+ * staged on chip).  The
  * tile maps stage each tile with a one-cell halo in LDS; UTM (thread space)
  * has no 2-D block, so its threads read their eight neighbours from global
  * memory (and it has no temporal blocking).  cur and nxt
@@ -245,7 +249,7 @@ tri_status tri_edm_workspace_size(const tri_plan *plan, int64_t d, int mode, siz
 tri_status tri_edm(const tri_plan *plan, const float *x, int64_t d, int64_t ldx, float *out,
                    int mode, float fixup_thr, void *ws, size_t ws_bytes, void *stream);
 
-/* Collision detection of n spheres (the shared-memory test of Section 4.1).
+/* Collision detection of n spheres (the shared-memory test of Section 5).
  * The plan covers the strict lower triangle (include_diag must be 0); any
  * map, tile 8, 16, 32, 64 or 128 (tile maps stage both blocks of spheres in
  * LDS; UTM reads them from global memory per pair).  spheres is n x 4 FP32
@@ -347,23 +351,29 @@ tri_status tri_batch_autotune(int32_t count, const int32_t *host_kind, const int
                               float *best_ms);
 
 /* ------------------------------------------------------------------------
- * Autotuner: tile size and map for a workload and problem size.
+ * Autotuner: tile size and map for a workload and problem size.  Not part
+ * of the paper's method (its Section 5 compares the maps at fixed sizes);
+ * a tool of this library that picks among the paper's maps on this GPU.
  *
  * tri_autotune times every candidate (tiles 8/16/32/64 — plus 128 for the
  * fp32 elementwise body, 16/32/64/128 for the FP32 distance map, 128 for the
  * MFMA one — times maps BB, RB, REC (when
  * m is a power of two) and lambda, the latter plain, with
  * TRI_FLAG_XCD_SWIZZLE, TRI_FLAG_ORDER_REVERSE, TRI_FLAG_ORDER_PAIRS and
- * swizzle + pairs, plus UTM for the elementwise bodies and Life) on this GPU: one warm-up and `reps` timed calls
- * with HIP events on `stream`, on scratch buffers of the problem's size that
- * it allocates and frees itself (so it is not for graph capture): zeroed,
- * except the distance maps' coordinates, uniform in [0, 1) (all-equal
- * points would time the near-duplicate recompute of every pair).
- * Life is timed over 32 generations (also with TRI_FLAG_LIFE_TEMPORAL
- * for BB and lambda at tiles 16..64, lambda plain, swizzled, or swizzled
- * in the pairs order) and reported per generation.  The
- * fastest candidate goes to *best and into a process-wide cache keyed by GPU
- * architecture, CU count, workload, floor(log2 n) and d (distance maps); with
+ * swizzle + pairs, plus UTM for the elementwise bodies and Life) on this
+ * GPU: one warm-up and `reps` timed calls, each between two HIP events on
+ * `stream`, ranked by the median of the calls, on scratch buffers of the
+ * problem's size that it allocates and frees itself (so it is not for graph
+ * capture): zeroed, except the distance maps' coordinates, uniform in
+ * [0, 1) (all-equal points would time the near-duplicate recompute of every
+ * pair).  d is the dimension of the distance maps; for Life it is the
+ * number of generations of one timed call (0: 32), so that a caller ranks
+ * the candidates on the schedule it runs.  Life candidates include
+ * TRI_FLAG_LIFE_TEMPORAL for BB and lambda at tiles 16..64 (lambda plain,
+ * swizzled, or swizzled in the pairs order); Life times are reported per
+ * generation.  The fastest candidate goes to *best and into a process-wide
+ * cache keyed by GPU architecture, CU count, workload, floor(log2 n) and d
+ * (distance maps and Life); with
  * use_cache non-zero a cached entry is returned without timing.  When `all`
  * is non-NULL up to all_cap timed candidates are written there and their
  * number to *all_count.
@@ -398,6 +408,23 @@ tri_status tri_tune_cache_clear(void);
  * plain kernel with the elementwise body's mix (two reads, one write)
  * reaches on this GPU. */
 tri_status tri_stream_add(float *c, const float *a, const float *b, int64_t count, void *stream);
+
+/* Measurement probe sweep: one streaming kernel over count FP32 (a multiple
+ * of 4, 16-byte aligned device buffers) with a chosen access mix, to find
+ * the bandwidth a plain kernel of each mix reaches on this GPU:
+ *   kind 0  read a (each workgroup's sum feeds a store to c that no run
+ *           takes),
+ *   kind 1  c = a + b (two reads, one write: the fp32 elementwise mix),
+ *   kind 2  fill c (write only; a and b unused),
+ *   kind 3  c = a (one read, one write).
+ * c holds count floats for every kind.  Each thread keeps `unroll` (1, 2, 4 or 8) 16-byte vectors per read stream
+ * in flight; workgroups of `threads` (64 .. 1024, a power of two) walk the
+ * buffers in chunks of threads * unroll vectors, grid-stride; `workgroups`
+ * caps the grid (0: one chunk per workgroup, no loop); `nontemporal`
+ * selects non-temporal loads and stores. */
+tri_status tri_stream_probe(int kind, int unroll, int threads, int nontemporal,
+                            int64_t workgroups, float *c, const float *a, const float *b,
+                            int64_t count, void *stream);
 
 /* Human-readable name of a status, and the last error message of the
  * calling thread ("" if none). */

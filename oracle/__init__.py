@@ -14,21 +14,30 @@ from __future__ import annotations
 import ctypes
 import os
 import subprocess
+import threading
 
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "trimap_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# a prebuilt oracle library to load instead (the sanitizer test builds one)
+_LIB_OVERRIDE = os.environ.get("TRIMAP_ORACLE_LIB")
 
 BB, RB, REC, UTM, LAMBDA = 0, 1, 2, 3, 4
 MAP_NAMES = {"bb": BB, "rb": RB, "rec": REC, "utm": UTM, "lambda": LAMBDA}
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (no HIP, no shared headers)."""
+def build(force: bool = True, out: str | None = None, extra_flags=()) -> str:
+    """Compile the oracle with gcc (no HIP, no shared headers); `out` and
+    `extra_flags` build a variant elsewhere (e.g. with sanitizers)."""
+    if out is not None:
+        subprocess.check_call(
+            ["gcc", "-O1", "-g", "-std=c11", "-ffp-contract=off", "-fPIC", "-shared",
+             *extra_flags, "-o", out, _SRC, "-lm"])
+        return out
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
+        tmp = f"{_LIB}.tmp{os.getpid()}"
         subprocess.check_call(
             ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fPIC", "-shared",
              "-o", tmp, _SRC, "-lm"])
@@ -37,13 +46,25 @@ def build(force: bool = True) -> str:
 
 
 _lib = None
+_lib_lock = threading.Lock()
 
 
 def lib() -> ctypes.CDLL:
     global _lib
+    if _lib is not None:
+        return _lib
+    with _lib_lock:
+        return _load()
+
+
+def _load() -> ctypes.CDLL:
+    global _lib
     if _lib is None:
-        build(force=False)
-        L = ctypes.CDLL(_LIB)
+        if _LIB_OVERRIDE:
+            L = ctypes.CDLL(_LIB_OVERRIDE)
+        else:
+            build(force=False)
+            L = ctypes.CDLL(_LIB)
         i64, u64, vp = ctypes.c_int64, ctypes.c_uint64, ctypes.c_void_p
         p64 = ctypes.POINTER(ctypes.c_int64)
         L.orc_isqrt.restype = u64

@@ -256,7 +256,7 @@ int orc_utm_pair(int64_t N, int64_t k, int64_t *a, int64_t *b)
 /* Integer body: for every cell (i, j) with 0 <= j <= i < n,
  *   C[i][j] = (A[i] XOR B[j]) + i*j   in uint32 arithmetic (mod 2^32).
  * Rows r0..r1-1 are computed into out (row r at out + (r-r0)*ldo); cells
- * j > i of out are not written.  The dummy-kernel role of Section 4.1, with
+ * j > i of out are not written.  The dummy-kernel role of Sections 4.1 and 5, with
  * a real per-cell write. */
 void orc_c0(int64_t n, const uint32_t *A, const uint32_t *B, int64_t r0, int64_t r1,
             int32_t *out, int64_t ldo)
@@ -379,7 +379,7 @@ void orc_edm_rows(int64_t n, int64_t d, const float *X, int64_t ldx, const int64
     }
 }
 
-/* Four-feature distance map, the global-memory test of Section 4.1: every
+/* Four-feature distance map, the global-memory test of Section 5: every
  * point carries (x, y, z, w).  The paper gives the formula (Section 5, the
  * EDM paragraph) without fixing a precision; here it is one binary32
  * expression with a fixed order, so that any conforming evaluation is
@@ -405,7 +405,7 @@ void orc_edm4(int64_t n, const float *P, int64_t r0, int64_t r1, float *out, int
 }
 
 /* ------------------------------------------------------------------------ */
-/* Collision detection of spheres (Section 4.1, the shared-memory test)       */
+/* Collision detection of spheres (Section 5, the shared-memory test)       */
 /* ------------------------------------------------------------------------ */
 
 /* Spheres k = 0..n-1 are rows (x, y, z, r) of S (n x 4).  In dim = 3 two

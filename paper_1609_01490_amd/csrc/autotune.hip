@@ -51,8 +51,11 @@ static tri_status device_key(int workload, int64_t n, int64_t d, TuneKey &k)
     std::string arch = prop.gcnArchName;
     const size_t colon = arch.find(':');
     if (colon != std::string::npos) arch.resize(colon);
+    // d is the dimension of the distance maps and the generations per timed
+    // call of Life; it does not enter the elementwise keys
     k = TuneKey{arch, prop.multiProcessorCount, workload, size_bucket(n),
-                workload == TRI_TUNE_EDM_FP32 || workload == TRI_TUNE_EDM_BF16X3 ? d : 0};
+                workload == TRI_TUNE_ELEMENTWISE_F32 || workload == TRI_TUNE_ELEMENTWISE_I32 ? 0
+                                                                                           : d};
     return TRI_OK;
 }
 
@@ -136,10 +139,19 @@ using namespace trimap;
 
 extern "C" {
 
-// Generations per Life timing: two launches of the deepest temporal kernel
-// (the step count's parity fixes the number of launches), so that the
-// dispatch orders are ranked as long runs use them
+// Generations per Life timing when the caller gives none: two launches of
+// the deepest temporal kernel (the step count's parity fixes the number of
+// launches), so that the dispatch orders are ranked as long runs use them
 constexpr int kTuneLifeGens = 32;
+
+// Timed calls per candidate are ranked by their median: one slow call (a
+// clock change, another process) does not decide the choice.
+static float median_of(std::vector<float> v)
+{
+    std::sort(v.begin(), v.end());
+    const size_t k = v.size();
+    return k % 2 ? v[k / 2] : 0.5f * (v[k / 2 - 1] + v[k / 2]);
+}
 
 tri_status tri_autotune(int workload, int64_t n, int64_t d, int reps, int use_cache, void *stream,
                         tri_tune_choice *best, tri_tune_choice *all, int32_t all_cap,
@@ -152,6 +164,9 @@ tri_status tri_autotune(int workload, int64_t n, int64_t d, int reps, int use_ca
     if (n < 2 || n >= (1ll << 31)) return fail(TRI_E_RANGE, "tri_autotune: n = %lld", (long long)n);
     const bool edm = workload == TRI_TUNE_EDM_FP32 || workload == TRI_TUNE_EDM_BF16X3;
     if (edm && (d < 1 || d > 4096)) return fail(TRI_E_RANGE, "tri_autotune: d = %lld", (long long)d);
+    if (workload == TRI_TUNE_LIFE && (d < 0 || d > 100000))
+        return fail(TRI_E_RANGE, "tri_autotune: %lld Life generations", (long long)d);
+    const int life_gens = workload == TRI_TUNE_LIFE && d > 0 ? (int)d : kTuneLifeGens;
     if (reps < 1) reps = 1;
     if (all_count) *all_count = 0;
 
@@ -218,10 +233,16 @@ tri_status tri_autotune(int workload, int64_t n, int64_t d, int reps, int use_ca
     }
     if (e != hipSuccess) return hip_fail(e, "tri_autotune: scratch");
 
-    hipEvent_t e0, e1;
-    TRI_HIP(hipEventCreate(&e0));
-    if ((e = hipEventCreate(&e1)) != hipSuccess) {
-        (void)hipEventDestroy(e0);
+    // one event per timed call boundary: call r is timed from ev[r] to ev[r + 1]
+    std::vector<hipEvent_t> ev(reps + 1, nullptr);
+    for (auto &x_ev : ev)
+        if ((e = hipEventCreate(&x_ev)) != hipSuccess) break;
+    auto destroy_events = [&]() {
+        for (auto &x_ev : ev)
+            if (x_ev) (void)hipEventDestroy(x_ev);
+    };
+    if (e != hipSuccess) {
+        destroy_events();
         return hip_fail(e, "tri_autotune: event");
     }
     tri_tune_choice bestc{0, -1, 0u, 0.f};
@@ -237,7 +258,7 @@ tri_status tri_autotune(int workload, int64_t n, int64_t d, int reps, int use_ca
             case TRI_TUNE_ELEMENTWISE_I32:
                 return tri_launch_elementwise(p, TRI_OP_XORMUL_I32, x, y, c, ld, 0.f, s);
             case TRI_TUNE_LIFE:
-                return tri_launch_stencil(p, (uint8_t *)x, (uint8_t *)y, ld, kTuneLifeGens, 0, s);
+                return tri_launch_stencil(p, (uint8_t *)x, (uint8_t *)y, ld, life_gens, 0, s);
             case TRI_TUNE_EDM_FP32:
                 return tri_edm(p, (const float *)x, d, d, (float *)c, TRI_EDM_FP32, 1e-2f, nullptr, 0, s);
             default:
@@ -251,26 +272,27 @@ tri_status tri_autotune(int workload, int64_t n, int64_t d, int reps, int use_ca
             if (rs == TRI_E_HIP) { st = rs; break; }
             continue;
         }
-        (void)hipEventRecord(e0, s);
-        for (int r = 0; r < reps && rs == TRI_OK; ++r) rs = run();
-        (void)hipEventRecord(e1, s);
-        e = hipEventSynchronize(e1);
+        (void)hipEventRecord(ev[0], s);
+        for (int r = 0; r < reps && rs == TRI_OK; ++r) {
+            rs = run();
+            (void)hipEventRecord(ev[r + 1], s);
+        }
+        e = hipEventSynchronize(ev[reps]);
         tri_plan_destroy(p);
         if (rs != TRI_OK || e != hipSuccess) {
             st = rs != TRI_OK ? rs : hip_fail(e, "tri_autotune: timing");
             break;
         }
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        ms /= (float)reps;
-        if (workload == TRI_TUNE_LIFE) ms /= (float)kTuneLifeGens;  // per generation
+        std::vector<float> t(reps, 0.f);
+        for (int r = 0; r < reps; ++r) (void)hipEventElapsedTime(&t[r], ev[r], ev[r + 1]);
+        float ms = median_of(t);
+        if (workload == TRI_TUNE_LIFE) ms /= (float)life_gens;  // per generation
         const tri_tune_choice ch{cd.tile, cd.map, cd.flags, ms};
         if (all && nall < all_cap) all[nall] = ch;
         ++nall;
         if (bestc.map < 0 || ms < bestc.ms) bestc = ch;
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    destroy_events();
     if (st != TRI_OK) return st;
     if (bestc.map < 0) return fail(TRI_E_UNSUPPORTED, "tri_autotune: no candidate ran");
     if (all_count) *all_count = std::min(nall, all_cap);

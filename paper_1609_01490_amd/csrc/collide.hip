@@ -1,4 +1,4 @@
-// Collision detection of n spheres (the shared-memory test of Section 4.1):
+// Collision detection of n spheres (the shared-memory test of Section 5):
 // every pair j < i of the strict lower triangle is tested once and, when the
 // spheres overlap, counted for both of them.
 //

@@ -1,4 +1,4 @@
-// The dummy kernel of the square-root study (Section 5.1): every cell (i, j)
+// The dummy kernel of the square-root study (Section 4.1): every cell (i, j)
 // of the plan's domain forms its coordinates through the map and computes
 // i + j; only cells whose sum equals a target store it.  With a target no
 // cell reaches, nothing is written and the kernel costs the dispatch, the

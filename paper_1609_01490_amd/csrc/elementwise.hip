@@ -5,9 +5,9 @@
 //  * AXPYT_F32: C[i][j] = fl(fl(a X[i][j]) + Y[j][i]) for j <= i.  The mirror
 //    tile of Y is read row-major (coalesced) and transposed through LDS.
 //  * XORMUL_I32: C[i][j] = (A[i] xor B[j]) + i j (mod 2^32), the dummy
-//    kernel of Section 4.1 with a real per-cell store.
+//    kernel of Sections 4.1 and 5 with a real per-cell store.
 //  * EDM4_F32: C[i][j] = |P_i - P_j| for four features per point, the
-//    global-memory distance test of Section 4.1: both points come straight
+//    global-memory distance test of Section 5: both points come straight
 //    from global memory (they stay in L1/L2), nothing is staged in LDS.
 //
 // All are HBM-bound: 12 B (axpyt) or 4 B (xormul, edm4) of algorithmic

@@ -1,7 +1,7 @@
 // Device side of the parallel-space maps: grid block -> tile (bi, bj) of the
 // lower triangle of an m x m tile grid (0 <= bj <= bi < m), and the
 // thread-space UTM map.  Each map is a self-contained function with no side
-// effects (Section 6 of the paper makes this point for lambda).
+// effects (the Conclusions, Section 7, make this point for lambda).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -38,7 +38,7 @@ constexpr uint32_t kLambda32 = 1u << 30;
 // it exact; that is why no epsilon is added as in the paper's lambda_N and
 // lambda_R.  omega >= 2^32 always takes the FP64 root.
 // ---------------------------------------------------------------------------
-// Square root of the lambda_N variant (Section 5.1): reciprocal square root
+// Square root of the lambda_N variant (Section 4.1): reciprocal square root
 // from the integer bit trick of the fast inverse square root (initial
 // constant 0x5f3759df, Lomont's analysis), three Newton-Raphson steps
 // y <- y (3/2 - (x/2) y^2), then sqrt(x) = x y.
@@ -58,7 +58,7 @@ __device__ __forceinline__ float sqrt_variant(float x, uint32_t flags)
     return __builtin_amdgcn_sqrtf(x);
 }
 
-// The paper's inexact form (Section 5.1): i = floor(sqrt(1/4 + 2 omega) + eps
+// The paper's inexact form (Section 4.1): i = floor(sqrt(1/4 + 2 omega) + eps
 // - 1/2) with eps = 1e-4 and no integer correction.  Kept for the square-root
 // study only: it is wrong for some omega, so kernels may miss or repeat tiles.
 __device__ __forceinline__ uint32_t lambda_row_eps(uint64_t w, uint32_t flags)

@@ -37,6 +37,16 @@ class TrimapError(RuntimeError):
         self.status = status
 
 
+class TrimapArgError(TrimapError, ValueError):
+    """A tensor argument the binding refuses before any device pointer is
+    passed on: wrong device, dtype or layout, or a buffer smaller than the
+    extent the call touches (the C side sees bare pointers and cannot check
+    extents).  Status TRI_E_INVAL."""
+
+    def __init__(self, msg: str):
+        super().__init__(E_INVAL, msg)
+
+
 class tri_plan_info(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int64) for name in (
         "n", "tile", "m", "tiles", "grid_x", "grid_y", "grid_blocks", "wasted_blocks",
@@ -131,6 +141,8 @@ def _load() -> ctypes.CDLL:
     L.tri_tune_cache_clear.argtypes = []
     L.tri_stream_add.restype = st
     L.tri_stream_add.argtypes = [vp, vp, vp, i64, vp]
+    L.tri_stream_probe.restype = st
+    L.tri_stream_probe.argtypes = [i32, i32, i32, i32, i64, vp, vp, vp, i64, vp]
     L.tri_status_str.restype = ctypes.c_char_p
     L.tri_status_str.argtypes = [st]
     L.tri_last_error.restype = ctypes.c_char_p
@@ -160,8 +172,45 @@ def _dptr(t) -> int:
     if t is None:
         return None
     if not t.is_cuda:
-        raise ValueError("expected a device tensor")
+        raise TrimapArgError("expected a device tensor")
     return t.data_ptr()
+
+
+def _span(t) -> int:
+    """Bytes of t's allocation from t.data_ptr() to its end."""
+    return t.untyped_storage().nbytes() - t.storage_offset() * t.element_size()
+
+
+def _arg(t, name: str, dtypes, elems: int, optional: bool = False):
+    """Device pointer of t after checking that it is a device tensor of one of
+    `dtypes` (torch dtype names), with unit stride in its last dimension, and
+    that its allocation holds at least `elems` elements from its first one."""
+    if t is None:
+        if optional:
+            return None
+        raise TrimapArgError(f"{name}: a tensor is required")
+    if not t.is_cuda:
+        raise TrimapArgError(f"{name}: expected a device tensor")
+    if str(t.dtype).replace("torch.", "") not in dtypes:
+        raise TrimapArgError(f"{name}: dtype {t.dtype} not in {sorted(dtypes)}")
+    if t.dim() > 0 and t.numel() > 1 and t.stride(-1) != 1:
+        raise TrimapArgError(f"{name}: the last dimension must have stride 1")
+    if elems > 0 and _span(t) < elems * t.element_size():
+        raise TrimapArgError(f"{name}: {elems} elements needed from its first one, the "
+                             f"allocation holds {_span(t) // t.element_size()}")
+    return t.data_ptr()
+
+
+def _rows_ld(t, ld):
+    """Row pitch of a 2-D grid argument (its stride unless given)."""
+    if ld is None:
+        ld = t.stride(0) if t.dim() == 2 else t.shape[-1]
+    return int(ld)
+
+
+F32 = {"float32"}
+I32 = {"int32", "uint32"}
+U8 = {"uint8"}
 
 
 @dataclass
@@ -227,14 +276,35 @@ class Plan:
     # -- kernels ----------------------------------------------------------
     def elementwise(self, op: int, x, y, c, ld: int | None = None, a: float = 0.0,
                     stream=None):
-        ld = c.stride(0) if ld is None else ld
-        _check(lib.tri_launch_elementwise(self._h, int(op), _dptr(x), _dptr(y), _dptr(c),
-                                          int(ld), float(a), _stream(stream)))
+        n = self.info.n
+        ld = _rows_ld(c, ld)
+        grid = n * max(ld, n)  # an n x ld matrix (ld < n is refused by the library)
+        if op == OP_XORMUL_I32:
+            px, py = _arg(x, "A", I32, n), _arg(y, "B", I32, n)
+            pc = _arg(c, "C", I32, grid)
+        elif op == OP_AXPYT_F32:
+            for t, nm in ((x, "X"), (y, "Y")):
+                if t is not None and t.dim() == 2 and t.stride(0) != ld:
+                    raise TrimapArgError(f"{nm}: row pitch {t.stride(0)} differs from ld {ld}")
+            px, py, pc = _arg(x, "X", F32, grid), _arg(y, "Y", F32, grid), _arg(c, "C", F32, grid)
+        elif op == OP_EDM4_F32:
+            px, py = _arg(x, "P", F32, 4 * n), _arg(y, "y", F32, 0, optional=True)
+            pc = _arg(c, "C", F32, grid)
+        else:
+            px, py, pc = _dptr(x), _dptr(y), _dptr(c)  # the library refuses the op
+        _check(lib.tri_launch_elementwise(self._h, int(op), px, py, pc, int(ld), float(a),
+                                          _stream(stream)))
 
     def stencil(self, cur, nxt, steps: int, ld: int | None = None, use_graph: bool = False,
                 stream=None):
-        ld = cur.stride(0) if ld is None else ld
-        _check(lib.tri_launch_stencil(self._h, _dptr(cur), _dptr(nxt), int(ld), int(steps),
+        n = self.info.n
+        ld = _rows_ld(cur, ld)
+        if nxt is not None and cur is not None and nxt.dim() == 2 and cur.dim() == 2 and \
+                nxt.stride(0) != cur.stride(0):
+            raise TrimapArgError("cur and nxt must have the same row pitch")
+        grid = n * max(ld, n)
+        _check(lib.tri_launch_stencil(self._h, _arg(cur, "cur", U8, grid),
+                                      _arg(nxt, "nxt", U8, grid), int(ld), int(steps),
                                       1 if use_graph else 0, _stream(stream)))
 
     def edm_workspace_size(self, d: int, mode: int) -> int:
@@ -244,20 +314,31 @@ class Plan:
 
     def edm(self, x, out, mode: int = EDM_FP32, fixup_thr: float = 1e-2, ws=None,
             stream=None):
-        d = x.shape[1]
-        wsb = 0 if ws is None else ws.numel() * ws.element_size()
-        _check(lib.tri_edm(self._h, _dptr(x), int(d), int(x.stride(0)), _dptr(out), int(mode),
-                           float(fixup_thr), _dptr(ws), int(wsb), _stream(stream)))
+        n = self.info.n
+        if x is None or x.dim() != 2:
+            raise TrimapArgError("x: an n x d matrix is required")
+        d, ldx = x.shape[1], x.stride(0)
+        if x.shape[0] != n:
+            raise TrimapArgError(f"x: {x.shape[0]} rows for a plan of n = {n}")
+        px = _arg(x, "x", F32, (n - 1) * ldx + d if n else 0)
+        po = _arg(out, "out", F32, n * (n - 1) // 2)
+        wsb = 0 if ws is None else min(ws.numel() * ws.element_size(), _span(ws))
+        pw = _arg(ws, "ws", {"uint8", "int8", "float32", "int32", "int64", "float64"}, 0,
+                  optional=True)
+        _check(lib.tri_edm(self._h, px, int(d), int(ldx), po, int(mode), float(fixup_thr), pw,
+                           int(wsb), _stream(stream)))
 
     def dummy(self, target: int, sink, stream=None):
         """The square-root study's dummy kernel (tri_launch_dummy)."""
-        _check(lib.tri_launch_dummy(self._h, int(target), _dptr(sink), _stream(stream)))
+        _check(lib.tri_launch_dummy(self._h, int(target), _arg(sink, "sink", I32, 1),
+                                    _stream(stream)))
 
     def collide(self, spheres, counts, dim: int = 3, stream=None):
         """Per-sphere overlap counts (tri_collide); spheres is a float32
         device tensor n x 4 (x, y, z, r), counts an int32 device tensor."""
-        _check(lib.tri_collide(self._h, _dptr(spheres), int(dim), _dptr(counts),
-                               _stream(stream)))
+        n = self.info.n
+        _check(lib.tri_collide(self._h, _arg(spheres, "spheres", F32, 4 * n), int(dim),
+                               _arg(counts, "counts", I32, n), _stream(stream)))
 
 
 class TetPlan:
@@ -297,19 +378,24 @@ class TetPlan:
 
     def triangles(self, points, r2: float, counts, total, stream=None):
         """Triangle counts of the neighbour graph (tri_triangles)."""
-        _check(lib.tri_triangles(self._h, _dptr(points), float(r2), _dptr(counts), _dptr(total),
-                                 _stream(stream)))
+        n = self.n
+        _check(lib.tri_triangles(self._h, _arg(points, "points", F32, 4 * n), float(r2),
+                                 _arg(counts, "counts", I32, n),
+                                 _arg(total, "total", {"int64", "uint64"}, 1), _stream(stream)))
 
     def dummy(self, target: int, sink, stream=None):
-        _check(lib.tri_tet_dummy(self._h, int(target), _dptr(sink), _stream(stream)))
+        _check(lib.tri_tet_dummy(self._h, int(target), _arg(sink, "sink", I32, 1),
+                                 _stream(stream)))
 
 
 def lambda3_eval(omega, flags: int = 0, stream=None):
     """Device tetrahedral lambda(omega) -> int64 [count, 3] = (i, j, k)."""
     import torch
     out = torch.empty((omega.numel(), 3), dtype=torch.int64, device=omega.device)
-    _check(lib.tri_lambda3_eval(_dptr(omega), int(omega.numel()), int(flags), _dptr(out),
-                                _stream(stream)))
+    if not omega.is_contiguous():
+        raise TrimapArgError("omega: a contiguous tensor is required")
+    _check(lib.tri_lambda3_eval(_arg(omega, "omega", {"int64", "uint64"}, omega.numel()),
+                                int(omega.numel()), int(flags), _dptr(out), _stream(stream)))
     return out
 
 
@@ -317,8 +403,11 @@ def lambda_eval(omega, include_diag: bool = True, flags: int = 0, stream=None):
     """Device lambda(omega) for a uint64/int64 device tensor of omegas."""
     import torch
     out = torch.empty((omega.numel(), 2), dtype=torch.int64, device=omega.device)
-    _check(lib.tri_lambda_eval(_dptr(omega), int(omega.numel()), 1 if include_diag else 0,
-                               int(flags), _dptr(out), _stream(stream)))
+    if not omega.is_contiguous():
+        raise TrimapArgError("omega: a contiguous tensor is required")
+    _check(lib.tri_lambda_eval(_arg(omega, "omega", {"int64", "uint64"}, omega.numel()),
+                               int(omega.numel()), 1 if include_diag else 0, int(flags),
+                               _dptr(out), _stream(stream)))
     return out
 
 
@@ -355,10 +444,9 @@ class Batch:
     def bind(self, a_list, b_list):
         import numpy as np
         n = self.kinds.size
-        assert len(a_list) == n and len(b_list) == n
-        A = (ctypes.c_void_p * n)(*[_dptr(t) for t in a_list])
-        B = (ctypes.c_void_p * n)(*[_dptr(t) for t in b_list])
-        ld = np.ascontiguousarray([t.stride(0) for t in a_list], dtype=np.int64)
+        if len(a_list) != n or len(b_list) != n:
+            raise TrimapArgError(f"bind: {n} instances, {len(a_list)} / {len(b_list)} buffers")
+        A, B, ld = _batch_buffers(self.kinds, self.ns, self.ds, a_list, b_list)
         _check(lib.tri_batch_bind(self._h, A, B, ld.ctypes.data))
         self._keep = (list(a_list), list(b_list))  # the buffers must outlive the plan's use
 
@@ -413,9 +501,10 @@ def batch_autotune(kinds, ns, ds, life_steps, a_list, b_list, reps: int = 2, str
     ns = np.ascontiguousarray(ns, dtype=np.int64)
     ds = np.ascontiguousarray(ds, dtype=np.int64)
     n = kinds.size
-    A = (ctypes.c_void_p * n)(*[_dptr(t) for t in a_list])
-    B = (ctypes.c_void_p * n)(*[_dptr(t) for t in b_list])
-    ld = np.ascontiguousarray([t.stride(0) for t in a_list], dtype=np.int64)
+    if len(a_list) != n or len(b_list) != n:
+        raise TrimapArgError(f"batch_autotune: {n} instances, {len(a_list)} / {len(b_list)} "
+                             "buffers")
+    A, B, ld = _batch_buffers(kinds, ns, ds, a_list, b_list)
     te, tl, fl, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_uint32(), ctypes.c_float()
     _check(lib.tri_batch_autotune(n, kinds.ctypes.data, ns.ctypes.data, ds.ctypes.data,
                                   int(life_steps), A, B, ld.ctypes.data, int(reps),
@@ -424,6 +513,59 @@ def batch_autotune(kinds, ns, ds, life_steps, a_list, b_list, reps: int = 2, str
     return te.value, tl.value, fl.value, ms.value
 
 
+def _batch_buffers(kinds, ns, ds, a_list, b_list):
+    """Checked device pointers and row pitches of a batch's buffers: a
+    distance map k takes x (n_k x d_k FP32 rows of pitch >= d_k) and its
+    condensed output (n_k (n_k - 1) / 2 FP32); a Life instance two uint8
+    grids of n_k rows of one pitch."""
+    import numpy as np
+    A, B, lds = [], [], []
+    for k, (a, b) in enumerate(zip(a_list, b_list)):
+        n, kind = int(ns[k]), int(kinds[k])
+        if kind == KIND_EDM:
+            d = int(ds[k])
+            if a is None or a.dim() != 2 or a.shape[1] < d:
+                raise TrimapArgError(f"instance {k}: x must be an n x d matrix")
+            ld = a.stride(0)
+            A.append(_arg(a, f"x[{k}]", F32, (n - 1) * ld + d if n else 0))
+            B.append(_arg(b, f"out[{k}]", F32, n * (n - 1) // 2))
+        else:
+            ld = _rows_ld(a, None)
+            if b is not None and b.dim() == 2 and a.dim() == 2 and b.stride(0) != a.stride(0):
+                raise TrimapArgError(f"instance {k}: both Life grids need one row pitch")
+            A.append(_arg(a, f"grid_a[{k}]", U8, n * max(ld, n)))
+            B.append(_arg(b, f"grid_b[{k}]", U8, n * max(ld, n)))
+        lds.append(ld)
+    m = len(A)
+    return ((ctypes.c_void_p * m)(*A), (ctypes.c_void_p * m)(*B),
+            np.ascontiguousarray(lds, dtype=np.int64))
+
+
 def stream_add(c, a, b, stream=None):
     """c = a + b with the library's streaming probe kernel (tri_stream_add)."""
-    _check(lib.tri_stream_add(_dptr(c), _dptr(a), _dptr(b), int(c.numel()), _stream(stream)))
+    cnt = c.numel()
+    for t, nm in ((c, "c"), (a, "a"), (b, "b")):
+        if not t.is_contiguous():
+            raise TrimapArgError(f"{nm}: a contiguous tensor is required")
+    _check(lib.tri_stream_add(_arg(c, "c", F32, cnt), _arg(a, "a", F32, cnt),
+                              _arg(b, "b", F32, cnt), int(cnt), _stream(stream)))
+
+
+PROBE_READ, PROBE_ADD, PROBE_FILL, PROBE_COPY = range(4)
+
+
+def stream_probe(kind: int, c, a=None, b=None, count: int | None = None, unroll: int = 4,
+                 threads: int = 256, nontemporal: bool = True, workgroups: int = 0,
+                 stream=None):
+    """One launch of the bandwidth probe (tri_stream_probe) over `count`
+    floats (default: all of a, or of c for the fill)."""
+    src = c if kind == PROBE_FILL else a
+    cnt = src.numel() if count is None else int(count)
+    for t, nm in ((c, "c"), (a, "a"), (b, "b")):
+        if t is not None and not t.is_contiguous():
+            raise TrimapArgError(f"{nm}: a contiguous tensor is required")
+    _check(lib.tri_stream_probe(int(kind), int(unroll), int(threads), 1 if nontemporal else 0,
+                                int(workgroups), _arg(c, "c", F32, cnt),
+                                _arg(a, "a", F32, cnt, optional=kind == PROBE_FILL),
+                                _arg(b, "b", F32, cnt, optional=kind != PROBE_ADD),
+                                cnt, _stream(stream)))

@@ -3,7 +3,9 @@ it, and never changes results (integer and Life bodies are tile-invariant)."""
 import numpy as np
 import pytest
 
-from gpu_helpers import note
+import oracle
+from gpu_helpers import dev, host, note, padded_ld
+from paper_1609_01490_amd import inputs
 
 pytestmark = pytest.mark.gpu
 
@@ -35,3 +37,51 @@ def test_autotune_picks_the_fastest_candidate(workload, n, d, tmp_path):
     tm.tune_cache_load(f)
     third, allc3 = tm.autotune(workload, n, d, reps=2, use_cache=True)
     assert allc3 == [] and third["tile"] == best["tile"] and third["map"] == best["map"]
+    # the chosen (tile, map, flags) runs the body and gives the oracle's result
+    note("autotune choice", workload, best)
+    _check_choice(tm, workload, n, d, best)
+
+
+def _check_choice(tm, workload, n, d, ch):
+    import torch
+    U = 2.0 ** -24
+    if workload in (0, 1, 2):
+        p = tm.Plan(n, ch["tile"], ch["map"], flags=ch["flags"])
+    else:
+        p = tm.Plan(n, ch["tile"], ch["map"], include_diag=False, flags=ch["flags"])
+    if workload == 0:
+        ld = padded_ld(n)
+        a, X, Y, C0 = inputs.f32_elementwise(n, seed=31, ld=ld)
+        c = dev(C0)
+        p.elementwise(tm.OP_AXPYT_F32, dev(X), dev(Y), c, ld=ld, a=float(a))
+        exp = C0.copy()
+        oracle.c1(a, X, Y, exp, n=n)
+        assert (host(c).view(np.uint32) == exp.view(np.uint32)).all()
+    elif workload == 1:
+        A, B, C0 = inputs.int_elementwise(n, seed=32)
+        c = dev(C0)
+        p.elementwise(tm.OP_XORMUL_I32, dev(A), dev(B), c, ld=n)
+        exp = C0.copy()
+        oracle.c0(A, B, exp)
+        assert (host(c) == exp).all()
+    elif workload == 2:
+        steps = 21
+        g = inputs.life(n, 0.3, seed=33, ld=padded_ld(n, 16))
+        cur, nxt = dev(g), torch.zeros((n, g.shape[1]), dtype=torch.uint8, device="cuda")
+        p.stencil(cur, nxt, steps)
+        got = host(nxt if steps % 2 else cur)[:, :n]
+        low = np.tril(np.ones((n, n), dtype=bool))
+        assert (got[low] == oracle.gol(g, n, steps)[low]).all()
+    else:
+        mode = tm.EDM_FP32 if workload == 3 else tm.EDM_BF16X3
+        X, _ = inputs.points(n, d, dup_frac=0.02, seed=34)
+        out = torch.full((n * (n - 1) // 2,), -1.0, dtype=torch.float32, device="cuda")
+        ws = None
+        if mode != tm.EDM_FP32:
+            ws = torch.empty(p.edm_workspace_size(d, mode), dtype=torch.uint8, device="cuda")
+        p.edm(dev(X), out, mode=mode, ws=ws)
+        got = host(out)
+        e = oracle.edm_condensed(X)
+        nz = e > 0
+        rel = np.abs(got.astype(np.float64)[nz] - e[nz]) / e[nz]
+        assert rel.max() <= ((d + 2) * U / 2 + U if mode == tm.EDM_FP32 else 1e-3)

@@ -186,3 +186,99 @@ def test_batch_binding_picks_the_life_kernel(all16, nodes):
     assert b.info["graph_nodes"] == nodes
     b.launch(tm.BATCH_GRAPH)
     _check_oracle(spec, host_in, _results(spec, A, B, steps), d, steps)
+
+
+@pytest.mark.slow
+def test_batch_512_benchmark_shape_matches_oracle():
+    """The 512-instance batch exactly as the benchmark builds and times it
+    (inputs.batch_instances(): n log-uniform in [64, 8192], even index a
+    distance map with d = 32, odd index Life for 20 generations with rows
+    padded to 16 bytes; distance tile 64, Life tile 64 with temporal
+    blocking, one graph launch).  Every distance instance is checked on
+    whole sampled rows (the first, the last and two seeded random ones)
+    within the FP32 bound, a seeded sample of 16 Life instances (always with
+    the largest) on the whole grid, bit-exact; the per-instance launches give
+    the same bits on that sample."""
+    import concurrent.futures as cf
+    import torch
+    tm = _tm()
+    d, steps = 32, 20
+    spec = inputs.batch_instances()
+    assert len(spec) == 512
+    kinds, ns, ds, A, B, host_in = [], [], [], [], [], []
+    for k, (kind, n) in enumerate(spec):
+        seed = inputs.seed_for(4) * 1000 + k
+        if kind == "edm":
+            X, _ = inputs.points(n, d, dup_frac=0.0, seed=seed)
+            host_in.append(X)
+            A.append(dev(X))
+            B.append(torch.full((n * (n - 1) // 2,), -1.0, dtype=torch.float32, device="cuda"))
+            kinds.append(tm.KIND_EDM)
+        else:
+            g = inputs.life(n, 0.3, seed=seed, ld=padded_ld(n, 16))
+            host_in.append(g)
+            A.append(dev(g))
+            B.append(torch.zeros_like(A[-1]))
+            kinds.append(tm.KIND_LIFE)
+        ns.append(n)
+        ds.append(d)
+    note("batch 512: inputs on the device")
+    b = tm.Batch(kinds, ns, ds, edm_tile=64, life_tile=64, life_steps=steps,
+                 flags=tm.FLAG_LIFE_TEMPORAL)
+    b.bind(A, B)
+    assert b.info["graph_nodes"] < steps  # temporally blocked nodes
+    note("batch 512: graph launch")
+    b.launch(tm.BATCH_GRAPH)
+    torch.cuda.synchronize()
+
+    rng = np.random.default_rng(512)
+    life_idx = [k for k, (kind, _) in enumerate(spec) if kind == "life"]
+    largest = max(life_idx, key=lambda k: spec[k][1])
+    sample = sorted(set(rng.choice(life_idx, 15, replace=False).tolist()) | {largest})
+
+    def life_result(k):
+        n = spec[k][1]
+        return host(A[k] if steps % 2 == 0 else B[k])[:, :n].copy()
+
+    got_life = {k: life_result(k) for k in sample}
+    edm_rows = {}
+    for k, (kind, n) in enumerate(spec):
+        if kind == "edm":
+            rows = sorted({1, n - 1} | set(rng.integers(1, n, 2).tolist()))
+            edm_rows[k] = (rows, [B[k][r * (r - 1) // 2: r * (r - 1) // 2 + r].cpu().numpy()
+                                  for r in rows])
+    note("batch 512: oracle")
+    bound = (d + 2) * U / 2 + U
+    for k, (rows, got) in edm_rows.items():
+        for r, g, e in zip(rows, got, oracle.edm_rows(host_in[k], rows)):
+            nz = e > 0
+            rel = np.abs(g.astype(np.float64)[nz] - e[nz]) / e[nz]
+            assert rel.size == 0 or rel.max() <= bound, (k, r, rel.max())
+
+    def life_oracle(k):
+        n = spec[k][1]
+        return k, oracle.gol(host_in[k], n, steps)
+
+    with cf.ThreadPoolExecutor(8) as ex:
+        for k, exp in ex.map(life_oracle, sample):
+            n = spec[k][1]
+            low = np.tril(np.ones((n, n), dtype=bool))
+            assert (got_life[k][low] == exp[low]).all(), (k, n)
+            note("batch 512: life instance", k, n, "exact")
+
+    # the same bodies launched per instance, from generation 0 again
+    for k in life_idx:
+        A[k].copy_(dev(host_in[k]))
+        B[k].zero_()
+    note("batch 512: per-instance launches")
+    b.launch(tm.BATCH_PER_INSTANCE)
+    torch.cuda.synchronize()
+    for k in sample:
+        assert (life_result(k) == got_life[k]).all(), k
+    for k, (rows, got) in edm_rows.items():
+        for r, g in zip(rows, got):
+            assert (B[k][r * (r - 1) // 2: r * (r - 1) // 2 + r].cpu().numpy().view(np.uint32)
+                    == g.view(np.uint32)).all(), (k, r)
+    b.close()
+    del A, B
+    torch.cuda.empty_cache()

@@ -1,5 +1,5 @@
 """GPU parity of sphere collision detection (tri_collide, the shared-memory
-test of Section 4.1) against the oracle: per-sphere overlap counts
+test of Section 5) against the oracle: per-sphere overlap counts
 bit-exact, for every map and tile size, 1-D and 3-D, ragged sizes, exact
 ties on lattice spheres, and sampled spheres at the full size
 n = 131072."""

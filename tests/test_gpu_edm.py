@@ -136,10 +136,18 @@ def _edm_mfma(tm, p, X, mode, thr=1e-2):
 
 
 @pytest.mark.parametrize("mode", [1, 2])
-@pytest.mark.parametrize("map_name", ["bb", "lambda", "rb"])
+@pytest.mark.parametrize("map_name", ["bb", "lambda", "rb", "rec"])
 def test_edm_mfma_small(mode, map_name):
+    """Whole rows of every n against the FP64 oracle.  REC needs m (tiles
+    per side) a power of two: n = 2..129 (m = 1), 130 and 257 (m = 2), 513
+    (m = 4), 1025 (m = 8); the other maps also take n = 700 (m = 6)."""
     tm = _tm()
-    for n in (2, 3, 50, 129, 130, 257, 700):
+    for n in (2, 3, 50, 129, 130, 257, 513, 700, 1025):
+        m = -(-(n - 1) // 128)
+        if map_name == "rec" and (m & (m - 1)):
+            continue
+        if map_name != "rec" and n in (513, 1025):
+            continue
         for d in (1, 4, 33, 128):
             X, pairs = inputs.points(n, d, dup_frac=0.02, seed=5000 + n + d)
             p = tm.Plan(n, 128, map_name, include_diag=False)
@@ -271,3 +279,38 @@ def test_edm_bf16x3_4096_sampled_rows():
     del out
     torch.cuda.empty_cache()
 
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("mode", [1, 2])
+def test_edm_mfma_rec_full_size_sampled_rows(mode):
+    """REC (m = 512 tiles per side, a power of two) at n = 65536, d = 128:
+    the map the autotuner times among the MFMA candidates.  Whole sampled
+    rows (first, last, 24 seeded random, 16 near-duplicate rows) against the
+    FP64 oracle: BF16X3 within 1e-3, single BF16 within its absolute
+    bound."""
+    import torch
+    tm = _tm()
+    n, d = 65536, 128
+    X, pairs = inputs.points(n, d)
+    p = tm.Plan(n, 128, "rec", include_diag=False)
+    note("edm rec full", mode, n, d)
+    out = _edm_mfma(tm, p, X, mode)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(17)
+    rows = sorted(set([1, 2, n - 1] + rng.choice(n, 24, replace=False).tolist()
+                      + pairs[:16].max(axis=1).tolist()))
+    sub = {r: out[r * (r - 1) // 2: r * (r - 1) // 2 + r].cpu().numpy() for r in rows}
+    if mode == 1:
+        for r, e in zip(rows, oracle.edm_rows(X, rows)):
+            g = sub[r].astype(np.float64)
+            nz = e > 0
+            assert (np.abs(g[nz] - e[nz]) / e[nz]).max() <= 1e-3, r
+    else:
+        Xc = X.astype(np.float64) - X.astype(np.float64).mean(axis=0)
+        nrm = np.sqrt((Xc ** 2).sum(axis=1))
+        for r, e in zip(rows, oracle.edm_rows(X, rows)):
+            g = sub[r].astype(np.float64)
+            assert (np.abs(g - e) <= 2.0 ** -7 * (nrm[r] + nrm[:r])).all(), r
+    del out
+    torch.cuda.empty_cache()

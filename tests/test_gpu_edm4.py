@@ -1,5 +1,5 @@
 """GPU parity of the four-feature distance map (TRI_OP_EDM4_F32, the
-global-memory distance test of Section 4.1) against the oracle: bit-exact on
+global-memory distance test of Section 5) against the oracle: bit-exact on
 every cell j <= i (the operation is one binary32 expression with a fixed
 order and a correctly rounded root), cells above the diagonal untouched, for
 all five maps and every tile size, ragged sizes, vector and scalar leading

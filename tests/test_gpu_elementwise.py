@@ -190,3 +190,33 @@ def test_stream_add_probe_is_exact():
     assert torch.equal(c, a + b)
     with pytest.raises(tm.TrimapError):
         tm.stream_add(c[:5], a[:5], b[:5])
+
+
+@pytest.mark.parametrize("unroll,threads,nt,wg", [(1, 256, True, 0), (4, 512, False, 0),
+                                                  (8, 1024, True, 64), (2, 64, False, 3)])
+def test_stream_probe_mixes_are_exact(unroll, threads, nt, wg):
+    """Every mix of the bandwidth probe computes what it states (c = a + b,
+    c = a, c filled with the target -1), over a count that is not a multiple
+    of a chunk, with and without the persistent grid; the read probe writes
+    nothing."""
+    import torch
+    tm = _tm()
+    cnt = (1 << 18) + 4 * 37
+    a = torch.rand(cnt, device="cuda")
+    b = torch.rand(cnt, device="cuda")
+    c = torch.full((cnt,), 7.0, device="cuda")
+    note("stream probe", unroll, threads, nt, wg)
+    tm.stream_probe(tm.PROBE_READ, c, a, None, unroll=unroll, threads=threads, nontemporal=nt,
+                    workgroups=wg)
+    assert bool((c == 7.0).all())
+    tm.stream_probe(tm.PROBE_ADD, c, a, b, unroll=unroll, threads=threads, nontemporal=nt,
+                    workgroups=wg)
+    assert torch.equal(c, a + b)
+    tm.stream_probe(tm.PROBE_COPY, c, b, None, unroll=unroll, threads=threads, nontemporal=nt,
+                    workgroups=wg)
+    assert torch.equal(c, b)
+    tm.stream_probe(tm.PROBE_FILL, c, None, None, unroll=unroll, threads=threads,
+                    nontemporal=nt, workgroups=wg)
+    assert bool((c == -1.0).all())
+    with pytest.raises(tm.TrimapError):
+        tm.stream_probe(tm.PROBE_ADD, c, a, b, unroll=3)

@@ -1,5 +1,5 @@
 """Pins of the oracle's sphere collision counts (the shared-memory test of
-Section 4.1): an exact integer brute force on lattice spheres (every
+Section 5): an exact integer brute force on lattice spheres (every
 binary32 step exact there, ties included), SciPy's binary64 distances away
 from ties, a 1-D chain with a closed-form answer, and the count of one
 sphere against the whole array."""

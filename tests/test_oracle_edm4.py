@@ -1,5 +1,5 @@
 """Pins of the oracle's four-feature distance map (the global-memory test of
-Section 4.1, formula of the EDM paragraph of Section 5): SciPy's binary64
+Section 5, formula of the EDM paragraph of Section 5): SciPy's binary64
 distances within the derived binary32 error bound, exact Pythagorean
 quadruples (each feature slot distinct), the fixed summation order, and row
 ranges.

@@ -249,6 +249,23 @@ tri_status tri_edm_workspace_size(const tri_plan *plan, int64_t d, int mode, siz
 tri_status tri_edm(const tri_plan *plan, const float *x, int64_t d, int64_t ldx, float *out,
                    int mode, float fixup_thr, void *ws, size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): tri_edm
+ * with the MFMA modes' workspace taken from a scratch array the library
+ * holds on each GPU it runs on (TRI_EDM_NOALLOC_SCRATCH_BYTES, kept until
+ * the process ends).  Same arguments, kernels and results as tri_edm;
+ * TRI_EDM_FP32 needs no workspace and runs as tri_edm does.  A request
+ * whose workspace (tri_edm_workspace_size) exceeds the scratch returns
+ * TRI_E_RANGE and launches nothing (with d = 128 that is n above about
+ * 32000 points).  The call allocates nothing, on the device or the host
+ * heap; the first call on a device looks up that device's scratch address.
+ * Every call on one GPU shares that GPU's scratch and nothing in it needs
+ * to start cleared: calls that overlap in time on one GPU (other streams,
+ * other threads) race and must be serialised by the caller. */
+#define TRI_EDM_NOALLOC_SCRATCH_BYTES (16u << 20)
+tri_status tri_edm_noalloc(const tri_plan *plan, const float *x, int64_t d, int64_t ldx,
+                           float *out, int mode, float fixup_thr, void *stream);
+
 /* Collision detection of n spheres (the shared-memory test of Section 5).
  * The plan covers the strict lower triangle (include_diag must be 0); any
  * map, tile 8, 16, 32, 64 or 128 (tile maps stage both blocks of spheres in

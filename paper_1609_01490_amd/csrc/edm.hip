@@ -28,6 +28,8 @@
 #include "common.hpp"
 #include "maps.hpp"
 
+#include <mutex>
+
 namespace trimap {
 
 TileGrid plan_tile_grid(const tri_plan *p);
@@ -627,11 +629,11 @@ extern "C" tri_status tri_edm_workspace_size(const tri_plan *p, int64_t d, int m
     return TRI_OK;
 }
 
-extern "C" tri_status tri_edm(const tri_plan *p, const float *x, int64_t d, int64_t ldx,
-                              float *out, int mode, float fixup_thr, void *ws, size_t ws_bytes,
-                              void *stream)
+namespace trimap {
+
+static tri_status edm_run(const tri_plan *p, const float *x, int64_t d, int64_t ldx, float *out,
+                          int mode, float fixup_thr, void *ws, size_t ws_bytes, void *stream)
 {
-    clear_error();
     tri_status st = edm_check(p, d, mode);
     if (st != TRI_OK) return st;
     if (p->n < 2) return TRI_OK;
@@ -669,4 +671,64 @@ extern "C" tri_status tri_edm(const tri_plan *p, const float *x, int64_t d, int6
     if (!edm_mfma(p, a, split, s)) return fail(TRI_E_UNSUPPORTED, "tri_edm: map");
     TRI_HIP(hipGetLastError());
     return TRI_OK;
+}
+
+// Scratch of the allocation-free entry point: the MFMA modes' workspace in a
+// device array of the library (one copy on every GPU the library runs on,
+// held until the process ends).  In host code `scratch` names a host-side
+// stand-in, never the device memory: host code uses only the address
+// hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[TRI_EDM_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices];
+
+// Device address of the current device's scratch, looked up on the first
+// call on that device and kept.
+static tri_status edm_scratch(void **out)
+{
+    int dev = 0;
+    TRI_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(TRI_E_RANGE, "tri_edm_noalloc: device %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        TRI_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(TRI_E_HIP, "tri_edm_noalloc: no device address for the scratch");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return TRI_OK;
+}
+
+}  // namespace trimap
+
+extern "C" tri_status tri_edm(const tri_plan *p, const float *x, int64_t d, int64_t ldx,
+                              float *out, int mode, float fixup_thr, void *ws, size_t ws_bytes,
+                              void *stream)
+{
+    clear_error();
+    return edm_run(p, x, d, ldx, out, mode, fixup_thr, ws, ws_bytes, stream);
+}
+
+extern "C" tri_status tri_edm_noalloc(const tri_plan *p, const float *x, int64_t d, int64_t ldx,
+                                      float *out, int mode, float fixup_thr, void *stream)
+{
+    clear_error();
+    tri_status st = edm_check(p, d, mode);
+    if (st != TRI_OK) return st;
+    if (mode == TRI_EDM_FP32 || p->n < 2)
+        return edm_run(p, x, d, ldx, out, mode, fixup_thr, nullptr, 0, stream);
+    const size_t need = edm_ws_layout(p->n, d).total;
+    if (need > (size_t)TRI_EDM_NOALLOC_SCRATCH_BYTES)
+        return fail(TRI_E_RANGE,
+                    "tri_edm_noalloc: n = %lld, d = %lld need %zu bytes of workspace, above the "
+                    "%zu-byte scratch (use tri_edm with a caller workspace)",
+                    (long long)p->n, (long long)d, need, (size_t)TRI_EDM_NOALLOC_SCRATCH_BYTES);
+    void *ws = nullptr;
+    st = edm_scratch(&ws);
+    if (st != TRI_OK) return st;
+    return edm_run(p, x, d, ldx, out, mode, fixup_thr, ws, TRI_EDM_NOALLOC_SCRATCH_BYTES, stream);
 }

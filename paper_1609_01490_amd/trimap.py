@@ -24,6 +24,7 @@ FLAG_ORDER_REVERSE, FLAG_ORDER_PAIRS, FLAG_LIFE_TEMPORAL = 8, 16, 32
 FLAG_SQRT_NEWTON, FLAG_SQRT_EPS = 64, 128
 OP_XORMUL_I32, OP_AXPYT_F32, OP_EDM4_F32 = 0, 1, 2
 EDM_FP32, EDM_BF16X3, EDM_BF16 = 0, 1, 2
+EDM_NOALLOC_SCRATCH_BYTES = 16 << 20
 KIND_EDM, KIND_LIFE = 0, 1
 TUNE_ELEMENTWISE_F32, TUNE_ELEMENTWISE_I32, TUNE_LIFE, TUNE_EDM_FP32, TUNE_EDM_BF16X3 = range(5)
 BATCH_GRAPH, BATCH_STREAM, BATCH_PER_INSTANCE = 0, 1, 2
@@ -96,6 +97,8 @@ def _load() -> ctypes.CDLL:
     L.tri_edm_workspace_size.argtypes = [vp, i64, i32, ctypes.POINTER(ctypes.c_size_t)]
     L.tri_edm.restype = st
     L.tri_edm.argtypes = [vp, vp, i64, i64, vp, i32, ctypes.c_float, vp, ctypes.c_size_t, vp]
+    L.tri_edm_noalloc.restype = st
+    L.tri_edm_noalloc.argtypes = [vp, vp, i64, i64, vp, i32, ctypes.c_float, vp]
     L.tri_tet_plan.restype = st
     L.tri_tet_plan.argtypes = [ctypes.POINTER(vp), i64, i32, i32, i32, u32]
     L.tri_tet_destroy.restype = st
@@ -327,6 +330,20 @@ class Plan:
                   optional=True)
         _check(lib.tri_edm(self._h, px, int(d), int(ldx), po, int(mode), float(fixup_thr), pw,
                            int(wsb), _stream(stream)))
+
+    def edm_noalloc(self, x, out, mode: int = EDM_FP32, fixup_thr: float = 1e-2, stream=None):
+        """tri_edm_noalloc: the distance map with the library's own scratch
+        (no workspace argument, nothing allocated)."""
+        n = self.info.n
+        if x is None or x.dim() != 2:
+            raise TrimapArgError("x: an n x d matrix is required")
+        d, ldx = x.shape[1], x.stride(0)
+        if x.shape[0] != n:
+            raise TrimapArgError(f"x: {x.shape[0]} rows for a plan of n = {n}")
+        px = _arg(x, "x", F32, (n - 1) * ldx + d if n else 0)
+        po = _arg(out, "out", F32, n * (n - 1) // 2)
+        _check(lib.tri_edm_noalloc(self._h, px, int(d), int(ldx), po, int(mode),
+                                   float(fixup_thr), _stream(stream)))
 
     def dummy(self, target: int, sink, stream=None):
         """The square-root study's dummy kernel (tri_launch_dummy)."""

@@ -66,6 +66,14 @@ enum {
     TRI_FLAG_SQRT_EPS = 128u
 };
 
+/* Plan flags, bits 8..11: the number of consecutive tiles of the map that one
+ * workgroup walks in the kernels that take strips (the distance map's MFMA
+ * modes): TRI_FLAG_STRIP(k) asks for G = 2^k tiles (k = 0..5, G = 1..32);
+ * none of these bits set: G chosen from the tile count.  Kernels without
+ * strips ignore them. */
+#define TRI_FLAG_STRIP_MASK 0xF00u
+#define TRI_FLAG_STRIP(k) ((uint32_t)((k) + 1) << 8)
+
 /* Elementwise bodies. */
 enum {
     /* C[i][j] = (A[i] XOR B[j]) + i*j, uint32 wrap-around; x = A (uint32[n]),

@@ -30,6 +30,7 @@
 
 #include <mutex>
 
+
 namespace trimap {
 
 TileGrid plan_tile_grid(const tri_plan *p);
@@ -94,12 +95,28 @@ constexpr int kEdmTile = 128;     // output tile of the MFMA kernel
 constexpr int kColsumRows = 64;   // rows per block of the column-sum pass
 
 // Workspace of the MFMA modes (all offsets 256-byte aligned).
+//
+// Up to 128 dimensions (the strip kernel) the BF16 operands are stored in
+// MFMA fragment order, in groups of 32 points: for k-step s (16
+// dimensions), plane (hi, lo) and half h (dimensions 16 s + 8 h .. + 7), one
+// 16-byte vector per point,
+//   frag[((p / 32) * S * planes * 2 + (s * planes + plane) * 2 + h) * 32 + p % 32],
+// so that a wave's 64 lanes (32 points, two halves) read the operand of one
+// 32 x 32 x 16 MFMA as 1 KiB of contiguous memory, and all operands of 32
+// points form one contiguous block.  The dimensions are padded to S = 2, 4
+// or 8 k-steps and the points to np (every row block of the tile grid,
+// zeros beyond n).
+// Above 128 dimensions the chunked kernel reads row-major hi and lo planes.
 struct EdmWs {
     size_t hi, lo, norms, mean, partial, total;
     int64_t dp, nb;
+    int64_t np;    // points in the fragment layout (strip kernel), else n
+    int32_t S;     // k-steps of the strip kernel, 0: chunked kernel
 };
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+constexpr int kStripMaxDims = 128;
 
 static EdmWs edm_ws_layout(int64_t n, int64_t d)
 {
@@ -107,9 +124,22 @@ static EdmWs edm_ws_layout(int64_t n, int64_t d)
     w.dp = (d + 15) / 16 * 16;
     w.nb = (n + kColsumRows - 1) / kColsumRows;
     size_t o = 0;
-    w.hi = o;      o = align256(o + (size_t)n * w.dp * 2);
-    w.lo = o;      o = align256(o + (size_t)n * w.dp * 2);
-    w.norms = o;   o = align256(o + (size_t)n * 4);
+    if (w.dp <= kStripMaxDims) {
+        const int64_t ks = w.dp / 16;
+        w.S = ks <= 2 ? 2 : (ks <= 4 ? 4 : 8);
+        w.dp = 16 * w.S;
+        // rows of the last tile row reach 1 + 128 m <= n + 128
+        w.np = (n + kEdmTile) / kEdmTile * kEdmTile + kEdmTile;
+        w.hi = o;  o = align256(o + (size_t)w.np * w.dp * 4);  // both planes
+        w.lo = w.hi;
+        w.norms = o; o = align256(o + (size_t)w.np * 4);
+    } else {
+        w.S = 0;
+        w.np = n;
+        w.hi = o;      o = align256(o + (size_t)n * w.dp * 2);
+        w.lo = o;      o = align256(o + (size_t)n * w.dp * 2);
+        w.norms = o;   o = align256(o + (size_t)n * 4);
+    }
     w.mean = o;    o = align256(o + (size_t)w.dp * 4);
     w.partial = o; o = align256(o + (size_t)w.nb * w.dp * 4);
     w.total = o;
@@ -190,11 +220,12 @@ struct EdmMfmaArgs {
     float thr;
 };
 
-__device__ __noinline__ float direct_d2(const float *x, int64_t ldx, int32_t d, int32_t i,
+__device__ __forceinline__ float direct_d2(const float *x, int64_t ldx, int32_t d, int32_t i,
                                            int32_t j)
 {
     const float *xi = x + (int64_t)i * ldx, *xj = x + (int64_t)j * ldx;
     float s = 0.f;
+#pragma unroll 1
     for (int32_t k = 0; k < d; ++k) {
         const float df = xi[k] - xj[k];
         s = __builtin_fmaf(df, df, s);
@@ -210,6 +241,11 @@ constexpr int kKC = 64;                // dimensions per LDS chunk
 constexpr int kRS = kKC + 8;           // operand row stride in bf16 (144 bytes)
 constexpr int kPlaneBytes = kEdmTile * kRS * 2;
 constexpr int kVecPerThread = kEdmTile * kKC / 8 / 256;  // 16-byte vectors per plane
+
+// s_waitcnt immediate that waits until at most n vector memory operations
+// of this wave are outstanding (vmcnt(n), 0 <= n <= 63), leaving expcnt and
+// lgkmcnt at their maxima (no wait).
+constexpr unsigned waitcnt_vm(unsigned n) { return (n & 0xFu) | ((n >> 4) << 14) | 0x0F70u; }
 
 // Workgroup barrier that orders LDS traffic only: wait for this wave's LDS
 // operations, then s_barrier.  Unlike __syncthreads() it does not wait for
@@ -578,6 +614,489 @@ static bool edm_mfma(const tri_plan *p, const EdmMfmaArgs &a, bool split, hipStr
     return false;
 }
 
+// ---------------------------------------------------------------------------
+// Strip kernel of the MFMA modes (up to 128 dimensions).
+//
+// A workgroup (four waves) takes G consecutive tiles of the map (a strip:
+// consecutive omega for lambda, consecutive grid columns of one grid row for
+// BB, RB and REC), which mostly share their tile row.  The row block of a
+// tile row (128 points x all k-steps x both planes, 64 KiB at 128
+// dimensions) is staged in LDS once per change of tile row; wave w owns the
+// tile's columns 32 w .. 32 w + 31 for all 128 rows (four 32 x 32 MFMA
+// blocks) and holds its column points' operands for every k-step in
+// registers.  Those registers are a ring: as soon as the products of k-step
+// s are issued, the operand of k-step s of the next tile of the strip is
+// loaded in its place, so each tile's column operands arrive during the
+// previous tile.  Distances are stored straight from the MFMA layout: per
+// store, 32 lanes write 32 consecutive pairs of one row (128 bytes), and
+// the four waves of a tile, and the tiles of a strip, complete each other's
+// cache lines in L2.
+// ---------------------------------------------------------------------------
+
+// Pre-pass in fragment order: one thread per point p < np centres its
+// coordinates, splits them into BF16 hi and lo (hi only for single BF16),
+// and sums the norm of the rounded operands, hi.hi + 2 hi.lo, in dimension
+// order.  Points beyond n get zeros.
+template <bool SPLIT, int S>
+__global__ void __launch_bounds__(256) k_edm_frag(const float *x, int32_t n, int32_t d,
+                                                  int64_t ldx, int32_t np, const float *mean,
+                                                  bf16x8 *frag, float *norms)
+{
+    constexpr int P = SPLIT ? 2 : 1;
+    const int32_t p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= np) return;
+    const bool live = p < n;
+    float acc = 0.f;
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            bf16x8 hv, lv;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int32_t k = 16 * s + 8 * h + e;
+                float c = 0.f;
+                if (live && k < d) c = x[(int64_t)p * ldx + k] - mean[k];
+                const __bf16 hb = (__bf16)c;
+                const float hf = (float)hb;
+                const __bf16 lb = (__bf16)(c - hf);
+                const float lf = (float)lb;
+                hv[e] = hb;
+                lv[e] = lb;
+                if (SPLIT) acc = __builtin_fmaf(hf, hf, __builtin_fmaf(2.f * hf, lf, acc));
+                else acc = __builtin_fmaf(hf, hf, acc);
+            }
+            const int64_t grp = (int64_t)(p >> 5) * (S * P * 2) * 32 + (p & 31);
+            frag[grp + ((s * P) * 2 + h) * 32] = hv;
+            if (SPLIT) frag[grp + ((s * P + 1) * 2 + h) * 32] = lv;
+        }
+    norms[p] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// Line-aligned strip kernel of the MFMA modes (up to 128 dimensions).
+//
+// A workgroup (four waves) walks G consecutive tiles of the map (a strip,
+// see strip_first); wave w owns rows R0 + 32 w .. + 31 of every tile and
+// all of its 128 columns (four 32 x 32 MFMA blocks), so the wave's row
+// operands stay in registers while the strip stays in one tile row, and the
+// tile's column operands (128 points x all k-steps x both planes, 64 KiB at
+// 128 dimensions) are staged in LDS straight from global memory for all
+// four waves, the next tile's during this tile's stores.
+//
+// Stores: the condensed rows start at any word, and a store that covers
+// parts of two 128-byte lines costs the memory system about 1.6 times a
+// whole-line store (measured).  So every store instruction writes one whole
+// aligned line of one row (lanes 0..31; lanes 32..63 the row four below):
+// with delta the row's misalignment (in floats) at the tile's first column,
+// line k of the row covers the tile's columns 32 k - delta .. 32 k + 31 -
+// delta, i.e. the last delta columns of MFMA block k - 1 and the first 32 -
+// delta of block k.  Lane l takes block k's column l when l < 32 - delta and
+// block k - 1's column l otherwise; the lanes then hold the line's 32
+// addresses in another order, and a per-lane select is all the data
+// movement.  Block -1 is the previous tile's block 3, carried in registers
+// when the previous tile of the strip is the left neighbour; at a strip's
+// end a tile stores its own tail.
+//
+// The norms enter the products through one more k-step (exact products of a
+// norm part and one), so the accumulator ends holding -d^2 / 2.
+// ---------------------------------------------------------------------------
+
+// Three BF16 parts of a value: v ~ h + m + lo to about 2^-24 relative.
+__device__ __forceinline__ void split3(float v, __bf16 &h, __bf16 &m, __bf16 &lo)
+{
+    h = (__bf16)v;
+    const float r1 = v - (float)h;
+    m = (__bf16)r1;
+    lo = (__bf16)(r1 - (float)m);
+}
+
+// Norm step of a row point (dimensions 0..5: -n_i / 2 in three parts, 1, 1,
+// 1) and of a column point (1, 1, 1, -n_j / 2 in three parts); lanes 32..63
+// hold dimensions 8..15, all zero.
+__device__ __forceinline__ bf16x8 ext_row(float ni, int l)
+{
+    bf16x8 v{};
+    if (l < 32) {
+        __bf16 h, m, lo;
+        split3(-0.5f * ni, h, m, lo);
+        v[0] = h; v[1] = m; v[2] = lo;
+        v[3] = (__bf16)1.f; v[4] = (__bf16)1.f; v[5] = (__bf16)1.f;
+    }
+    return v;
+}
+
+__device__ __forceinline__ bf16x8 ext_col(float nj, int l)
+{
+    bf16x8 v{};
+    if (l < 32) {
+        __bf16 h, m, lo;
+        split3(-0.5f * nj, h, m, lo);
+        v[0] = (__bf16)1.f; v[1] = (__bf16)1.f; v[2] = (__bf16)1.f;
+        v[3] = h; v[4] = m; v[5] = lo;
+    }
+    return v;
+}
+
+// The distance from an accumulator holding -d^2 / 2: d^2 = -2 acc exactly.
+// A square that rounding made negative (acc > 0) counts as near and is
+// recomputed; its magnitude keeps the stored value a number.
+__device__ __forceinline__ float dist_of(float acc)
+{
+    return __builtin_amdgcn_sqrtf(2.f * __builtin_fabsf(acc));
+}
+
+struct EdmLinesArgs {
+    TileGrid g;
+    StripGrid sg;
+    int32_t n, d;
+    int64_t ldx;
+    const float *x;
+    const bf16x8 *frag;
+    const float *norms;
+    float *out;
+    float thr;  // fix-up threshold on d^2
+};
+
+template <int MAP, bool SPLIT, int S>
+__global__ void __launch_bounds__(256, 2) k_edm_lines(EdmLinesArgs a)
+{
+    constexpr int P = SPLIT ? 2 : 1;
+    constexpr int KP = S * P;                 // operand planes (k-step, hi / lo)
+    constexpr int kGroup = KP * 2 * 32;       // frag vectors per group of 32 points
+    // column operands of the tile: 16-byte vector (plane r, block c, lane) at
+    // (r 4 + c) 64 + lane; the column norms of block c at sN[c 64 + lane]
+    // (lanes 32..63 repeat lanes 0..31)
+    __shared__ bf16x8 sB[KP * 4 * 64];
+    __shared__ float sN[4 * 64];
+
+    const int t = threadIdx.x, l = t & 63, lo = l & 31, hf = l >> 5;
+    const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int32_t n = a.n;
+    const float nthr = -0.5f * a.thr;  // near: acc > -thr / 2, i.e. d^2 < thr
+    // misalignment of the output array within a 128-byte line, in floats
+    const uint32_t amod = (uint32_t)(((uintptr_t)a.out >> 2) & 31u);
+
+    const uint32_t first = strip_first<MAP>(a.g, a.sg);
+    int32_t bi, bj;
+    int k = strip_next<MAP>(a.g, a.sg, first, 0, bi, bj);
+    if (k >= a.sg.G) return;  // the whole strip maps to no tile (uniform)
+    bi = __builtin_amdgcn_readfirstlane(bi);
+    bj = __builtin_amdgcn_readfirstlane(bj);
+
+    // the wave's row operands: row R0 + 32 w + (l & 31), half l >> 5
+    bf16x8 A[S][P];
+    bf16x8 Ax;   // its norm step
+    float nrow = 0.f;
+    auto load_rows = [&](int32_t rbi) {
+        const int32_t r0 = 1 + rbi * kEdmTile + 32 * w + lo;
+        const bf16x8 *rowp = a.frag + (int64_t)(r0 >> 5) * kGroup + hf * 32 + (r0 & 31);
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int pl = 0; pl < P; ++pl) A[s][pl] = rowp[(s * P + pl) * 64];
+        nrow = a.norms[r0];
+    };
+    // the tile's column operands into LDS: wave w stages column block w
+    // (32 points: each plane is 1 KiB of contiguous frag, one 16-byte load
+    // per lane landing in lane order) and its 32 column norms, with no
+    // register in between
+    auto stage_cols = [&](int32_t cbj) {
+        const bf16x8 *src = a.frag + (int64_t)(4 * cbj + w) * kGroup + l;
+#pragma unroll
+        for (int r = 0; r < KP; ++r)
+            __builtin_amdgcn_global_load_lds(
+                (const __attribute__((address_space(1))) void *)(src + r * 64),
+                (__attribute__((address_space(3))) void *)(sB + (r * 4 + w) * 64), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds(
+            (const __attribute__((address_space(1))) void *)(a.norms + cbj * kEdmTile + 32 * w + lo),
+            (__attribute__((address_space(3))) void *)(sN + w * 64), 4, 0, 0);
+    };
+
+    // The store geometry of a tile row, the same for all its tiles (their
+    // first columns are multiples of 32 floats): for the row i of register r
+    // (this lane's half), offw[r] = 4 (rowoff(i) + lane - 32 wrap) + wrap,
+    // with rowoff(i) the offset of (i, 0) from row R0's start and wrap = 1 when
+    // this lane takes the block to the left in every line of the row (lane >=
+    // 32 - delta, delta the row's misalignment).  Line k of the tile at
+    // column CW then sits at orow + 4 CW + (offw & ~3) + 128 k.
+    uint32_t offw[16];
+    char *orow = nullptr;
+    int32_t R0 = 0;
+    auto set_rows = [&](int32_t rbi) {
+        R0 = 1 + rbi * kEdmTile;
+        const uint64_t TR0 = (uint64_t)R0 * (uint64_t)(R0 - 1) / 2;
+        orow = (char *)(a.out + TR0);
+        const uint32_t rmod = (uint32_t)(TR0 & 31u) + amod;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int32_t i = R0 + 32 * w + 8 * (r >> 2) + 4 * hf + (r & 3);
+            const uint32_t ro = (uint32_t)((i - R0) * (i + R0 - 1)) / 2u;
+            const uint32_t wrap = (uint32_t)(lo + (int32_t)((ro + rmod) & 31u) >= 32);
+            offw[r] = ((ro + (uint32_t)lo - 32u * wrap) << 2) | wrap;
+        }
+    };
+
+    load_rows(bi);
+    stage_cols(bj);
+    set_rows(bi);
+    __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
+    Ax = ext_row(nrow, l);
+    lds_barrier();
+
+    f32x16 carry{};           // distances of the previous tile's block 3
+    uint32_t carry_near = 0;  // which of them are near (bit r)
+    bool carry_ok = false;    // the previous tile of the strip is the left neighbour
+    for (;;) {
+        int32_t nbi = 0, nbj = 0;
+        const int nk = strip_next<MAP>(a.g, a.sg, first, k + 1, nbi, nbj);
+        const bool more = nk < a.sg.G;
+        nbi = __builtin_amdgcn_readfirstlane(nbi);
+        nbj = __builtin_amdgcn_readfirstlane(nbj);
+
+        const int32_t CW = bj * kEdmTile;
+        const uint32_t cw4 = 4u * (uint32_t)CW;
+        const bool tail_self = !(more && nbi == bi && nbj == bj + 1);
+        const bool full = CW + kEdmTile - 1 < R0 && R0 + kEdmTile - 1 < n;
+        // per-lane test of pair (row of register r, tile column jt), for
+        // tiles that cross the diagonal or the last row
+        auto inside = [&](int r, int32_t jt) {
+            const int32_t i = R0 + 32 * w + 8 * (r >> 2) + 4 * hf + (r & 3);
+            return i < n && CW + jt >= 0 && CW + jt < i;
+        };
+
+        // Two passes of two column blocks each: acc[e] = rows x column
+        // block 2 pass + e (half the accumulators of the tile at a time).
+        f32x16 mid{};          // distances of block 1 (line 2 takes its tail)
+        uint64_t near = 0;     // bit c 16 + r: the square is below the threshold
+        bool waited = false;
+#pragma unroll
+        for (int pass = 0; pass < 2; ++pass) {
+            f32x16 acc[2];
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const f32x16 z{};
+                acc[e] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                    Ax, ext_col(sN[(2 * pass + e) * 64 + l], l), z, 0, 0, 0);
+            }
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                bf16x8 Bh[2], Bl[2];
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    Bh[e] = sB[((s * P) * 4 + 2 * pass + e) * 64 + l];
+                    if constexpr (SPLIT) Bl[e] = sB[((s * P + 1) * 4 + 2 * pass + e) * 64 + l];
+                }
+#pragma unroll
+                for (int e = 0; e < 2; ++e)
+                    acc[e] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[s][0], Bh[e], acc[e], 0, 0, 0);
+                if constexpr (SPLIT) {
+#pragma unroll
+                    for (int e = 0; e < 2; ++e)
+                        acc[e] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[s][0], Bl[e], acc[e], 0, 0, 0);
+#pragma unroll
+                    for (int e = 0; e < 2; ++e)
+                        acc[e] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[s][P - 1], Bh[e], acc[e], 0, 0, 0);
+                }
+            }
+            // keep the scheduler from moving the stores' arithmetic into the
+            // products (it would hold it in registers there)
+            __builtin_amdgcn_sched_barrier(0);
+            {
+                float mx = acc[0][0];
+#pragma unroll
+                for (int e = 0; e < 2; ++e)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) mx = fmaxf(mx, acc[e][r]);
+                if (__any(mx > nthr)) {  // rare: which squares (bit c 16 + r)
+                    // shifted in one at a time: no per-bit constant is held
+                    uint32_t m = 0;
+#pragma unroll
+                    for (int e = 1; e >= 0; --e)
+#pragma unroll
+                        for (int r = 15; r >= 0; --r) m = (m << 1) | (uint32_t)(acc[e][r] > nthr);
+                    near |= (uint64_t)m << (32 * pass);
+                }
+            }
+            f32x16 D[2];
+#pragma unroll
+            for (int e = 0; e < 2; ++e)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) D[e][r] = dist_of(acc[e][r]);
+
+            if (pass == 0) {
+                // line 0 (the carry's tail and block 0) and line 1 (blocks 0, 1)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const bool wrap = offw[r] & 1u;
+                    const uint32_t off = (offw[r] & ~3u) + cw4;
+                    if (full) {
+                        if (carry_ok || !wrap) *(float *)(orow + off) = wrap ? carry[r] : D[0][r];
+                        *(float *)(orow + off + 128u) = wrap ? D[0][r] : D[1][r];
+                    } else {
+                        const int32_t jt = lo - 32 * (int32_t)wrap;
+                        if ((carry_ok || !wrap) && inside(r, jt))
+                            *(float *)(orow + off) = wrap ? carry[r] : D[0][r];
+                        if (inside(r, jt + 32)) *(float *)(orow + off + 128u) = wrap ? D[0][r] : D[1][r];
+                    }
+                    __builtin_amdgcn_sched_barrier(0);  // one row at a time
+                }
+                mid = D[1];
+                __builtin_amdgcn_sched_barrier(0);
+            } else {
+                lds_barrier();  // every wave is done with sB
+                // line 4: the tile's own tail (block 3, columns 128 - delta ..)
+                if (tail_self) {
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const uint32_t off = (offw[r] & ~3u) + cw4 + 512u;
+                        if ((offw[r] & 1u) && (full || inside(r, 96 + lo)))
+                            *(float *)(orow + off) = D[1][r];
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                }
+                // the next tile's operands, in flight during lines 2 and 3
+                if (more) stage_cols(nbj);
+                const bool reload = more && nbi != bi;
+                if (reload) {
+                    // a new tile row (once a strip, or where it crosses a row
+                    // end): wait for its row operands here, so that the
+                    // products never wait for a store
+                    load_rows(nbi);
+                    __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
+                }
+                // the 32 stores below stay after these loads (the wait for the
+                // loads counts them)
+                asm volatile("" ::: "memory");
+                // lines 2 (blocks 1, 2) and 3 (blocks 2, 3)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const bool wrap = offw[r] & 1u;
+                    const uint32_t off = (offw[r] & ~3u) + cw4;
+                    if (full) {
+                        *(float *)(orow + off + 256u) = wrap ? mid[r] : D[0][r];
+                        *(float *)(orow + off + 384u) = wrap ? D[0][r] : D[1][r];
+                    } else {
+                        const int32_t jt = lo - 32 * (int32_t)wrap;
+                        if (inside(r, jt + 64)) *(float *)(orow + off + 256u) = wrap ? mid[r] : D[0][r];
+                        if (inside(r, jt + 96)) *(float *)(orow + off + 384u) = wrap ? D[0][r] : D[1][r];
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                // near-duplicates (rare): recompute directly in FP32 over the
+                // values just stored, the carried ones included
+                if (__any((near | (carry_ok ? carry_near : 0u)) != 0)) {
+                    // bits 0..63: this tile's squares; then the carried ones
+                    uint64_t mk = near;
+                    uint32_t mc = carry_ok ? carry_near : 0u;
+                    while (mk | mc) {
+                        int r, jt;
+                        if (mk) {
+                            const int b = __builtin_ctzll(mk);
+                            mk &= mk - 1;
+                            r = b & 15;
+                            jt = 32 * (b >> 4) + lo;
+                            // block 3's tail goes to the next tile unless this tile stores it
+                            if ((b >> 4) == 3 && (offw[r] & 1u) && !tail_self) continue;
+                        } else {
+                            r = __builtin_ctz(mc);
+                            mc &= mc - 1;
+                            if (!(offw[r] & 1u)) continue;  // not a carried value
+                            jt = lo - 32;
+                        }
+                        if (!inside(r, jt)) continue;
+                        const int32_t i = R0 + 32 * w + 8 * (r >> 2) + 4 * hf + (r & 3);
+                        const uint32_t ro = (uint32_t)((i - R0) * (i + R0 - 1)) / 2u;
+                        *(float *)(orow + 4u * (ro + (uint32_t)(CW + jt))) =
+                            __builtin_amdgcn_sqrtf(direct_d2(a.x, a.ldx, a.d, i, CW + jt));
+                    }
+                    __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
+                    waited = true;
+                }
+                carry = D[1];
+            }
+        }
+        const bool reload = more && nbi != bi;
+        // the carry for the next tile (block 3's distances, set above)
+        carry_near = (uint32_t)(near >> 48);
+        carry_ok = !tail_self;
+
+        // Every load issued so far is complete here; in a full tile only the
+        // 32 stores of lines 2 and 3 may still be in flight.
+        if (!waited) {
+            if (full) __builtin_amdgcn_s_waitcnt(waitcnt_vm(32));
+            else __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
+        }
+        if (reload) {
+            Ax = ext_row(nrow, l);
+            set_rows(nbi);
+        }
+        lds_barrier();
+        if (!more) break;
+        k = nk;
+        bi = nbi;
+        bj = nbj;
+    }
+}
+
+// Workgroups that share a group of strips (1: each workgroup's tiles are
+// consecutive, so the carry passes from tile to tile).
+constexpr int32_t kEdmStripGroup = 1;
+
+// Tiles per strip: the plan's TRI_FLAG_STRIP, else enough strips for
+// several rounds of the GPU's workgroup slots and strips long enough that the
+// row operands loaded into registers serve several tiles.
+static int32_t strip_len(const tri_plan *p)
+{
+    if (const int32_t f = strip_flag_len(p->flags)) return f;
+    const uint64_t g = (uint64_t)p->T / 8192;
+    return (int32_t)(g < 1 ? 1 : (g > 8 ? 8 : g));
+}
+
+template <int MAP, bool SPLIT, int S>
+static void edm_lines_launch(const tri_plan *p, const EdmLinesArgs &a0, hipStream_t s)
+{
+    EdmLinesArgs a = a0;
+    dim3 grid;
+    a.sg = strip_grid(MAP, a.g.T, p->gx, p->gy, strip_len(p), kEdmStripGroup, grid);
+    k_edm_lines<MAP, SPLIT, S><<<grid, 256, 0, s>>>(a);
+}
+
+template <bool SPLIT, int S>
+static bool edm_lines_map(const tri_plan *p, const EdmLinesArgs &a, hipStream_t s)
+{
+    switch (p->map) {
+    case TRI_MAP_BB: edm_lines_launch<MAP_BB, SPLIT, S>(p, a, s); return true;
+    case TRI_MAP_RB: edm_lines_launch<MAP_RB, SPLIT, S>(p, a, s); return true;
+    case TRI_MAP_REC: edm_lines_launch<MAP_REC, SPLIT, S>(p, a, s); return true;
+    case TRI_MAP_LAMBDA: edm_lines_launch<MAP_LAMBDA, SPLIT, S>(p, a, s); return true;
+    }
+    return false;
+}
+
+template <bool SPLIT>
+static bool edm_lines(const tri_plan *p, const EdmLinesArgs &a, int S, hipStream_t s)
+{
+    switch (S) {
+    case 2: return edm_lines_map<SPLIT, 2>(p, a, s);
+    case 4: return edm_lines_map<SPLIT, 4>(p, a, s);
+    case 8: return edm_lines_map<SPLIT, 8>(p, a, s);
+    }
+    return false;
+}
+
+template <bool SPLIT>
+static void edm_frag_launch(int S, const float *x, int32_t n, int32_t d, int64_t ldx, int32_t np,
+                            const float *mean, bf16x8 *frag, float *norms, hipStream_t s)
+{
+    const dim3 grid((uint32_t)((np + 255) / 256));
+    switch (S) {
+    case 2: k_edm_frag<SPLIT, 2><<<grid, 256, 0, s>>>(x, n, d, ldx, np, mean, frag, norms); break;
+    case 4: k_edm_frag<SPLIT, 4><<<grid, 256, 0, s>>>(x, n, d, ldx, np, mean, frag, norms); break;
+    case 8: k_edm_frag<SPLIT, 8><<<grid, 256, 0, s>>>(x, n, d, ldx, np, mean, frag, norms); break;
+    }
+}
+
 // One distance-map domain under lambda with the FP32 body (batched
 // per-instance mode); false for an unsupported tile.
 bool launch_edm_f32_lambda(int tile, const TileGrid &g, const EdmTile &t, hipStream_t s)
@@ -662,6 +1181,18 @@ static tri_status edm_run(const tri_plan *p, const float *x, int64_t d, int64_t 
     const bool split = (mode == TRI_EDM_BF16X3);
     k_edm_colsum<<<dim3((uint32_t)L.nb), 256, 0, s>>>(x, n, dd, ldx, dp, partial);
     k_edm_mean<<<dim3((uint32_t)dp), 256, 0, s>>>(partial, (int32_t)L.nb, n, dp, mean);
+    if (L.S) {
+        bf16x8 *frag = (bf16x8 *)(w + L.hi);
+        const int32_t np = (int32_t)L.np;
+        if (split) edm_frag_launch<true>(L.S, x, n, dd, ldx, np, mean, frag, norms, s);
+        else edm_frag_launch<false>(L.S, x, n, dd, ldx, np, mean, frag, norms, s);
+        TRI_HIP(hipGetLastError());
+        EdmLinesArgs a{plan_tile_grid(p), StripGrid{}, n, dd, ldx, x, frag, norms, out, fixup_thr};
+        const bool ok = split ? edm_lines<true>(p, a, L.S, s) : edm_lines<false>(p, a, L.S, s);
+        if (!ok) return fail(TRI_E_UNSUPPORTED, "tri_edm: map");
+        TRI_HIP(hipGetLastError());
+        return TRI_OK;
+    }
     if (split)
         k_edm_split<true><<<dim3((uint32_t)n), 64, 0, s>>>(x, dd, ldx, dp, mean, hi, lo, norms);
     else

@@ -165,10 +165,11 @@ enum { MAP_BB = TRI_MAP_BB, MAP_RB = TRI_MAP_RB, MAP_REC = TRI_MAP_REC,
 // Tile of this workgroup under a tile-space map, or false when the block is
 // discarded.  BB, RB and REC use a 2-D grid (blockIdx.x = column); lambda a
 // 1-D grid (2-D only when the tile count exceeds one grid dimension).
+// The 2-D tile maps at an explicit grid position (bx, by): BB, RB and REC.
 template <int MAP>
-__device__ __forceinline__ bool tile_of_block_raw(const TileGrid &g, int32_t &bi, int32_t &bj)
+__device__ __forceinline__ bool tile_at_xy(const TileGrid &g, int32_t bx, int32_t by, int32_t &bi,
+                                           int32_t &bj)
 {
-    const int32_t bx = (int32_t)blockIdx.x, by = (int32_t)blockIdx.y;
     if constexpr (MAP == MAP_BB) {
         // Section 4.2: the block test (on or below the diagonal) comes before
         // any thread coordinate is formed.
@@ -200,7 +201,16 @@ __device__ __forceinline__ bool tile_of_block_raw(const TileGrid &g, int32_t &bi
         bi = q * 2 * s + s + r;
         bj = q * 2 * s + c;
         return true;
-    } else {  // MAP_LAMBDA
+    }
+    return false;
+}
+
+template <int MAP>
+__device__ __forceinline__ bool tile_of_block_raw(const TileGrid &g, int32_t &bi, int32_t &bj)
+{
+    if constexpr (MAP != MAP_LAMBDA) {
+        return tile_at_xy<MAP>(g, (int32_t)blockIdx.x, (int32_t)blockIdx.y, bi, bj);
+    } else {
         if (g.flags & kLambda24) {
             // 1-D grid of exactly T < 2^24 blocks, default root and order
             uint32_t L = blockIdx.x;
@@ -234,6 +244,99 @@ __device__ __forceinline__ bool tile_of_block(const TileGrid &g, int32_t &bi, in
 {
     if (!tile_of_block_raw<MAP>(g, bi, bj)) return false;
     return (uint32_t)bi < (uint32_t)g.m && (uint32_t)bj <= (uint32_t)bi;
+}
+
+// ---------------------------------------------------------------------------
+// Strips: a workgroup walks G tiles of the map, so that one dispatch serves
+// several tiles and the tiles of a strip, which mostly share their tile row,
+// reuse what the workgroup has staged.  The tiles are taken in groups of
+// K G consecutive tile numbers (omega under lambda; grid columns of one
+// grid row, blockIdx.y, under BB, RB and REC) shared by K consecutive
+// workgroups: workgroup k of a group takes numbers k, k + K, k + 2K, ...,
+// so at each step the group's K workgroups work on K adjacent tiles (with
+// the XCD swizzle, on one XCD and one L2).  The dispatch order and swizzle
+// of lambda act on workgroups.  Every tile is still mapped on its own.
+// ---------------------------------------------------------------------------
+struct StripGrid {
+    uint32_t strips;  // lambda: workgroups in the launch (gridDim.x)
+    int32_t G;        // tiles per workgroup
+    int32_t K;        // workgroups per group
+    int32_t gx;       // BB / RB / REC: columns of the map's grid
+};
+
+// Launch grid of a strip kernel for a plan's map and its grid (gx, gy).
+__host__ __forceinline__ StripGrid strip_grid(int map, uint64_t T, uint32_t gx, uint32_t gy,
+                                              int32_t G, int32_t K, dim3 &grid)
+{
+    StripGrid s{0u, G, K, (int32_t)gx};
+    const uint64_t span = (uint64_t)G * (uint64_t)K;  // tile numbers per group
+    if (map == TRI_MAP_LAMBDA) {
+        s.strips = (uint32_t)((T + span - 1) / span * (uint64_t)K);
+        grid = dim3(s.strips, 1);
+    } else {
+        grid = dim3((uint32_t)((gx + span - 1) / span * (uint64_t)K), gy);
+    }
+    return s;
+}
+
+// First tile number of this workgroup's strip; its tile t is first + t K.
+template <int MAP>
+__device__ __forceinline__ uint32_t strip_first(const TileGrid &g, const StripGrid &sg)
+{
+    uint32_t L = blockIdx.x;
+    if constexpr (MAP == MAP_LAMBDA) {
+        const uint32_t ns = sg.strips;
+        if (g.flags & TRI_FLAG_XCD_SWIZZLE) {
+            const uint32_t x = L & 7, q = ns >> 3, r = ns & 7;
+            L = x * q + (x < r ? x : r) + (L >> 3);
+        }
+        // the orders act on whole groups
+        const uint32_t K = (uint32_t)sg.K, ng = ns / K, grp = L / K, k = L % K;
+        uint32_t G2 = grp;
+        if (g.flags & TRI_FLAG_ORDER_REVERSE) G2 = ng - 1 - grp;
+        else if (g.flags & TRI_FLAG_ORDER_PAIRS) G2 = (grp & 1) ? ng - 1 - (grp >> 1) : (grp >> 1);
+        return G2 * K * (uint32_t)sg.G + k;
+    } else {
+        const uint32_t K = (uint32_t)sg.K;
+        return (L / K) * K * (uint32_t)sg.G + L % K;
+    }
+}
+
+// Tile t of the strip starting at `first`, or false when it maps to no tile
+// (beyond the grid, or a bounding-box block above the diagonal).  Lambda
+// takes its 32-bit exact form (strip kernels need fewer than 2^32 tiles).
+template <int MAP>
+__device__ __forceinline__ bool strip_tile(const TileGrid &g, const StripGrid &sg, uint32_t first,
+                                           int k, int32_t &bi, int32_t &bj)
+{
+    if constexpr (MAP == MAP_LAMBDA) {
+        const uint32_t w = first + (uint32_t)k * (uint32_t)sg.K;
+        if (w >= (uint32_t)g.T) return false;
+        if (g.T <= (1ull << 24)) lambda_tile_24(w, bi, bj);
+        else lambda_tile_32(w, bi, bj);
+    } else {
+        const int32_t bx = (int32_t)first + k * sg.K;
+        if (bx >= sg.gx) return false;
+        if (!tile_at_xy<MAP>(g, bx, (int32_t)blockIdx.y, bi, bj)) return false;
+    }
+    return (uint32_t)bi < (uint32_t)g.m && (uint32_t)bj <= (uint32_t)bi;
+}
+
+// First tile index >= k of the strip that maps to a tile (G if none).
+template <int MAP>
+__device__ __forceinline__ int strip_next(const TileGrid &g, const StripGrid &sg, uint32_t first,
+                                          int k, int32_t &bi, int32_t &bj)
+{
+    for (; k < sg.G; ++k)
+        if (strip_tile<MAP>(g, sg, first, k, bi, bj)) return k;
+    return sg.G;
+}
+
+// Tiles per strip asked for by a plan's TRI_FLAG_STRIP bits (0: none).
+__host__ __device__ __forceinline__ int32_t strip_flag_len(uint32_t flags)
+{
+    const uint32_t v = (flags & TRI_FLAG_STRIP_MASK) >> 8;
+    return v ? (1 << (v - 1)) : 0;
 }
 
 // ---------------------------------------------------------------------------

@@ -22,6 +22,12 @@ MAP_NAMES = {v: k for k, v in MAPS.items()}
 FLAG_XCD_SWIZZLE, FLAG_SQRT_RSQ, FLAG_SQRT_F64 = 1, 2, 4
 FLAG_ORDER_REVERSE, FLAG_ORDER_PAIRS, FLAG_LIFE_TEMPORAL = 8, 16, 32
 FLAG_SQRT_NEWTON, FLAG_SQRT_EPS = 64, 128
+FLAG_STRIP_MASK = 0xF00
+
+
+def FLAG_STRIP(k: int) -> int:
+    """Plan flag: strips of 2^k consecutive tiles per workgroup (k = 0..5)."""
+    return (k + 1) << 8
 OP_XORMUL_I32, OP_AXPYT_F32, OP_EDM4_F32 = 0, 1, 2
 EDM_FP32, EDM_BF16X3, EDM_BF16 = 0, 1, 2
 EDM_NOALLOC_SCRATCH_BYTES = 16 << 20

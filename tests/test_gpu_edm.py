@@ -167,6 +167,49 @@ def test_edm_mfma_small(mode, map_name):
                     assert abs(g - e[j]) / e[j] <= _fp32_bound(d)
 
 
+@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("map_name,flags", [("lambda", 0), ("lambda", 1 | 16), ("lambda", 8),
+                                            ("bb", 0), ("rb", 0), ("rec", 0)])
+@pytest.mark.parametrize("strip", [1, 2, 5])
+def test_edm_mfma_strips(mode, map_name, flags, strip):
+    """Workgroups walking strips of 2, 4 and 32 consecutive tiles (the row
+    block staged once per change of tile row, the column operands loaded one
+    tile ahead): whole rows against the FP64 oracle at n where strips cross
+    tile rows and end past the last tile.  REC at m = 8 and 16."""
+    tm = _tm()
+    cases = ((1025, 128), (2049, 33)) if map_name == "rec" else ((900, 128), (1500, 4), (2100, 40))
+    for n, d in cases:
+        X, pairs = inputs.points(n, d, dup_frac=0.02, seed=5100 + n + d + strip)
+        p = tm.Plan(n, 128, map_name, include_diag=False, flags=flags | tm.FLAG_STRIP(strip))
+        note("edm mfma strips", mode, map_name, flags, strip, n, d)
+        got = host(_edm_mfma(tm, p, X, mode))
+        assert (got >= 0).all()
+        if mode == 1:
+            _check_rows(X, got, list(range(n)), MFMA_TOL[mode])
+        else:
+            _check_rows_bf16(X, got, list(range(n)))
+        # and identical to one tile per workgroup (same arithmetic per tile)
+        q = tm.Plan(n, 128, map_name, include_diag=False, flags=flags | tm.FLAG_STRIP(0))
+        one = host(_edm_mfma(tm, q, X, mode))
+        assert (got.view(np.uint32) == one.view(np.uint32)).all()
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_edm_mfma_beyond_128_dims(mode):
+    """d above 128: the chunked kernel (row-major planes, 64 dimensions per
+    LDS chunk)."""
+    tm = _tm()
+    for n, d in ((300, 129), (700, 200)):
+        X, _ = inputs.points(n, d, dup_frac=0.02, seed=5300 + n + d)
+        p = tm.Plan(n, 128, "lambda", include_diag=False)
+        note("edm mfma wide", mode, n, d)
+        got = host(_edm_mfma(tm, p, X, mode))
+        if mode == 1:
+            _check_rows(X, got, list(range(n)), MFMA_TOL[mode])
+        else:
+            _check_rows_bf16(X, got, list(range(n)))
+
+
 def test_edm_mfma_exact_duplicates_are_zero():
     tm = _tm()
     n, d = 300, 64

@@ -97,10 +97,11 @@ constexpr int kColsumRows = 64;   // rows per block of the column-sum pass
 // Workspace of the MFMA modes (all offsets 256-byte aligned).
 //
 // Up to 128 dimensions (the strip kernel) the BF16 operands are stored in
-// MFMA fragment order, in groups of 32 points: for k-step s (16
-// dimensions), plane (hi, lo) and half h (dimensions 16 s + 8 h .. + 7), one
-// 16-byte vector per point,
-//   frag[((p / 32) * S * planes * 2 + (s * planes + plane) * 2 + h) * 32 + p % 32],
+// MFMA fragment order, in groups of 32 points: for plane q (k-step s and
+// part hi / lo: q = s * parts + part; then the norm step as a column
+// operand, q = KP = S * parts, and as a row operand, q = KP + 1) and half h
+// (dimensions 16 s + 8 h .. + 7), one 16-byte vector per point,
+//   frag[((p / 32) * (KP + 2) * 2 + q * 2 + h) * 32 + p % 32],
 // so that a wave's 64 lanes (32 points, two halves) read the operand of one
 // 32 x 32 x 16 MFMA as 1 KiB of contiguous memory, and all operands of 32
 // points form one contiguous block.  The dimensions are padded to S = 2, 4
@@ -117,6 +118,8 @@ struct EdmWs {
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 constexpr int kStripMaxDims = 128;
+// frag vectors per group of 32 points with KP operand planes
+__host__ __device__ constexpr int edm_group_vecs(int KP) { return (KP + 2) * 2 * 32; }
 
 static EdmWs edm_ws_layout(int64_t n, int64_t d)
 {
@@ -130,9 +133,11 @@ static EdmWs edm_ws_layout(int64_t n, int64_t d)
         w.dp = 16 * w.S;
         // rows of the last tile row reach 1 + 128 m <= n + 128
         w.np = (n + kEdmTile) / kEdmTile * kEdmTile + kEdmTile;
-        w.hi = o;  o = align256(o + (size_t)w.np * w.dp * 4);  // both planes
+        // fragments: up to 2 S operand planes and two norm-step planes of
+        // 32 bytes per point
+        w.hi = o;  o = align256(o + (size_t)w.np * (2 * w.S + 2) * 32);
         w.lo = w.hi;
-        w.norms = o; o = align256(o + (size_t)w.np * 4);
+        w.norms = w.hi;
     } else {
         w.S = 0;
         w.np = n;
@@ -615,74 +620,18 @@ static bool edm_mfma(const tri_plan *p, const EdmMfmaArgs &a, bool split, hipStr
 }
 
 // ---------------------------------------------------------------------------
-// Strip kernel of the MFMA modes (up to 128 dimensions).
-//
-// A workgroup (four waves) takes G consecutive tiles of the map (a strip:
-// consecutive omega for lambda, consecutive grid columns of one grid row for
-// BB, RB and REC), which mostly share their tile row.  The row block of a
-// tile row (128 points x all k-steps x both planes, 64 KiB at 128
-// dimensions) is staged in LDS once per change of tile row; wave w owns the
-// tile's columns 32 w .. 32 w + 31 for all 128 rows (four 32 x 32 MFMA
-// blocks) and holds its column points' operands for every k-step in
-// registers.  Those registers are a ring: as soon as the products of k-step
-// s are issued, the operand of k-step s of the next tile of the strip is
-// loaded in its place, so each tile's column operands arrive during the
-// previous tile.  Distances are stored straight from the MFMA layout: per
-// store, 32 lanes write 32 consecutive pairs of one row (128 bytes), and
-// the four waves of a tile, and the tiles of a strip, complete each other's
-// cache lines in L2.
-// ---------------------------------------------------------------------------
-
-// Pre-pass in fragment order: one thread per point p < np centres its
-// coordinates, splits them into BF16 hi and lo (hi only for single BF16),
-// and sums the norm of the rounded operands, hi.hi + 2 hi.lo, in dimension
-// order.  Points beyond n get zeros.
-template <bool SPLIT, int S>
-__global__ void __launch_bounds__(256) k_edm_frag(const float *x, int32_t n, int32_t d,
-                                                  int64_t ldx, int32_t np, const float *mean,
-                                                  bf16x8 *frag, float *norms)
-{
-    constexpr int P = SPLIT ? 2 : 1;
-    const int32_t p = blockIdx.x * 256 + threadIdx.x;
-    if (p >= np) return;
-    const bool live = p < n;
-    float acc = 0.f;
-#pragma unroll
-    for (int s = 0; s < S; ++s)
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            bf16x8 hv, lv;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int32_t k = 16 * s + 8 * h + e;
-                float c = 0.f;
-                if (live && k < d) c = x[(int64_t)p * ldx + k] - mean[k];
-                const __bf16 hb = (__bf16)c;
-                const float hf = (float)hb;
-                const __bf16 lb = (__bf16)(c - hf);
-                const float lf = (float)lb;
-                hv[e] = hb;
-                lv[e] = lb;
-                if (SPLIT) acc = __builtin_fmaf(hf, hf, __builtin_fmaf(2.f * hf, lf, acc));
-                else acc = __builtin_fmaf(hf, hf, acc);
-            }
-            const int64_t grp = (int64_t)(p >> 5) * (S * P * 2) * 32 + (p & 31);
-            frag[grp + ((s * P) * 2 + h) * 32] = hv;
-            if (SPLIT) frag[grp + ((s * P + 1) * 2 + h) * 32] = lv;
-        }
-    norms[p] = acc;
-}
-
-// ---------------------------------------------------------------------------
 // Line-aligned strip kernel of the MFMA modes (up to 128 dimensions).
 //
 // A workgroup (four waves) walks G consecutive tiles of the map (a strip,
 // see strip_first); wave w owns rows R0 + 32 w .. + 31 of every tile and
 // all of its 128 columns (four 32 x 32 MFMA blocks), so the wave's row
-// operands stay in registers while the strip stays in one tile row, and the
+// operands stay in registers while the strip stays in one tile row.  The
 // tile's column operands (128 points x all k-steps x both planes, 64 KiB at
-// 128 dimensions) are staged in LDS straight from global memory for all
-// four waves, the next tile's during this tile's stores.
+// 128 dimensions, plus the norm step) are staged in LDS straight from global
+// memory for all four waves, in two halves (column blocks 0, 1 and 2, 3):
+// each half of the next tile is loaded as soon as every wave has issued its
+// products over that half of this tile, so its loads are in flight for about
+// one tile.
 //
 // Stores: the condensed rows start at any word, and a store that covers
 // parts of two 128-byte lines costs the memory system about 1.6 times a
@@ -711,31 +660,58 @@ __device__ __forceinline__ void split3(float v, __bf16 &h, __bf16 &m, __bf16 &lo
     lo = (__bf16)(r1 - (float)m);
 }
 
-// Norm step of a row point (dimensions 0..5: -n_i / 2 in three parts, 1, 1,
-// 1) and of a column point (1, 1, 1, -n_j / 2 in three parts); lanes 32..63
-// hold dimensions 8..15, all zero.
-__device__ __forceinline__ bf16x8 ext_row(float ni, int l)
+// Pre-pass in fragment order: one thread per point p < np centres its
+// coordinates, splits them into BF16 hi and lo (hi only for single BF16),
+// and sums the norm of the rounded operands, hi.hi + 2 hi.lo, in dimension
+// order.  It then writes the two planes of the norm step: as a column
+// operand (dimensions 0..5: 1, 1, 1 and -n / 2 in three parts) and as a row
+// operand (the three parts, then 1, 1, 1); dimensions 8..15 are zero.
+// Points beyond n get zeros (their norm steps carry no norm).
+template <bool SPLIT, int S>
+__global__ void __launch_bounds__(256) k_edm_frag(const float *x, int32_t n, int32_t d,
+                                                  int64_t ldx, int32_t np, const float *mean,
+                                                  bf16x8 *frag)
 {
-    bf16x8 v{};
-    if (l < 32) {
-        __bf16 h, m, lo;
-        split3(-0.5f * ni, h, m, lo);
-        v[0] = h; v[1] = m; v[2] = lo;
-        v[3] = (__bf16)1.f; v[4] = (__bf16)1.f; v[5] = (__bf16)1.f;
-    }
-    return v;
-}
-
-__device__ __forceinline__ bf16x8 ext_col(float nj, int l)
-{
-    bf16x8 v{};
-    if (l < 32) {
-        __bf16 h, m, lo;
-        split3(-0.5f * nj, h, m, lo);
-        v[0] = (__bf16)1.f; v[1] = (__bf16)1.f; v[2] = (__bf16)1.f;
-        v[3] = h; v[4] = m; v[5] = lo;
-    }
-    return v;
+    constexpr int P = SPLIT ? 2 : 1;
+    constexpr int KP = S * P;
+    const int32_t p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= np) return;
+    const bool live = p < n;
+    const int64_t grp = (int64_t)(p >> 5) * edm_group_vecs(KP) + (p & 31);
+    float acc = 0.f;
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            bf16x8 hv, lv;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int32_t k = 16 * s + 8 * h + e;
+                float c = 0.f;
+                if (live && k < d) c = x[(int64_t)p * ldx + k] - mean[k];
+                const __bf16 hb = (__bf16)c;
+                const float hf = (float)hb;
+                const __bf16 lb = (__bf16)(c - hf);
+                const float lf = (float)lb;
+                hv[e] = hb;
+                lv[e] = lb;
+                if (SPLIT) acc = __builtin_fmaf(hf, hf, __builtin_fmaf(2.f * hf, lf, acc));
+                else acc = __builtin_fmaf(hf, hf, acc);
+            }
+            frag[grp + ((s * P) * 2 + h) * 32] = hv;
+            if (SPLIT) frag[grp + ((s * P + 1) * 2 + h) * 32] = lv;
+        }
+    __bf16 nh, nm, nl;
+    split3(-0.5f * acc, nh, nm, nl);
+    const __bf16 one = (__bf16)1.f;
+    bf16x8 col{}, row{};
+    col[0] = one; col[1] = one; col[2] = one; col[3] = nh; col[4] = nm; col[5] = nl;
+    row[0] = nh; row[1] = nm; row[2] = nl; row[3] = one; row[4] = one; row[5] = one;
+    if (!live) col = row = bf16x8{};
+    frag[grp + (KP * 2) * 32] = col;
+    frag[grp + (KP * 2 + 1) * 32] = bf16x8{};
+    frag[grp + ((KP + 1) * 2) * 32] = row;
+    frag[grp + ((KP + 1) * 2 + 1) * 32] = bf16x8{};
 }
 
 // The distance from an accumulator holding -d^2 / 2: d^2 = -2 acc exactly.
@@ -753,7 +729,6 @@ struct EdmLinesArgs {
     int64_t ldx;
     const float *x;
     const bf16x8 *frag;
-    const float *norms;
     float *out;
     float thr;  // fix-up threshold on d^2
 };
@@ -762,13 +737,13 @@ template <int MAP, bool SPLIT, int S>
 __global__ void __launch_bounds__(256, 2) k_edm_lines(EdmLinesArgs a)
 {
     constexpr int P = SPLIT ? 2 : 1;
-    constexpr int KP = S * P;                 // operand planes (k-step, hi / lo)
-    constexpr int kGroup = KP * 2 * 32;       // frag vectors per group of 32 points
-    // column operands of the tile: 16-byte vector (plane r, block c, lane) at
-    // (r 4 + c) 64 + lane; the column norms of block c at sN[c 64 + lane]
-    // (lanes 32..63 repeat lanes 0..31)
-    __shared__ bf16x8 sB[KP * 4 * 64];
-    __shared__ float sN[4 * 64];
+    constexpr int KP = S * P;                   // operand planes (k-step, hi / lo)
+    constexpr int kGroup = edm_group_vecs(KP);  // frag vectors per group of 32 points
+    // column operands of the tile, one array per half (blocks 2 h, 2 h + 1):
+    // 16-byte vector (plane p, block 2 h + e, lane) at (p 2 + e) 64 + lane,
+    // plane KP the norm step
+    __shared__ bf16x8 sB0[(KP + 1) * 2 * 64];
+    __shared__ bf16x8 sB1[(KP + 1) * 2 * 64];
 
     const int t = threadIdx.x, l = t & 63, lo = l & 31, hf = l >> 5;
     const int w = __builtin_amdgcn_readfirstlane(t >> 6);
@@ -784,10 +759,10 @@ __global__ void __launch_bounds__(256, 2) k_edm_lines(EdmLinesArgs a)
     bi = __builtin_amdgcn_readfirstlane(bi);
     bj = __builtin_amdgcn_readfirstlane(bj);
 
-    // the wave's row operands: row R0 + 32 w + (l & 31), half l >> 5
+    // the wave's row operands: row R0 + 32 w + (l & 31), half l >> 5, and
+    // its norm step
     bf16x8 A[S][P];
-    bf16x8 Ax;   // its norm step
-    float nrow = 0.f;
+    bf16x8 Ax;
     auto load_rows = [&](int32_t rbi) {
         const int32_t r0 = 1 + rbi * kEdmTile + 32 * w + lo;
         const bf16x8 *rowp = a.frag + (int64_t)(r0 >> 5) * kGroup + hf * 32 + (r0 & 31);
@@ -795,32 +770,34 @@ __global__ void __launch_bounds__(256, 2) k_edm_lines(EdmLinesArgs a)
         for (int s = 0; s < S; ++s)
 #pragma unroll
             for (int pl = 0; pl < P; ++pl) A[s][pl] = rowp[(s * P + pl) * 64];
-        nrow = a.norms[r0];
+        Ax = rowp[(KP + 1) * 64];
     };
-    // the tile's column operands into LDS: wave w stages column block w
-    // (32 points: each plane is 1 KiB of contiguous frag, one 16-byte load
-    // per lane landing in lane order) and its 32 column norms, with no
-    // register in between
-    auto stage_cols = [&](int32_t cbj) {
-        const bf16x8 *src = a.frag + (int64_t)(4 * cbj + w) * kGroup + l;
+    // one half of a tile's column operands into LDS, with no register in
+    // between: each plane of 32 points is 1 KiB of contiguous frag, one
+    // 16-byte load per lane landing in lane order.  Wave w loads block
+    // 2 h + (w & 1), the planes of parity w >> 1.
+    auto stage_half = [&](bf16x8 *dst, int32_t cbj, int h) {
+        const int e = w & 1;
+        const bf16x8 *src = a.frag + (int64_t)(4 * cbj + 2 * h + e) * kGroup + l;
 #pragma unroll
-        for (int r = 0; r < KP; ++r)
-            __builtin_amdgcn_global_load_lds(
-                (const __attribute__((address_space(1))) void *)(src + r * 64),
-                (__attribute__((address_space(3))) void *)(sB + (r * 4 + w) * 64), 16, 0, 0);
-        __builtin_amdgcn_global_load_lds(
-            (const __attribute__((address_space(1))) void *)(a.norms + cbj * kEdmTile + 32 * w + lo),
-            (__attribute__((address_space(3))) void *)(sN + w * 64), 4, 0, 0);
+        for (int q = 0; q < (KP + 2) / 2; ++q) {
+            const int p = 2 * q + (w >> 1);
+            if (p <= KP)
+                __builtin_amdgcn_global_load_lds(
+                    (const __attribute__((address_space(1))) void *)(src + p * 64),
+                    (__attribute__((address_space(3))) void *)(dst + (p * 2 + e) * 64), 16, 0, 0);
+        }
     };
 
     // The store geometry of a tile row, the same for all its tiles (their
     // first columns are multiples of 32 floats): for the row i of register r
-    // (this lane's half), offw[r] = 4 (rowoff(i) + lane - 32 wrap) + wrap,
-    // with rowoff(i) the offset of (i, 0) from row R0's start and wrap = 1 when
-    // this lane takes the block to the left in every line of the row (lane >=
-    // 32 - delta, delta the row's misalignment).  Line k of the tile at
-    // column CW then sits at orow + 4 CW + (offw & ~3) + 128 k.
+    // (this lane's half), bit r of wbits is set when this lane takes the
+    // block to the left in every line of the row (lane >= 32 - delta, delta
+    // the row's misalignment), and offw[r] = 4 (rowoff(i) + lane - 32 wrap),
+    // with rowoff(i) the offset of (i, 0) from row R0's start.  Line k of the
+    // tile at column CW then sits at orow + 4 CW + offw + 128 k.
     uint32_t offw[16];
+    uint32_t wbits = 0;
     char *orow = nullptr;
     int32_t R0 = 0;
     auto set_rows = [&](int32_t rbi) {
@@ -828,25 +805,27 @@ __global__ void __launch_bounds__(256, 2) k_edm_lines(EdmLinesArgs a)
         const uint64_t TR0 = (uint64_t)R0 * (uint64_t)(R0 - 1) / 2;
         orow = (char *)(a.out + TR0);
         const uint32_t rmod = (uint32_t)(TR0 & 31u) + amod;
+        wbits = 0;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const int32_t i = R0 + 32 * w + 8 * (r >> 2) + 4 * hf + (r & 3);
             const uint32_t ro = (uint32_t)((i - R0) * (i + R0 - 1)) / 2u;
             const uint32_t wrap = (uint32_t)(lo + (int32_t)((ro + rmod) & 31u) >= 32);
-            offw[r] = ((ro + (uint32_t)lo - 32u * wrap) << 2) | wrap;
+            offw[r] = (ro + (uint32_t)lo - 32u * wrap) << 2;
+            wbits |= wrap << r;
         }
     };
 
     load_rows(bi);
-    stage_cols(bj);
+    stage_half(sB0, bj, 0);
+    stage_half(sB1, bj, 1);
     set_rows(bi);
     __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
-    Ax = ext_row(nrow, l);
-    lds_barrier();
 
     f32x16 carry{};           // distances of the previous tile's block 3
     uint32_t carry_near = 0;  // which of them are near (bit r)
     bool carry_ok = false;    // the previous tile of the strip is the left neighbour
+    bool pfull = false;       // the previous tile was full (its 32 line 2, 3 stores issued)
     for (;;) {
         int32_t nbi = 0, nbj = 0;
         const int nk = strip_next<MAP>(a.g, a.sg, first, k + 1, nbi, nbj);
@@ -855,7 +834,9 @@ __global__ void __launch_bounds__(256, 2) k_edm_lines(EdmLinesArgs a)
         nbj = __builtin_amdgcn_readfirstlane(nbj);
 
         const int32_t CW = bj * kEdmTile;
-        const uint32_t cw4 = 4u * (uint32_t)CW;
+        char *const obt = orow + 4 * (int64_t)CW;  // the tile's row R0, column 0
+        // store of line k (byte offset 128 k) of the row of register r
+        auto st = [&](int r, uint32_t k128, float v) { *(float *)((obt + offw[r]) + k128) = v; };
         const bool tail_self = !(more && nbi == bi && nbj == bj + 1);
         const bool full = CW + kEdmTile - 1 < R0 && R0 + kEdmTile - 1 < n;
         // per-lane test of pair (row of register r, tile column jt), for
@@ -865,43 +846,71 @@ __global__ void __launch_bounds__(256, 2) k_edm_lines(EdmLinesArgs a)
             return i < n && CW + jt >= 0 && CW + jt < i;
         };
 
-        // Two passes of two column blocks each: acc[e] = rows x column
-        // block 2 pass + e (half the accumulators of the tile at a time).
         f32x16 mid{};          // distances of block 1 (line 2 takes its tail)
         uint64_t near = 0;     // bit c 16 + r: the square is below the threshold
         bool waited = false;
 #pragma unroll
         for (int pass = 0; pass < 2; ++pass) {
-            f32x16 acc[2];
+            bf16x8 *const sB = pass ? sB1 : sB0;
+            // This half's loads are complete in every wave.  They were issued
+            // a half tile of stores and loads ago: when the previous tile was
+            // full, at least 16 + 32 of its stores and KP / 2 loads of the
+            // other half are younger (the first half), or 32 of its stores and
+            // 16 of this tile's (the second half, when this tile is full too).
+            if (pass == 0) {
+                if (pfull) __builtin_amdgcn_s_waitcnt(waitcnt_vm(48 + KP / 2));
+                else __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
+            } else {
+                if (pfull && full) __builtin_amdgcn_s_waitcnt(waitcnt_vm(48));
+                else __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
+            }
+            lds_barrier();
+            // acc[e] = rows x column block 2 pass + e.  The column operands of
+            // k-step s are read from LDS kPf k-steps ahead of their products,
+            // so that the reads' latency hides behind the products in flight.
+            constexpr int kPf = SPLIT ? 2 : 4;
+            bf16x8 Bh[S][2], Bl[S][2];
+            auto read_b = [&](int s) {
 #pragma unroll
-            for (int e = 0; e < 2; ++e) {
+                for (int e = 0; e < 2; ++e) {
+                    Bh[s][e] = sB[((s * P) * 2 + e) * 64 + l];
+                    if constexpr (SPLIT) Bl[s][e] = sB[((s * P + 1) * 2 + e) * 64 + l];
+                }
+            };
+            f32x16 acc[2];
+            {
+                const bf16x8 X0 = sB[(KP * 2) * 64 + l], X1 = sB[(KP * 2 + 1) * 64 + l];
+#pragma unroll
+                for (int s = 0; s < kPf && s < S; ++s) read_b(s);
+                __builtin_amdgcn_sched_barrier(0);
                 const f32x16 z{};
-                acc[e] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                    Ax, ext_col(sN[(2 * pass + e) * 64 + l], l), z, 0, 0, 0);
+                acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ax, X0, z, 0, 0, 0);
+                acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ax, X1, z, 0, 0, 0);
             }
 #pragma unroll
             for (int s = 0; s < S; ++s) {
-                bf16x8 Bh[2], Bl[2];
-#pragma unroll
-                for (int e = 0; e < 2; ++e) {
-                    Bh[e] = sB[((s * P) * 4 + 2 * pass + e) * 64 + l];
-                    if constexpr (SPLIT) Bl[e] = sB[((s * P + 1) * 4 + 2 * pass + e) * 64 + l];
-                }
+                if (s + kPf < S) read_b(s + kPf);
+                __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int e = 0; e < 2; ++e)
-                    acc[e] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[s][0], Bh[e], acc[e], 0, 0, 0);
+                    acc[e] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[s][0], Bh[s][e], acc[e], 0, 0, 0);
                 if constexpr (SPLIT) {
 #pragma unroll
                     for (int e = 0; e < 2; ++e)
-                        acc[e] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[s][0], Bl[e], acc[e], 0, 0, 0);
+                        acc[e] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[s][0], Bl[s][e], acc[e], 0, 0, 0);
 #pragma unroll
                     for (int e = 0; e < 2; ++e)
-                        acc[e] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[s][P - 1], Bh[e], acc[e], 0, 0, 0);
+                        acc[e] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[s][P - 1], Bh[s][e], acc[e], 0, 0, 0);
                 }
+                __builtin_amdgcn_sched_barrier(0);
             }
-            // keep the scheduler from moving the stores' arithmetic into the
-            // products (it would hold it in registers there)
-            __builtin_amdgcn_sched_barrier(0);
+            // every wave's products over this half are issued (their LDS
+            // reads done): the next tile's half may overwrite it
+            lds_barrier();
+            if (more) {
+                if (pass == 0) stage_half(sB0, nbj, 0);
+                else stage_half(sB1, nbj, 1);
+            }
             {
                 float mx = acc[0][0];
 #pragma unroll
@@ -925,63 +934,73 @@ __global__ void __launch_bounds__(256, 2) k_edm_lines(EdmLinesArgs a)
                 for (int r = 0; r < 16; ++r) D[e][r] = dist_of(acc[e][r]);
 
             if (pass == 0) {
-                // line 0 (the carry's tail and block 0) and line 1 (blocks 0, 1)
+                // line 0 (the carry's tail and block 0) and line 1 (blocks 0, 1);
+                // the branches are uniform, each store one row at a time
+                if (full && carry_ok) {
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const bool wrap = offw[r] & 1u;
-                    const uint32_t off = (offw[r] & ~3u) + cw4;
-                    if (full) {
-                        if (carry_ok || !wrap) *(float *)(orow + off) = wrap ? carry[r] : D[0][r];
-                        *(float *)(orow + off + 128u) = wrap ? D[0][r] : D[1][r];
-                    } else {
-                        const int32_t jt = lo - 32 * (int32_t)wrap;
-                        if ((carry_ok || !wrap) && inside(r, jt))
-                            *(float *)(orow + off) = wrap ? carry[r] : D[0][r];
-                        if (inside(r, jt + 32)) *(float *)(orow + off + 128u) = wrap ? D[0][r] : D[1][r];
+                    for (int r = 0; r < 16; ++r) {
+                        const bool wrap = (wbits >> r) & 1u;
+                        st(r, 0u, wrap ? carry[r] : D[0][r]);
+                        st(r, 128u, wrap ? D[0][r] : D[1][r]);
+                        __builtin_amdgcn_sched_barrier(0);
                     }
-                    __builtin_amdgcn_sched_barrier(0);  // one row at a time
+                } else if (full) {
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const bool wrap = (wbits >> r) & 1u;
+                        if (!wrap) st(r, 0u, D[0][r]);
+                        st(r, 128u, wrap ? D[0][r] : D[1][r]);
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const bool wrap = (wbits >> r) & 1u;
+                        const int32_t jt = lo - 32 * (int32_t)wrap;
+                        if ((carry_ok || !wrap) && inside(r, jt)) st(r, 0u, wrap ? carry[r] : D[0][r]);
+                        if (inside(r, jt + 32)) st(r, 128u, wrap ? D[0][r] : D[1][r]);
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
                 }
                 mid = D[1];
                 __builtin_amdgcn_sched_barrier(0);
             } else {
-                lds_barrier();  // every wave is done with sB
                 // line 4: the tile's own tail (block 3, columns 128 - delta ..)
                 if (tail_self) {
 #pragma unroll
                     for (int r = 0; r < 16; ++r) {
-                        const uint32_t off = (offw[r] & ~3u) + cw4 + 512u;
-                        if ((offw[r] & 1u) && (full || inside(r, 96 + lo)))
-                            *(float *)(orow + off) = D[1][r];
+                        if (((wbits >> r) & 1u) && (full || inside(r, 96 + lo))) st(r, 512u, D[1][r]);
                         __builtin_amdgcn_sched_barrier(0);
                     }
                 }
-                // the next tile's operands, in flight during lines 2 and 3
-                if (more) stage_cols(nbj);
-                const bool reload = more && nbi != bi;
-                if (reload) {
+                if (more && nbi != bi) {
                     // a new tile row (once a strip, or where it crosses a row
                     // end): wait for its row operands here, so that the
                     // products never wait for a store
                     load_rows(nbi);
                     __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
                 }
-                // the 32 stores below stay after these loads (the wait for the
-                // loads counts them)
+                // the stores below stay after these loads (the waits for the
+                // loads count them)
                 asm volatile("" ::: "memory");
                 // lines 2 (blocks 1, 2) and 3 (blocks 2, 3)
+                if (full) {
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const bool wrap = offw[r] & 1u;
-                    const uint32_t off = (offw[r] & ~3u) + cw4;
-                    if (full) {
-                        *(float *)(orow + off + 256u) = wrap ? mid[r] : D[0][r];
-                        *(float *)(orow + off + 384u) = wrap ? D[0][r] : D[1][r];
-                    } else {
-                        const int32_t jt = lo - 32 * (int32_t)wrap;
-                        if (inside(r, jt + 64)) *(float *)(orow + off + 256u) = wrap ? mid[r] : D[0][r];
-                        if (inside(r, jt + 96)) *(float *)(orow + off + 384u) = wrap ? D[0][r] : D[1][r];
+                    for (int r = 0; r < 16; ++r) {
+                        const bool wrap = (wbits >> r) & 1u;
+                        st(r, 256u, wrap ? mid[r] : D[0][r]);
+                        st(r, 384u, wrap ? D[0][r] : D[1][r]);
+                        __builtin_amdgcn_sched_barrier(0);
                     }
-                    __builtin_amdgcn_sched_barrier(0);
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const bool wrap = (wbits >> r) & 1u;
+                        const int32_t jt = lo - 32 * (int32_t)wrap;
+                        if (inside(r, jt + 64)) st(r, 256u, wrap ? mid[r] : D[0][r]);
+                        if (inside(r, jt + 96)) st(r, 384u, wrap ? D[0][r] : D[1][r]);
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
                 }
                 // near-duplicates (rare): recompute directly in FP32 over the
                 // values just stored, the carried ones included
@@ -997,17 +1016,17 @@ __global__ void __launch_bounds__(256, 2) k_edm_lines(EdmLinesArgs a)
                             r = b & 15;
                             jt = 32 * (b >> 4) + lo;
                             // block 3's tail goes to the next tile unless this tile stores it
-                            if ((b >> 4) == 3 && (offw[r] & 1u) && !tail_self) continue;
+                            if ((b >> 4) == 3 && ((wbits >> r) & 1u) && !tail_self) continue;
                         } else {
                             r = __builtin_ctz(mc);
                             mc &= mc - 1;
-                            if (!(offw[r] & 1u)) continue;  // not a carried value
+                            if (!((wbits >> r) & 1u)) continue;  // not a carried value
                             jt = lo - 32;
                         }
                         if (!inside(r, jt)) continue;
                         const int32_t i = R0 + 32 * w + 8 * (r >> 2) + 4 * hf + (r & 3);
                         const uint32_t ro = (uint32_t)((i - R0) * (i + R0 - 1)) / 2u;
-                        *(float *)(orow + 4u * (ro + (uint32_t)(CW + jt))) =
+                        *(float *)(obt + 4u * (ro + (uint32_t)jt)) =
                             __builtin_amdgcn_sqrtf(direct_d2(a.x, a.ldx, a.d, i, CW + jt));
                     }
                     __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
@@ -1016,23 +1035,14 @@ __global__ void __launch_bounds__(256, 2) k_edm_lines(EdmLinesArgs a)
                 carry = D[1];
             }
         }
-        const bool reload = more && nbi != bi;
         // the carry for the next tile (block 3's distances, set above)
         carry_near = (uint32_t)(near >> 48);
         carry_ok = !tail_self;
-
-        // Every load issued so far is complete here; in a full tile only the
-        // 32 stores of lines 2 and 3 may still be in flight.
-        if (!waited) {
-            if (full) __builtin_amdgcn_s_waitcnt(waitcnt_vm(32));
-            else __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
-        }
-        if (reload) {
-            Ax = ext_row(nrow, l);
-            set_rows(nbi);
-        }
-        lds_barrier();
+        // a wait in this tile (fix-up) completed everything; else the next
+        // tile counts this tile's unconditional stores
+        pfull = full && !waited;
         if (!more) break;
+        if (nbi != bi) set_rows(nbi);
         k = nk;
         bi = nbi;
         bj = nbj;
@@ -1087,13 +1097,13 @@ static bool edm_lines(const tri_plan *p, const EdmLinesArgs &a, int S, hipStream
 
 template <bool SPLIT>
 static void edm_frag_launch(int S, const float *x, int32_t n, int32_t d, int64_t ldx, int32_t np,
-                            const float *mean, bf16x8 *frag, float *norms, hipStream_t s)
+                            const float *mean, bf16x8 *frag, hipStream_t s)
 {
     const dim3 grid((uint32_t)((np + 255) / 256));
     switch (S) {
-    case 2: k_edm_frag<SPLIT, 2><<<grid, 256, 0, s>>>(x, n, d, ldx, np, mean, frag, norms); break;
-    case 4: k_edm_frag<SPLIT, 4><<<grid, 256, 0, s>>>(x, n, d, ldx, np, mean, frag, norms); break;
-    case 8: k_edm_frag<SPLIT, 8><<<grid, 256, 0, s>>>(x, n, d, ldx, np, mean, frag, norms); break;
+    case 2: k_edm_frag<SPLIT, 2><<<grid, 256, 0, s>>>(x, n, d, ldx, np, mean, frag); break;
+    case 4: k_edm_frag<SPLIT, 4><<<grid, 256, 0, s>>>(x, n, d, ldx, np, mean, frag); break;
+    case 8: k_edm_frag<SPLIT, 8><<<grid, 256, 0, s>>>(x, n, d, ldx, np, mean, frag); break;
     }
 }
 
@@ -1184,10 +1194,10 @@ static tri_status edm_run(const tri_plan *p, const float *x, int64_t d, int64_t 
     if (L.S) {
         bf16x8 *frag = (bf16x8 *)(w + L.hi);
         const int32_t np = (int32_t)L.np;
-        if (split) edm_frag_launch<true>(L.S, x, n, dd, ldx, np, mean, frag, norms, s);
-        else edm_frag_launch<false>(L.S, x, n, dd, ldx, np, mean, frag, norms, s);
+        if (split) edm_frag_launch<true>(L.S, x, n, dd, ldx, np, mean, frag, s);
+        else edm_frag_launch<false>(L.S, x, n, dd, ldx, np, mean, frag, s);
         TRI_HIP(hipGetLastError());
-        EdmLinesArgs a{plan_tile_grid(p), StripGrid{}, n, dd, ldx, x, frag, norms, out, fixup_thr};
+        EdmLinesArgs a{plan_tile_grid(p), StripGrid{}, n, dd, ldx, x, frag, out, fixup_thr};
         const bool ok = split ? edm_lines<true>(p, a, L.S, s) : edm_lines<false>(p, a, L.S, s);
         if (!ok) return fail(TRI_E_UNSUPPORTED, "tri_edm: map");
         TRI_HIP(hipGetLastError());

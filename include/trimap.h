@@ -73,6 +73,12 @@ enum {
  * strips ignore them. */
 #define TRI_FLAG_STRIP_MASK 0xF00u
 #define TRI_FLAG_STRIP(k) ((uint32_t)((k) + 1) << 8)
+/* Plan flag for the same kernels under lambda: strips aligned to tile rows
+ * (strip c of tile row i holds the row's tiles c G .. c G + G - 1) and
+ * taken column by column (strip c of every row before strip c + 1), so that
+ * the workgroups running together share their column tiles.  Without it a
+ * strip is G consecutive omega in row order (it may cross a row end). */
+#define TRI_FLAG_STRIP_COLS 0x1000u
 
 /* Elementwise bodies. */
 enum {

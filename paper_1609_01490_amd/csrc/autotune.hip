@@ -121,6 +121,11 @@ static std::vector<Candidate> candidates(int workload, int64_t n)
             }
         }
     if (utm) c.push_back({32, TRI_MAP_UTM, 0u});
+    if (workload == TRI_TUNE_EDM_BF16X3)  // column-major strips of 16 and 32 tiles
+        for (uint32_t st : {(uint32_t)TRI_FLAG_STRIP(4), (uint32_t)TRI_FLAG_STRIP(5)}) {
+            c.push_back({128, TRI_MAP_LAMBDA, (uint32_t)TRI_FLAG_STRIP_COLS | st});
+            c.push_back({128, TRI_MAP_LAMBDA, (uint32_t)TRI_FLAG_STRIP_COLS | TRI_FLAG_XCD_SWIZZLE | st});
+        }
     if (workload == TRI_TUNE_LIFE)  // temporal blocking (tiles 16..64)
         for (int t : {16, 32, 64}) {
             c.push_back({t, TRI_MAP_BB, (uint32_t)TRI_FLAG_LIFE_TEMPORAL});

@@ -825,7 +825,14 @@ __global__ void __launch_bounds__(256, 2) k_edm_lines(EdmLinesArgs a)
     f32x16 carry{};           // distances of the previous tile's block 3
     uint32_t carry_near = 0;  // which of them are near (bit r)
     bool carry_ok = false;    // the previous tile of the strip is the left neighbour
-    bool pfull = false;       // the previous tile was full (its 32 line 2, 3 stores issued)
+    // Stores of whole lines are deferred into the next pass's products, a few
+    // per k-step, so that every wave writes while its products run: V0, V1
+    // hold two lines of the 16 rows, stored at vbase + offw + k0 / k1.
+    f32x16 V0{}, V1{};
+    bool vpend = false;       // V0, V1 hold lines 2, 3 of the previous tile
+    char *vbase = nullptr;
+    bool pfull = false;       // the previous tile was full and waited for nothing
+    bool pcok = false;        // ... and deferred its line 0
     for (;;) {
         int32_t nbi = 0, nbj = 0;
         const int nk = strip_next<MAP>(a.g, a.sg, first, k + 1, nbi, nbj);
@@ -853,22 +860,31 @@ __global__ void __launch_bounds__(256, 2) k_edm_lines(EdmLinesArgs a)
         for (int pass = 0; pass < 2; ++pass) {
             bf16x8 *const sB = pass ? sB1 : sB0;
             // This half's loads are complete in every wave.  They were issued
-            // a half tile of stores and loads ago: when the previous tile was
-            // full, at least 16 + 32 of its stores and KP / 2 loads of the
-            // other half are younger (the first half), or 32 of its stores and
-            // 16 of this tile's (the second half, when this tile is full too).
+            // a half tile ago; younger, when the previous tile was full: its
+            // 16 line 1 stores (and 16 of line 0 when deferred) and KP / 2
+            // loads of the other half (the first half), or its 32 stores of
+            // lines 2 and 3 (the second half).
             if (pass == 0) {
-                if (pfull) __builtin_amdgcn_s_waitcnt(waitcnt_vm(48 + KP / 2));
+                if (pfull && pcok) __builtin_amdgcn_s_waitcnt(waitcnt_vm(32 + KP / 2));
+                else if (pfull) __builtin_amdgcn_s_waitcnt(waitcnt_vm(16 + KP / 2));
                 else __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
             } else {
-                if (pfull && full) __builtin_amdgcn_s_waitcnt(waitcnt_vm(48));
+                if (pfull) __builtin_amdgcn_s_waitcnt(waitcnt_vm(32));
                 else __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
             }
             lds_barrier();
+            // the deferred lines stored during this pass: lines 2, 3 of the
+            // previous tile (pass 0) or lines 0 (when the carry is there)
+            // and 1 of this tile (pass 1)
+            const bool sv = pass ? full : vpend;
+            const bool sv0 = pass ? (full && carry_ok) : vpend;
+            char *const sbase = pass ? obt : vbase;
+            const uint32_t k0 = pass ? 0u : 256u, k1 = pass ? 128u : 384u;
             // acc[e] = rows x column block 2 pass + e.  The column operands of
             // k-step s are read from LDS kPf k-steps ahead of their products,
             // so that the reads' latency hides behind the products in flight.
-            constexpr int kPf = SPLIT ? 2 : 4;
+            constexpr int kPf = SPLIT ? 1 : 4;
+            constexpr int kRows = 16 / S;  // deferred rows stored per k-step
             bf16x8 Bh[S][2], Bl[S][2];
             auto read_b = [&](int s) {
 #pragma unroll
@@ -890,6 +906,14 @@ __global__ void __launch_bounds__(256, 2) k_edm_lines(EdmLinesArgs a)
 #pragma unroll
             for (int s = 0; s < S; ++s) {
                 if (s + kPf < S) read_b(s + kPf);
+                if (sv) {
+#pragma unroll
+                    for (int q = 0; q < kRows; ++q) {
+                        const int r = s * kRows + q;
+                        if (sv0) *(float *)((sbase + offw[r]) + k0) = V0[r];
+                        *(float *)((sbase + offw[r]) + k1) = V1[r];
+                    }
+                }
                 __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int e = 0; e < 2; ++e)
@@ -934,23 +958,22 @@ __global__ void __launch_bounds__(256, 2) k_edm_lines(EdmLinesArgs a)
                 for (int r = 0; r < 16; ++r) D[e][r] = dist_of(acc[e][r]);
 
             if (pass == 0) {
-                // line 0 (the carry's tail and block 0) and line 1 (blocks 0, 1);
-                // the branches are uniform, each store one row at a time
-                if (full && carry_ok) {
+                // line 0 (the carry's tail and block 0) and line 1 (blocks 0,
+                // 1): deferred in a full tile (line 0 stored now when there is
+                // no carry, by the lanes that do not take it)
+                if (full) {
 #pragma unroll
                     for (int r = 0; r < 16; ++r) {
                         const bool wrap = (wbits >> r) & 1u;
-                        st(r, 0u, wrap ? carry[r] : D[0][r]);
-                        st(r, 128u, wrap ? D[0][r] : D[1][r]);
-                        __builtin_amdgcn_sched_barrier(0);
+                        V0[r] = wrap ? carry[r] : D[0][r];
+                        V1[r] = wrap ? D[0][r] : D[1][r];
                     }
-                } else if (full) {
+                    if (!carry_ok) {
 #pragma unroll
-                    for (int r = 0; r < 16; ++r) {
-                        const bool wrap = (wbits >> r) & 1u;
-                        if (!wrap) st(r, 0u, D[0][r]);
-                        st(r, 128u, wrap ? D[0][r] : D[1][r]);
-                        __builtin_amdgcn_sched_barrier(0);
+                        for (int r = 0; r < 16; ++r) {
+                            if (!((wbits >> r) & 1u)) st(r, 0u, V0[r]);
+                            __builtin_amdgcn_sched_barrier(0);
+                        }
                     }
                 } else {
 #pragma unroll
@@ -983,14 +1006,25 @@ __global__ void __launch_bounds__(256, 2) k_edm_lines(EdmLinesArgs a)
                 // the stores below stay after these loads (the waits for the
                 // loads count them)
                 asm volatile("" ::: "memory");
-                // lines 2 (blocks 1, 2) and 3 (blocks 2, 3)
+                const bool anynear = __any((near | (carry_ok ? carry_near : 0u)) != 0);
+                // lines 2 (blocks 1, 2) and 3 (blocks 2, 3): deferred into the
+                // next tile's first pass when it continues this tile row and
+                // no near square waits for its fix-up
+                const bool defer = full && more && nbi == bi && !anynear;
                 if (full) {
 #pragma unroll
                     for (int r = 0; r < 16; ++r) {
                         const bool wrap = (wbits >> r) & 1u;
-                        st(r, 256u, wrap ? mid[r] : D[0][r]);
-                        st(r, 384u, wrap ? D[0][r] : D[1][r]);
-                        __builtin_amdgcn_sched_barrier(0);
+                        V0[r] = wrap ? mid[r] : D[0][r];
+                        V1[r] = wrap ? D[0][r] : D[1][r];
+                    }
+                    if (!defer) {
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) {
+                            st(r, 256u, V0[r]);
+                            st(r, 384u, V1[r]);
+                            __builtin_amdgcn_sched_barrier(0);
+                        }
                     }
                 } else {
 #pragma unroll
@@ -1002,9 +1036,11 @@ __global__ void __launch_bounds__(256, 2) k_edm_lines(EdmLinesArgs a)
                         __builtin_amdgcn_sched_barrier(0);
                     }
                 }
+                vpend = defer;
+                vbase = obt;
                 // near-duplicates (rare): recompute directly in FP32 over the
                 // values just stored, the carried ones included
-                if (__any((near | (carry_ok ? carry_near : 0u)) != 0)) {
+                if (anynear) {
                     // bits 0..63: this tile's squares; then the carried ones
                     uint64_t mk = near;
                     uint32_t mc = carry_ok ? carry_near : 0u;
@@ -1037,10 +1073,11 @@ __global__ void __launch_bounds__(256, 2) k_edm_lines(EdmLinesArgs a)
         }
         // the carry for the next tile (block 3's distances, set above)
         carry_near = (uint32_t)(near >> 48);
-        carry_ok = !tail_self;
         // a wait in this tile (fix-up) completed everything; else the next
         // tile counts this tile's unconditional stores
         pfull = full && !waited;
+        pcok = carry_ok;
+        carry_ok = !tail_self;
         if (!more) break;
         if (nbi != bi) set_rows(nbi);
         k = nk;
@@ -1068,7 +1105,7 @@ static void edm_lines_launch(const tri_plan *p, const EdmLinesArgs &a0, hipStrea
 {
     EdmLinesArgs a = a0;
     dim3 grid;
-    a.sg = strip_grid(MAP, a.g.T, p->gx, p->gy, strip_len(p), kEdmStripGroup, grid);
+    a.sg = strip_grid(MAP, a.g.m, a.g.flags, a.g.T, p->gx, p->gy, strip_len(p), kEdmStripGroup, grid);
     k_edm_lines<MAP, SPLIT, S><<<grid, 256, 0, s>>>(a);
 }
 

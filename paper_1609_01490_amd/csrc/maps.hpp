@@ -257,6 +257,17 @@ __device__ __forceinline__ bool tile_of_block(const TileGrid &g, int32_t &bi, in
 // the XCD swizzle, on one XCD and one L2).  The dispatch order and swizzle
 // of lambda act on workgroups.  Every tile is still mapped on its own.
 // ---------------------------------------------------------------------------
+//
+// Column-major strips (TRI_FLAG_STRIP_COLS, lambda, K = 1): the strips are
+// aligned to tile rows (strip c of row i holds omega T_i + c G .. up to the
+// row's end) and workgroup s takes them column by column: strip column c
+// (rows c G .. m - 1, m - c G strips) before c + 1.  With the XCD swizzle
+// the workgroups resident on one XCD then walk the same columns of many
+// rows, so a kernel that stages column operands per tile finds them in L2.
+// Strip s lies in column c with P(c) <= s < P(c + 1), P(c) = c m - G c (c -
+// 1) / 2 (the strips of the columns before c): the root of the quadratic,
+// corrected by integer steps, as lambda finds its row.
+// ---------------------------------------------------------------------------
 struct StripGrid {
     uint32_t strips;  // lambda: workgroups in the launch (gridDim.x)
     int32_t G;        // tiles per workgroup
@@ -264,13 +275,37 @@ struct StripGrid {
     int32_t gx;       // BB / RB / REC: columns of the map's grid
 };
 
-// Launch grid of a strip kernel for a plan's map and its grid (gx, gy).
-__host__ __forceinline__ StripGrid strip_grid(int map, uint64_t T, uint32_t gx, uint32_t gy,
-                                              int32_t G, int32_t K, dim3 &grid)
+__host__ __device__ __forceinline__ uint64_t strip_cols_prefix(uint32_t c, uint32_t m, uint32_t G)
+{
+    return c ? (uint64_t)c * m - (uint64_t)G * c * (c - 1) / 2 : 0;
+}
+
+// First omega of column-major strip s (s below the strip count).
+__device__ __forceinline__ uint32_t strip_cols_first(uint32_t s, uint32_t m, uint32_t G)
+{
+    const double a = (double)m + 0.5 * (double)G;
+    const double disc = a * a - 2.0 * (double)G * (double)s;
+    const double c0 = (a - __builtin_sqrt(disc > 0.0 ? disc : 0.0)) / (double)G;
+    uint32_t c = c0 > 0.0 ? (uint32_t)c0 : 0u;
+    while (c > 0 && strip_cols_prefix(c, m, G) > s) --c;
+    while (strip_cols_prefix(c + 1, m, G) <= s) ++c;
+    const uint32_t i = c * G + (uint32_t)(s - strip_cols_prefix(c, m, G));
+    return (uint32_t)((uint64_t)i * (i + 1) / 2) + c * G;
+}
+
+// Launch grid of a strip kernel for a plan's map, tile grid (m tiles a side,
+// flags) and map grid (gx, gy).
+__host__ __forceinline__ StripGrid strip_grid(int map, int32_t m, uint32_t flags, uint64_t T,
+                                              uint32_t gx, uint32_t gy, int32_t G, int32_t K,
+                                              dim3 &grid)
 {
     StripGrid s{0u, G, K, (int32_t)gx};
     const uint64_t span = (uint64_t)G * (uint64_t)K;  // tile numbers per group
-    if (map == TRI_MAP_LAMBDA) {
+    if (map == TRI_MAP_LAMBDA && (flags & TRI_FLAG_STRIP_COLS)) {
+        s.K = 1;
+        s.strips = (uint32_t)strip_cols_prefix((uint32_t)((m + G - 1) / G), (uint32_t)m, (uint32_t)G);
+        grid = dim3(s.strips, 1);
+    } else if (map == TRI_MAP_LAMBDA) {
         s.strips = (uint32_t)((T + span - 1) / span * (uint64_t)K);
         grid = dim3(s.strips, 1);
     } else {
@@ -295,6 +330,7 @@ __device__ __forceinline__ uint32_t strip_first(const TileGrid &g, const StripGr
         uint32_t G2 = grp;
         if (g.flags & TRI_FLAG_ORDER_REVERSE) G2 = ng - 1 - grp;
         else if (g.flags & TRI_FLAG_ORDER_PAIRS) G2 = (grp & 1) ? ng - 1 - (grp >> 1) : (grp >> 1);
+        if (g.flags & TRI_FLAG_STRIP_COLS) return strip_cols_first(G2, (uint32_t)g.m, (uint32_t)sg.G);
         return G2 * K * (uint32_t)sg.G + k;
     } else {
         const uint32_t K = (uint32_t)sg.K;
@@ -314,6 +350,9 @@ __device__ __forceinline__ bool strip_tile(const TileGrid &g, const StripGrid &s
         if (w >= (uint32_t)g.T) return false;
         if (g.T <= (1ull << 24)) lambda_tile_24(w, bi, bj);
         else lambda_tile_32(w, bi, bj);
+        // a column-major strip ends with its row: tile k of the strip has
+        // column bj0 + k >= k, the next row's tiles columns below k
+        if ((g.flags & TRI_FLAG_STRIP_COLS) && bj < k) return false;
     } else {
         const int32_t bx = (int32_t)first + k * sg.K;
         if (bx >= sg.gx) return false;

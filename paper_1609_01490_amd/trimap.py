@@ -28,6 +28,9 @@ FLAG_STRIP_MASK = 0xF00
 def FLAG_STRIP(k: int) -> int:
     """Plan flag: strips of 2^k consecutive tiles per workgroup (k = 0..5)."""
     return (k + 1) << 8
+
+
+FLAG_STRIP_COLS = 0x1000  # lambda strips aligned to tile rows, taken column by column
 OP_XORMUL_I32, OP_AXPYT_F32, OP_EDM4_F32 = 0, 1, 2
 EDM_FP32, EDM_BF16X3, EDM_BF16 = 0, 1, 2
 EDM_NOALLOC_SCRATCH_BYTES = 16 << 20

@@ -210,6 +210,36 @@ def bench_elementwise(tm, torch, args, timer):
     return n, E, res, cpu, table
 
 
+def named_tiles(table, E, headline_GBps):
+    """Tiles 16 and 32 (the tiles the elementwise workload names), from the
+    autotuner's table: for each map its fastest candidate with one tile per
+    workgroup (flags without strip bits) and with strips (TRI_FLAG_STRIP),
+    HBM GB/s (12 B per cell), I = t_BB / t_map within each form, and
+    lambda's bandwidth over the headline launch's."""
+    out = {}
+    for t in (16, 32):
+        row = {}
+        for form, want_strip in (("per_tile", False), ("strips", True)):
+            best = {}
+            for c in table:
+                if c["tile"] != t or bool(c["flags"] & 0xF00) != want_strip:
+                    continue
+                if c["map"] not in best or c["ms"] < best[c["map"]]["ms"]:
+                    best[c["map"]] = c
+            if not best:
+                continue
+            ent = {mp: {"ms": round(c["ms"], 4), "flags": c["flags"],
+                        "GBps": round(12 * E / (c["ms"] * 1e-3) / 1e9, 1)} for mp, c in best.items()}
+            if "bb" in best:
+                for mp, c in best.items():
+                    ent[mp]["I_vs_bb"] = round(best["bb"]["ms"] / c["ms"], 4)
+            if "lambda" in best:
+                ent["lambda_vs_headline_bw"] = round(ent["lambda"]["GBps"] / headline_GBps, 4)
+            row[form] = ent
+        out[f"t{t}"] = row
+    return out
+
+
 def bench_probes(tm, torch, timer, c, x, y):
     """The bandwidth a plain streaming kernel reaches for each access mix
     (read, two reads and one write, write, copy) over the same 4 GiB
@@ -741,7 +771,8 @@ def main():
              "I_lambda_vs_bb_elementwise": round(res["bb"][0] / ms, 4),
              "bb_ms": round(res["bb"][0], 4), "bb_tile": res["bb"][1], "src_digest": digest,
              "elementwise_ms_by_map_tile": {f"{c['map']}/t{c['tile']}/f{c['flags']}":
-                                            round(c["ms"], 4) for c in table}}
+                                            round(c["ms"], 4) for c in table},
+             "named_tiles": named_tiles(table, E, achieved)}
     if not args.no_extra:
         for name, fn in (("int32_n2048", lambda: bench_int_elementwise(tm, torch, timer)),
                          ("life_n16384", lambda: bench_life(tm, torch, timer)),

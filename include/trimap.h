@@ -79,6 +79,11 @@ enum {
  * the workgroups running together share their column tiles.  Without it a
  * strip is G consecutive omega in row order (it may cross a row end). */
 #define TRI_FLAG_STRIP_COLS 0x1000u
+/* Plan flag for the same kernels under lambda: strips aligned to tile rows
+ * as with TRI_FLAG_STRIP_COLS, taken row by row (every strip of tile row i
+ * before row i + 1), so that each strip's first tile column is a multiple
+ * of G.  TRI_FLAG_STRIP_COLS takes precedence. */
+#define TRI_FLAG_STRIP_ALIGN 0x2000u
 
 /* Elementwise bodies. */
 enum {

@@ -121,6 +121,16 @@ static std::vector<Candidate> candidates(int workload, int64_t n)
             }
         }
     if (utm) c.push_back({32, TRI_MAP_UTM, 0u});
+    if (workload == TRI_TUNE_ELEMENTWISE_F32)  // strips of 4, 8 and 16 tiles at tiles 16, 32
+        for (int t : {16, 32})
+            for (uint32_t st : {(uint32_t)TRI_FLAG_STRIP(2), (uint32_t)TRI_FLAG_STRIP(3),
+                                (uint32_t)TRI_FLAG_STRIP(4)}) {
+                for (int m : maps) c.push_back({t, m, st});
+                c.push_back({t, TRI_MAP_LAMBDA, st | (uint32_t)TRI_FLAG_ORDER_PAIRS});
+                c.push_back({t, TRI_MAP_LAMBDA, st | (uint32_t)TRI_FLAG_XCD_SWIZZLE});
+                c.push_back({t, TRI_MAP_LAMBDA, st | (uint32_t)TRI_FLAG_STRIP_ALIGN});
+                c.push_back({t, TRI_MAP_LAMBDA, st | (uint32_t)(TRI_FLAG_STRIP_ALIGN | TRI_FLAG_ORDER_PAIRS)});
+            }
     if (workload == TRI_TUNE_EDM_BF16X3)  // column-major strips of 16 and 32 tiles
         for (uint32_t st : {(uint32_t)TRI_FLAG_STRIP(4), (uint32_t)TRI_FLAG_STRIP(5)}) {
             c.push_back({128, TRI_MAP_LAMBDA, (uint32_t)TRI_FLAG_STRIP_COLS | st});

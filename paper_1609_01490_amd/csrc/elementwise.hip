@@ -140,6 +140,226 @@ __global__ void __launch_bounds__((ElemShape<TILE, VECTOR>::NT)) k_axpyt(ElemArg
     }
 }
 
+// Strip form of AXPYT for tiles 16 and 32 (plans with TRI_FLAG_STRIP): a
+// workgroup of four waves walks G consecutive tiles of the map (strip_first
+// and strip_tile; every tile still mapped on its own), wave w taking tiles
+// w, w + 4, w + 8, ... of the strip, so that the four waves work on adjacent
+// tiles and one dispatch serves G tiles instead of one.  A wave moves a
+// whole tile by itself: 16-byte vectors, rows per pass 64 / (TILE / 4), and
+// its own transpose buffer in LDS (the LDS operations of one wave execute in
+// order, so a wave needs no barrier between its tiles).  The loads of the
+// wave's next tile are issued before the current tile's transpose and
+// stores.  Same arithmetic and operation order as k_axpyt.
+template <int MAP, int TILE>
+__global__ void __launch_bounds__(256) k_axpyt_strip(ElemArgs p, StripGrid sg)
+{
+    constexpr int VPR = TILE / 4, RPP = 64 / VPR, PASSES = TILE / RPP;
+    static_assert(RPP * PASSES == TILE, "tile shape");
+    __shared__ float ysh[4][TILE][TILE + 1];
+    const int l = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    float (*ys)[TILE + 1] = ysh[w];
+    const int tr = l / VPR, tc = (l % VPR) * 4;
+    const int32_t n = p.n;
+    const int64_t ld = p.ld;
+    const float *X = (const float *)p.x;
+    const float *Y = (const float *)p.y;
+    float *C = (float *)p.c;
+    const float a = p.a;
+    const int32_t cmax = (int32_t)(ld - 4);  // last column start of a vector
+    const uint32_t first = strip_first<MAP>(p.g, sg);
+
+    // the wave's next tile at or after strip index k (k >= G: none)
+    auto next = [&](int k, int32_t &bi, int32_t &bj) {
+        for (; k < sg.G; k += 4)
+            if (strip_tile<MAP>(p.g, sg, first, k, bi, bj)) break;
+        bi = __builtin_amdgcn_readfirstlane(bi);
+        bj = __builtin_amdgcn_readfirstlane(bj);
+        return k;
+    };
+    f4 xv[PASSES], yv[PASSES];
+    // every load unconditional; addresses clamped into the matrices on
+    // tiles that cross the diagonal or the last row (values never stored)
+    auto load = [&](int32_t bi, int32_t bj) {
+        const int32_t i0 = bi * TILE, j0 = bj * TILE;
+        const bool full = (bj < bi) && (i0 + TILE <= n);
+#pragma unroll
+        for (int ps = 0; ps < PASSES; ++ps) {
+            const int r = tr + ps * RPP;
+            int32_t i = i0 + r, jc = j0 + tc;
+            if (!full) {
+                i = i < n ? i : n - 1;
+                jc = jc < cmax ? jc : cmax;
+            }
+            xv[ps] = __builtin_nontemporal_load((const f4 *)(X + (int64_t)i * ld + jc));
+        }
+#pragma unroll
+        for (int ps = 0; ps < PASSES; ++ps) {
+            const int r = tr + ps * RPP;
+            int32_t jr = j0 + r, ic = i0 + tc;
+            if (!full) {
+                jr = jr < n ? jr : n - 1;
+                ic = ic < cmax ? ic : cmax;
+            }
+            yv[ps] = __builtin_nontemporal_load((const f4 *)(Y + (int64_t)jr * ld + ic));
+        }
+    };
+
+    int32_t bi = 0, bj = 0;
+    int k = next(w, bi, bj);
+    if (k >= sg.G) return;
+    load(bi, bj);
+    while (k < sg.G) {
+        // this tile's operands into the transpose buffer and registers
+#pragma unroll
+        for (int ps = 0; ps < PASSES; ++ps) {
+            const int r = tr + ps * RPP;
+            ys[r][tc + 0] = yv[ps].x;
+            ys[r][tc + 1] = yv[ps].y;
+            ys[r][tc + 2] = yv[ps].z;
+            ys[r][tc + 3] = yv[ps].w;
+        }
+        f4 xc[PASSES];
+#pragma unroll
+        for (int ps = 0; ps < PASSES; ++ps) xc[ps] = xv[ps];
+        const int32_t i0 = bi * TILE, j0 = bj * TILE;
+        const bool full = (bj < bi) && (i0 + TILE <= n);
+        // the next tile's loads, in flight during this tile's stores
+        int32_t nbi = 0, nbj = 0;
+        const int nk = next(k + 4, nbi, nbj);
+        if (nk < sg.G) load(nbi, nbj);
+#pragma unroll
+        for (int ps = 0; ps < PASSES; ++ps) {
+            const int r = tr + ps * RPP;
+            const int32_t i = i0 + r, jc = j0 + tc;
+            if (!full && (i >= n || jc > i)) continue;
+            float *crow = C + (int64_t)i * ld + jc;
+            f4 o;
+            o.x = __fadd_rn(__fmul_rn(a, xc[ps].x), ys[tc + 0][r]);
+            o.y = __fadd_rn(__fmul_rn(a, xc[ps].y), ys[tc + 1][r]);
+            o.z = __fadd_rn(__fmul_rn(a, xc[ps].z), ys[tc + 2][r]);
+            o.w = __fadd_rn(__fmul_rn(a, xc[ps].w), ys[tc + 3][r]);
+            if (full || jc + 3 <= i) {
+                __builtin_nontemporal_store(o, (f4 *)crow);
+            } else {  // the vector straddles the diagonal
+                crow[0] = o.x;
+                if (jc + 1 <= i) crow[1] = o.y;
+                if (jc + 2 <= i) crow[2] = o.z;
+            }
+        }
+        k = nk;
+        bi = nbi;
+        bj = nbj;
+    }
+}
+
+// Tile 16 in strips: a wave moves two tiles at once, one per half-wave
+// (tiles 2 j and 2 j + 1 of the strip, j = w, w + 4, ...), so that where the
+// two are neighbours in a tile row (the usual case) every load and store
+// instruction covers whole 128-byte lines: 8 rows x 64 bytes of each tile.
+// Each half-wave maps its tile on its own; a half whose tile is missing
+// (past the strip or the grid) loads tile (0, 0) and stores nothing.
+template <int MAP>
+__global__ void __launch_bounds__(256) k_axpyt_strip_pairs(ElemArgs p, StripGrid sg)
+{
+    constexpr int TILE = 16, RPP = 8, PASSES = 2;
+    __shared__ float ysh[8][TILE][TILE + 1];
+    const int l = threadIdx.x & 63, h = l >> 5, hl = l & 31;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    float (*ys)[TILE + 1] = ysh[2 * w + h];
+    const int tr = hl / 4, tc = (hl % 4) * 4;
+    const int32_t n = p.n;
+    const int64_t ld = p.ld;
+    const float *X = (const float *)p.x;
+    const float *Y = (const float *)p.y;
+    float *C = (float *)p.c;
+    const float a = p.a;
+    const int32_t cmax = (int32_t)(ld - 4);
+    const uint32_t first = strip_first<MAP>(p.g, sg);
+
+    // this half's tile of pair j (false: none)
+    auto tile = [&](int j, int32_t &bi, int32_t &bj) {
+        const int k = 2 * j + h;
+        const bool v = k < sg.G && strip_tile<MAP>(p.g, sg, first, k, bi, bj);
+        if (!v) bi = bj = 0;
+        return v;
+    };
+    f4 xv[PASSES], yv[PASSES];
+    auto load = [&](int32_t bi, int32_t bj) {
+        const int32_t i0 = bi * TILE, j0 = bj * TILE;
+        const bool full = (bj < bi) && (i0 + TILE <= n);
+#pragma unroll
+        for (int ps = 0; ps < PASSES; ++ps) {
+            const int r = tr + ps * RPP;
+            int32_t i = i0 + r, jc = j0 + tc;
+            if (!full) {
+                i = i < n ? i : n - 1;
+                jc = jc < cmax ? jc : cmax;
+            }
+            xv[ps] = __builtin_nontemporal_load((const f4 *)(X + (int64_t)i * ld + jc));
+        }
+#pragma unroll
+        for (int ps = 0; ps < PASSES; ++ps) {
+            const int r = tr + ps * RPP;
+            int32_t jr = j0 + r, ic = i0 + tc;
+            if (!full) {
+                jr = jr < n ? jr : n - 1;
+                ic = ic < cmax ? ic : cmax;
+            }
+            yv[ps] = __builtin_nontemporal_load((const f4 *)(Y + (int64_t)jr * ld + ic));
+        }
+    };
+
+    int j = w;
+    int32_t bi = 0, bj = 0;
+    bool v = tile(j, bi, bj);
+    load(bi, bj);
+    while (2 * j < sg.G) {
+#pragma unroll
+        for (int ps = 0; ps < PASSES; ++ps) {
+            const int r = tr + ps * RPP;
+            ys[r][tc + 0] = yv[ps].x;
+            ys[r][tc + 1] = yv[ps].y;
+            ys[r][tc + 2] = yv[ps].z;
+            ys[r][tc + 3] = yv[ps].w;
+        }
+        f4 xc[PASSES];
+#pragma unroll
+        for (int ps = 0; ps < PASSES; ++ps) xc[ps] = xv[ps];
+        const int32_t i0 = bi * TILE, j0 = bj * TILE;
+        const bool full = v && (bj < bi) && (i0 + TILE <= n);
+        const bool cv = v;
+        // the next pair's loads, in flight during this pair's stores
+        int32_t nbi = 0, nbj = 0;
+        const int nj = j + 4;
+        const bool nv = tile(nj, nbi, nbj);
+        if (2 * nj < sg.G) load(nbi, nbj);
+#pragma unroll
+        for (int ps = 0; ps < PASSES; ++ps) {
+            const int r = tr + ps * RPP;
+            const int32_t i = i0 + r, jc = j0 + tc;
+            if (!cv || (!full && (i >= n || jc > i))) continue;
+            float *crow = C + (int64_t)i * ld + jc;
+            f4 o;
+            o.x = __fadd_rn(__fmul_rn(a, xc[ps].x), ys[tc + 0][r]);
+            o.y = __fadd_rn(__fmul_rn(a, xc[ps].y), ys[tc + 1][r]);
+            o.z = __fadd_rn(__fmul_rn(a, xc[ps].z), ys[tc + 2][r]);
+            o.w = __fadd_rn(__fmul_rn(a, xc[ps].w), ys[tc + 3][r]);
+            if (full || jc + 3 <= i) {
+                __builtin_nontemporal_store(o, (f4 *)crow);
+            } else {  // the vector straddles the diagonal
+                crow[0] = o.x;
+                if (jc + 1 <= i) crow[1] = o.y;
+                if (jc + 2 <= i) crow[2] = o.z;
+            }
+        }
+        j = nj;
+        v = nv;
+        bi = nbi;
+        bj = nbj;
+    }
+}
+
 template <int MAP, int TILE, bool VECTOR>
 __global__ void __launch_bounds__((ElemShape<TILE, VECTOR>::NT)) k_xormul(ElemArgs p)
 {
@@ -307,9 +527,41 @@ static bool dispatch_tile(const tri_plan *p, const ElemArgs &args, hipStream_t s
     return false;
 }
 
+template <int MAP, int TILE>
+static void launch_axpyt_strip(const tri_plan *p, const ElemArgs &args, hipStream_t s)
+{
+    dim3 grid;
+    const StripGrid sg = strip_grid(MAP, args.g.m, args.g.flags, args.g.T, p->gx, p->gy,
+                                    strip_flag_len(p->flags), 1, grid);
+    if constexpr (TILE == 16)
+        k_axpyt_strip_pairs<MAP><<<grid, 256, 0, s>>>(args, sg);
+    else
+        k_axpyt_strip<MAP, TILE><<<grid, 256, 0, s>>>(args, sg);
+}
+
+template <int MAP>
+static bool dispatch_axpyt_strip(const tri_plan *p, const ElemArgs &args, hipStream_t s)
+{
+    if (p->tile == 16) launch_axpyt_strip<MAP, 16>(p, args, s);
+    else if (p->tile == 32) launch_axpyt_strip<MAP, 32>(p, args, s);
+    else return false;
+    return true;
+}
+
 template <int OP, bool VECTOR>
 static bool dispatch_map(const tri_plan *p, const ElemArgs &args, hipStream_t s)
 {
+    // strips of tiles 16 and 32 (16-byte vectors, tile maps)
+    if constexpr (OP == TRI_OP_AXPYT_F32 && VECTOR) {
+        if ((p->tile == 16 || p->tile == 32) && strip_flag_len(p->flags) && p->map != TRI_MAP_UTM) {
+            switch (p->map) {
+            case TRI_MAP_BB: return dispatch_axpyt_strip<MAP_BB>(p, args, s);
+            case TRI_MAP_RB: return dispatch_axpyt_strip<MAP_RB>(p, args, s);
+            case TRI_MAP_REC: return dispatch_axpyt_strip<MAP_REC>(p, args, s);
+            case TRI_MAP_LAMBDA: return dispatch_axpyt_strip<MAP_LAMBDA>(p, args, s);
+            }
+        }
+    }
     switch (p->map) {
     case TRI_MAP_BB: return dispatch_tile<OP, MAP_BB, VECTOR>(p, args, s);
     case TRI_MAP_RB: return dispatch_tile<OP, MAP_RB, VECTOR>(p, args, s);

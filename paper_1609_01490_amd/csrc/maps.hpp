@@ -267,6 +267,15 @@ __device__ __forceinline__ bool tile_of_block(const TileGrid &g, int32_t &bi, in
 // Strip s lies in column c with P(c) <= s < P(c + 1), P(c) = c m - G c (c -
 // 1) / 2 (the strips of the columns before c): the root of the quadratic,
 // corrected by integer steps, as lambda finds its row.
+//
+// Row-major aligned strips (TRI_FLAG_STRIP_ALIGN, lambda, K = 1): the same
+// row-aligned strips taken row by row (every strip of row i before row
+// i + 1), so that each strip starts at a multiple of G tiles in its row.
+// Row i has ceil((i + 1) / G) strips, so the rows a G .. a G + G - 1 have
+// a + 1 each and G a (a + 1) / 2 strips lie before row a G: strip s is in
+// row group a = floor((sqrt(8 s / G + 1) - 1) / 2) (lambda on s / G, with
+// the integer correction), row a G + o / (a + 1), strip o mod (a + 1), for
+// o = s - G a (a + 1) / 2.
 // ---------------------------------------------------------------------------
 struct StripGrid {
     uint32_t strips;  // lambda: workgroups in the launch (gridDim.x)
@@ -293,6 +302,25 @@ __device__ __forceinline__ uint32_t strip_cols_first(uint32_t s, uint32_t m, uin
     return (uint32_t)((uint64_t)i * (i + 1) / 2) + c * G;
 }
 
+// Strips of the row-major aligned order before row i.
+__host__ __device__ __forceinline__ uint64_t strip_align_prefix(uint32_t i, uint32_t G)
+{
+    const uint64_t a = i / G, b = i % G;
+    return (uint64_t)G * a * (a + 1) / 2 + b * (a + 1);
+}
+
+// First omega of row-major aligned strip s (s below the strip count).
+__device__ __forceinline__ uint32_t strip_align_first(uint32_t s, uint32_t G)
+{
+    const double x = 8.0 * (double)s / (double)G + 1.0;
+    uint64_t a = (uint64_t)((__builtin_sqrt(x) - 1.0) * 0.5);
+    while (a > 0 && (uint64_t)G * a * (a + 1) / 2 > s) --a;
+    while ((uint64_t)G * (a + 1) * (a + 2) / 2 <= s) ++a;
+    const uint64_t o = s - (uint64_t)G * a * (a + 1) / 2;
+    const uint64_t i = a * G + o / (a + 1), c = o % (a + 1);
+    return (uint32_t)(i * (i + 1) / 2 + c * G);
+}
+
 // Launch grid of a strip kernel for a plan's map, tile grid (m tiles a side,
 // flags) and map grid (gx, gy).
 __host__ __forceinline__ StripGrid strip_grid(int map, int32_t m, uint32_t flags, uint64_t T,
@@ -304,6 +332,10 @@ __host__ __forceinline__ StripGrid strip_grid(int map, int32_t m, uint32_t flags
     if (map == TRI_MAP_LAMBDA && (flags & TRI_FLAG_STRIP_COLS)) {
         s.K = 1;
         s.strips = (uint32_t)strip_cols_prefix((uint32_t)((m + G - 1) / G), (uint32_t)m, (uint32_t)G);
+        grid = dim3(s.strips, 1);
+    } else if (map == TRI_MAP_LAMBDA && (flags & TRI_FLAG_STRIP_ALIGN)) {
+        s.K = 1;
+        s.strips = (uint32_t)strip_align_prefix((uint32_t)m, (uint32_t)G);
         grid = dim3(s.strips, 1);
     } else if (map == TRI_MAP_LAMBDA) {
         s.strips = (uint32_t)((T + span - 1) / span * (uint64_t)K);
@@ -331,6 +363,7 @@ __device__ __forceinline__ uint32_t strip_first(const TileGrid &g, const StripGr
         if (g.flags & TRI_FLAG_ORDER_REVERSE) G2 = ng - 1 - grp;
         else if (g.flags & TRI_FLAG_ORDER_PAIRS) G2 = (grp & 1) ? ng - 1 - (grp >> 1) : (grp >> 1);
         if (g.flags & TRI_FLAG_STRIP_COLS) return strip_cols_first(G2, (uint32_t)g.m, (uint32_t)sg.G);
+        if (g.flags & TRI_FLAG_STRIP_ALIGN) return strip_align_first(G2, (uint32_t)sg.G);
         return G2 * K * (uint32_t)sg.G + k;
     } else {
         const uint32_t K = (uint32_t)sg.K;
@@ -350,9 +383,9 @@ __device__ __forceinline__ bool strip_tile(const TileGrid &g, const StripGrid &s
         if (w >= (uint32_t)g.T) return false;
         if (g.T <= (1ull << 24)) lambda_tile_24(w, bi, bj);
         else lambda_tile_32(w, bi, bj);
-        // a column-major strip ends with its row: tile k of the strip has
+        // an aligned strip ends with its row: tile k of the strip has
         // column bj0 + k >= k, the next row's tiles columns below k
-        if ((g.flags & TRI_FLAG_STRIP_COLS) && bj < k) return false;
+        if ((g.flags & (TRI_FLAG_STRIP_COLS | TRI_FLAG_STRIP_ALIGN)) && bj < k) return false;
     } else {
         const int32_t bx = (int32_t)first + k * sg.K;
         if (bx >= sg.gx) return false;

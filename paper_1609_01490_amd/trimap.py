@@ -31,6 +31,7 @@ def FLAG_STRIP(k: int) -> int:
 
 
 FLAG_STRIP_COLS = 0x1000  # lambda strips aligned to tile rows, taken column by column
+FLAG_STRIP_ALIGN = 0x2000  # lambda strips aligned to tile rows, taken row by row
 OP_XORMUL_I32, OP_AXPYT_F32, OP_EDM4_F32 = 0, 1, 2
 EDM_FP32, EDM_BF16X3, EDM_BF16 = 0, 1, 2
 EDM_NOALLOC_SCRATCH_BYTES = 16 << 20
@@ -496,7 +497,7 @@ def autotune(workload: int, n: int, d: int = 0, reps: int = 3, use_cache: bool =
     """Time the tile/map candidates (tri_autotune); returns (best, all) with
     each choice a dict(tile, map, flags, ms)."""
     best = tri_tune_choice()
-    cap = 64
+    cap = 256
     arr = (tri_tune_choice * cap)()
     cnt = ctypes.c_int32()
     _check(lib.tri_autotune(int(workload), int(n), int(d), int(reps), 1 if use_cache else 0,

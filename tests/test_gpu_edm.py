@@ -170,13 +170,15 @@ def test_edm_mfma_small(mode, map_name):
 @pytest.mark.parametrize("mode", [1, 2])
 @pytest.mark.parametrize("map_name,flags", [("lambda", 0), ("lambda", 1 | 16), ("lambda", 8),
                                             ("lambda", 0x1000), ("lambda", 0x1000 | 1),
-                                            ("lambda", 0x1000 | 1 | 8),
+                                            ("lambda", 0x1000 | 1 | 8), ("lambda", 0x2000),
+                                            ("lambda", 0x2000 | 1 | 16),
                                             ("bb", 0), ("rb", 0), ("rec", 0)])
 @pytest.mark.parametrize("strip", [1, 2, 5])
 def test_edm_mfma_strips(mode, map_name, flags, strip):
     """Workgroups walking strips of 2, 4 and 32 consecutive tiles (row
     operands reloaded at each change of tile row, the carry of block 3 passed
-    along the strip), in row order or column-major (0x1000): whole rows
+    along the strip), in omega order or aligned to tile rows (column-major
+    0x1000, row-major 0x2000): whole rows
     against the FP64 oracle at n where strips cross tile rows and end past the
     last tile.  REC at m = 8 and 16."""
     tm = _tm()

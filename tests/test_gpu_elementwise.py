@@ -71,6 +71,36 @@ def test_axpyt_f32_bit_exact(map_name, tile):
             assert (got.view(np.uint32) == exp.view(np.uint32)).all(), (map_name, tile, n, ld)
 
 
+@pytest.mark.parametrize("map_name", ["bb", "rb", "rec", "lambda"])
+@pytest.mark.parametrize("tile", [16, 32])
+@pytest.mark.parametrize("strip,flags", [(0, 0), (2, 0), (4, 0), (5, 0), (4, 16), (4, 1),
+                                         (4, 0x1000), (3, 0x1001), (2, 0x2000), (3, 0x2010),
+                                         (5, 0x2001)])
+def test_axpyt_f32_strips_bit_exact(map_name, tile, strip, flags):
+    """Workgroups of four waves walking strips of 1, 4, 16 and 32 tiles (each
+    wave every fourth tile, its next tile's loads in flight), in row order
+    or aligned to tile rows (column-major 0x1000, row-major 0x2000) and
+    under the lambda orders: bit-exact at ragged
+    n with 16-byte rows, the upper part untouched."""
+    if map_name != "lambda" and flags:
+        pytest.skip("orders and column-major strips are lambda flags")
+    tm = _tm()
+    for n in (1, 17, 100, 257, 300, 1024, 1500):
+        ld = padded_ld(n)
+        m = -(-n // tile)
+        if map_name == "rec" and (m & (m - 1)):
+            continue
+        p = tm.Plan(n, tile, map_name, flags=flags | tm.FLAG_STRIP(strip))
+        a, X, Y, C0 = inputs.f32_elementwise(n, seed=2500 + n + tile, ld=ld)
+        exp = C0.copy()
+        oracle.c1(a, X, Y, exp, n=n)
+        note("axpyt strips", map_name, tile, strip, flags, n, ld)
+        c = dev(C0)
+        p.elementwise(tm.OP_AXPYT_F32, dev(X), dev(Y), c, ld=ld, a=float(a))
+        got = host(c)
+        assert (got.view(np.uint32) == exp.view(np.uint32)).all(), (map_name, tile, strip, flags, n)
+
+
 def test_empty_domain_is_a_no_op():
     import torch
     tm = _tm()
@@ -112,7 +142,10 @@ def full_inputs():
 @pytest.mark.slow
 @pytest.mark.parametrize("map_name,tile,flags", [("lambda", 128, 16), ("lambda", 64, 16),
                                                  ("bb", 128, 0), ("lambda", 32, 0), ("bb", 32, 0),
-                                                 ("lambda", 16, 0)])
+                                                 ("lambda", 16, 0), ("lambda", 16, 0x500),
+                                                 ("lambda", 32, 0x500), ("bb", 16, 0x500),
+                                                 ("lambda", 16, 0x511), ("lambda", 32, 0x601),
+                                                 ("lambda", 16, 0x2300), ("lambda", 32, 0x2410)])
 def test_axpyt_full_size_sampled_rows(full_inputs, map_name, tile, flags):
     """n = 32768 (12 GiB of operands), the configuration the benchmark times
     (lambda, tile 128, pairs order) and its neighbours; 64 sampled rows plus
@@ -144,20 +177,29 @@ def test_axpyt_full_size_sampled_rows(full_inputs, map_name, tile, flags):
 
 
 @pytest.mark.slow
-def test_axpyt_full_size_whole_triangle(full_inputs):
-    """The benchmarked launch (n = 32768, lambda, tile 128, pairs order):
-    every cell of the lower triangle bit for bit against the oracle, which
-    computes 1024-row bands on a thread pool (its C loop runs without the
-    GIL); every cell above the diagonal keeps its pre-fill."""
+@pytest.mark.parametrize("which", ["t128_pairs", "tuned"])
+def test_axpyt_full_size_whole_triangle(full_inputs, which):
+    """At n = 32768: the launch the benchmark timed before tile-16/32 strips
+    existed (lambda, tile 128, pairs order) and the lambda launch the
+    autotuner picks now (what the benchmark times): every cell of the lower
+    triangle bit for bit against the oracle, which computes 1024-row bands
+    on a thread pool (its C loop runs without the GIL); every cell above
+    the diagonal keeps its pre-fill."""
     import concurrent.futures as cf
     import torch
     tm = _tm()
     n, a, X, Y, xd, yd = full_inputs
-    note("axpyt whole triangle", n)
+    if which == "tuned":
+        tm.tune_cache_clear()
+        _, table = tm.autotune(tm.TUNE_ELEMENTWISE_F32, n, 0, reps=3, use_cache=False)
+        best = min((c for c in table if c["map"] == "lambda"), key=lambda c: c["ms"])
+        tile, flags = best["tile"], best["flags"]
+    else:
+        tile, flags = 128, tm.FLAG_ORDER_PAIRS
+    note("axpyt whole triangle", n, tile, flags)
     fill = np.float32(-7.5)
     c = torch.full((n, n), float(fill), dtype=torch.float32, device="cuda")
-    tm.Plan(n, 128, "lambda", flags=tm.FLAG_ORDER_PAIRS).elementwise(
-        tm.OP_AXPYT_F32, xd, yd, c, ld=n, a=float(a))
+    tm.Plan(n, tile, "lambda", flags=flags).elementwise(tm.OP_AXPYT_F32, xd, yd, c, ld=n, a=float(a))
     torch.cuda.synchronize()
     got = c.cpu().numpy()
     del c
@@ -174,7 +216,7 @@ def test_axpyt_full_size_whole_triangle(full_inputs):
 
     with cf.ThreadPoolExecutor(16) as ex:
         res = list(ex.map(band, range(0, n, 1024)))
-    print(f"[axpyt whole triangle] {len(res)} bands checked", flush=True)
+    print(f"[axpyt whole triangle] tile {tile} flags {flags}: {len(res)} bands checked", flush=True)
     assert sum(r[0] for r in res) == 0, [r[0] for r in res]
     assert sum(r[1] for r in res) == 0, [r[1] for r in res]
 

@@ -88,6 +88,26 @@ __global__ void __launch_bounds__(64) k_life_bits(LifeArgs p, int gens)
     life_bits_wave_body<VEC, KH>(p.t, bi, bj, gens, buf);
 }
 
+// Strips (plans with TRI_FLAG_STRIP): a workgroup of four waves walks G
+// consecutive tiles of the map, wave w taking tiles w, w + 4, ... of the
+// strip, each with its own LDS buffers (the wave body needs no workgroup
+// barrier), so that one dispatch serves G tiles.  KH = 1: one generation
+// with the 1-cell halo; else up to KH generations.
+template <int MAP, int KH>
+__global__ void __launch_bounds__(256) k_life_bits_strip(LifeArgs p, int gens, StripGrid sg)
+{
+    __shared__ __attribute__((aligned(16))) uint32_t buf[4][2 * LifeBitsShape<KH>::WORDS];
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t first = strip_first<MAP>(p.g, sg);
+    for (int k = w; k < sg.G; k += 4) {
+        int32_t bi, bj;
+        if (!strip_tile<MAP>(p.g, sg, first, k, bi, bj)) continue;
+        bi = __builtin_amdgcn_readfirstlane(bi);
+        bj = __builtin_amdgcn_readfirstlane(bj);
+        life_bits_wave_body<true, KH>(p.t, bi, bj, gens, buf[w]);
+    }
+}
+
 // One generation of 64 x 64 tiles with the 1-cell halo of the paper's tiles,
 // bit-sliced, one wave per tile, 16-byte row moves
 template <int MAP>
@@ -105,6 +125,18 @@ static bool life_vec16(const LifeTile &t)
     return t.ld % 16 == 0 && (((uintptr_t)t.cur | (uintptr_t)t.nxt) & 15) == 0;
 }
 
+// strip walk and launch grid of a plan's strip kernels
+static StripGrid life_strip_grid(const tri_plan *p, const TileGrid &g, dim3 &grid)
+{
+    return strip_grid(p->map, g.m, g.flags, g.T, p->gx, p->gy, strip_flag_len(p->flags), 1, grid);
+}
+
+// strips take the bit-sliced kernels only (tile 64, 16-byte rows)
+static bool life_strips(const tri_plan *p, const LifeTile &t)
+{
+    return p->map != TRI_MAP_UTM && p->tile == 64 && strip_flag_len(p->flags) && life_vec16(t);
+}
+
 // One generation of a plan's tiles (64 x 64 tiles with 16-byte rows:
 // bit-sliced)
 template <int MAP>
@@ -116,8 +148,15 @@ static bool life_tile(const tri_plan *p, const LifeArgs &a, hipStream_t s)
     case 16: k_life<MAP, 16><<<grid, life_threads<16>(), 0, s>>>(a); return true;
     case 32: k_life<MAP, 32><<<grid, life_threads<32>(), 0, s>>>(a); return true;
     case 64:
-        if (life_vec16(a.t)) k_life_bits1<MAP><<<grid, 64, 0, s>>>(a);
-        else k_life<MAP, 64><<<grid, life_threads<64>(), 0, s>>>(a);
+        if (life_vec16(a.t) && strip_flag_len(p->flags)) {
+            dim3 sgrid;
+            const StripGrid sg = life_strip_grid(p, a.g, sgrid);
+            k_life_bits_strip<MAP, 1><<<sgrid, 256, 0, s>>>(a, 1, sg);
+        } else if (life_vec16(a.t)) {
+            k_life_bits1<MAP><<<grid, 64, 0, s>>>(a);
+        } else {
+            k_life<MAP, 64><<<grid, life_threads<64>(), 0, s>>>(a);
+        }
         return true;
     }
     return false;
@@ -151,6 +190,25 @@ static bool life_multi_kernel_tile(int tile, uint64_t tiles, bool vec, const voi
         return true;
     }
     return false;
+}
+
+template <int MAP>
+static const void *life_strip_kernel(int kh)
+{
+    return kh == 1 ? (const void *)k_life_bits_strip<MAP, 1>
+                   : (const void *)k_life_bits_strip<MAP, kLifeBitsStencilGen>;
+}
+
+// the strip kernel of a plan (kh = 1: one generation; else the temporal one)
+static const void *life_strip_fn(const tri_plan *p, int kh)
+{
+    switch (p->map) {
+    case TRI_MAP_BB: return life_strip_kernel<MAP_BB>(kh);
+    case TRI_MAP_RB: return life_strip_kernel<MAP_RB>(kh);
+    case TRI_MAP_REC: return life_strip_kernel<MAP_REC>(kh);
+    case TRI_MAP_LAMBDA: return life_strip_kernel<MAP_LAMBDA>(kh);
+    }
+    return nullptr;
 }
 
 static bool life_multi_kernel(const tri_plan *p, bool vec, const void *&fn, int &threads,
@@ -293,6 +351,15 @@ static tri_status life_graph(const tri_plan *p, const LifeArgs &a0, int steps,
     int threads = 0;
     if (!life_kernel(p, life_vec16(a0.t), fn, threads))
         return fail(TRI_E_UNSUPPORTED, "tri_launch_stencil: tile");
+    dim3 grid(p->gx, p->gy);
+    StripGrid sg{};
+    int one = 1;
+    const bool strips = life_strips(p, a0.t);
+    if (strips) {
+        fn = life_strip_fn(p, 1);
+        threads = 256;
+        sg = life_strip_grid(p, a0.g, grid);
+    }
     hipGraph_t g = nullptr;
     TRI_HIP(hipGraphCreate(&g, 0));
     hipGraphNode_t prev = nullptr;
@@ -301,13 +368,14 @@ static tri_status life_graph(const tri_plan *p, const LifeArgs &a0, int steps,
         LifeArgs a = a0;
         a.t.cur = (k & 1) ? a0.t.nxt : a0.t.cur;
         a.t.nxt = (k & 1) ? (uint8_t *)a0.t.cur : a0.t.nxt;
-        void *args[] = {&a};
+        void *args1[] = {&a};
+        void *args3[] = {&a, &one, &sg};
         hipKernelNodeParams np{};
         np.func = (void *)fn;
-        np.gridDim = dim3(p->gx, p->gy);
+        np.gridDim = grid;
         np.blockDim = dim3(threads);
         np.sharedMemBytes = 0;
-        np.kernelParams = args;
+        np.kernelParams = strips ? args3 : args1;
         np.extra = nullptr;
         hipGraphNode_t node;
         e = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &np);
@@ -349,13 +417,22 @@ extern "C" tri_status tri_launch_stencil(const tri_plan *p, uint8_t *cur, uint8_
         int threads = 256, maxgen = kLifeMaxGen;
         if (!life_multi_kernel(p, life_vec16(a.t), fn, threads, maxgen))
             return fail(TRI_E_UNSUPPORTED, "tri_launch_stencil: temporal blocking needs tile 16, 32 or 64");
+        dim3 grid(p->gx, p->gy);
+        StripGrid sg{};
+        const bool strips = life_strips(p, a.t);
+        if (strips) {
+            fn = life_strip_fn(p, kLifeBitsStencilGen);
+            threads = 256;
+            maxgen = kLifeBitsStencilGen;
+            sg = life_strip_grid(p, a.g, grid);
+        }
         const std::vector<int> sched = life_multi_schedule(steps, maxgen);
         for (size_t k = 0; k < sched.size(); ++k) {
             a.t.cur = (k & 1) ? nxt : cur;
             a.t.nxt = (k & 1) ? cur : nxt;
             int gens = sched[k];
-            void *args[] = {&a, &gens};
-            TRI_HIP(hipLaunchKernel(fn, dim3(p->gx, p->gy), dim3(threads), args, 0, s));
+            void *args[] = {&a, &gens, &sg};
+            TRI_HIP(hipLaunchKernel(fn, grid, dim3(threads), args, 0, s));
         }
         return TRI_OK;
     }

@@ -168,6 +168,42 @@ def test_life_graph_mode_matches_eager_and_replays(map_name, tile, multiple):
             assert (got[low] == eager[:, :n][low]).all()
 
 
+@pytest.mark.parametrize("map_name,flags", [("lambda", 0), ("lambda", 17), ("lambda", 0x2000),
+                                            ("lambda", 0x1001), ("bb", 0), ("rb", 0), ("rec", 0)])
+@pytest.mark.parametrize("strip", [0, 2, 3, 5])
+@pytest.mark.parametrize("temporal", [False, True])
+def test_life_strips_bit_exact(map_name, flags, strip, temporal):
+    """Tile 64 with 16-byte rows in strips of 1, 4, 8 and 32 tiles per
+    workgroup (each wave its own tiles): one generation per launch (eager
+    and in a graph) and the temporal kernel, bit-exact against the oracle,
+    upper triangle untouched."""
+    import torch
+    tm = _tm()
+    fl = flags | tm.FLAG_STRIP(strip) | (tm.FLAG_LIFE_TEMPORAL if temporal else 0)
+    for n in (1, 33, 200, 700, 1500):
+        m = -(-n // 64)
+        if map_name == "rec" and (m & (m - 1)):
+            continue
+        ld = padded_ld(n, 16)
+        g = inputs.life(n, 0.3, seed=7000 + n + strip, ld=ld)
+        p = tm.Plan(n, 64, map_name, flags=fl)
+        low = np.tril(np.ones((n, n), dtype=bool))
+        for steps in (1, 2, 5, 20):
+            note("life strips", map_name, flags, strip, temporal, n, steps)
+            got = _run(tm, p, g, steps, garbage_seed=n * 7 + steps)
+            exp = oracle.gol(g, n, steps)
+            assert (got[:, :n][low] == exp[low]).all(), (map_name, fl, n, steps)
+        if not temporal and n == 700:
+            cur, nxt = dev(g), torch.zeros((n, ld), dtype=torch.uint8, device="cuda")
+            for rep in range(2):
+                note("life strips graph", map_name, flags, strip, rep)
+                p.stencil(cur, nxt, 4, ld=ld, use_graph=True)
+                torch.cuda.synchronize()
+                _ = torch.ones(100, device="cuda").sum().item()
+            exp = oracle.gol(g, n, 8)
+            assert (host(cur)[:, :n][low] == exp[low]).all()
+
+
 @pytest.mark.parametrize("map_name", ["lambda", "bb", "rb"])
 @pytest.mark.parametrize("tile", [16, 32, 64])
 def test_life_temporal_blocking_bit_exact(map_name, tile):

@@ -605,11 +605,8 @@ def bench_tetra(tm, torch, timer, n=8192):
             "dummy_n2048_us_by_map_tile": dummy_us, "dummy_I_vs_bb": Id}
 
 
-def bench_batch(tm, torch, timer, steps=20, d=32, tiles=None):
-    """512 uneven instances (n log-uniform in [64, 8192]), even index distance
-    map (d = 32), odd index Life (20 generations).  Tiles from the batch
-    autotuner (tri_batch_autotune) unless given; then one hipGraph launch of
-    the persistent queue vs the same bodies launched per instance."""
+def make_batch(tm, torch, steps=20, d=32, tiles=None):
+    """The 512-instance batch (see bench_batch), bound to device buffers."""
     from paper_1609_01490_amd import inputs
     spec = inputs.batch_instances()
     kinds, ns, A, B, init = [], [], [], [], []
@@ -642,6 +639,15 @@ def bench_batch(tm, torch, timer, steps=20, d=32, tiles=None):
         te, tl, fl = tiles
     b = tm.Batch(kinds, ns, ds, edm_tile=te, life_tile=tl, life_steps=steps, flags=fl)
     b.bind(A, B)
+    return spec, kinds, A, B, b, te, tl, fl, tune_ms, pairs, cells
+
+
+def bench_batch(tm, torch, timer, steps=20, d=32, tiles=None):
+    """512 uneven instances (n log-uniform in [64, 8192]), even index distance
+    map (d = 32), odd index Life (20 generations).  Tiles from the batch
+    autotuner (tri_batch_autotune) unless given; then one hipGraph launch of
+    the persistent queue vs the same bodies launched per instance."""
+    spec, kinds, A, B, b, te, tl, fl, tune_ms, pairs, cells = make_batch(tm, torch, steps, d, tiles)
     res = {}
     for how, name in ((tm.BATCH_GRAPH, "graph"), (tm.BATCH_STREAM, "stream"),
                       (tm.BATCH_PER_INSTANCE, "per_instance")):
@@ -716,6 +722,14 @@ def profile_target(tm, torch, args):
         nxt = torch.zeros_like(cur)
         p = tm.Plan(n, args.tile or 64, args.map, flags=args.flags)
         p.stencil(cur, nxt, reps)
+    elif t == "batch":
+        tiles = (args.tile, args.tile, args.flags) if args.tile else None
+        spec, kinds, A, B, b, *_ = make_batch(tm, torch, tiles=tiles)
+        torch.cuda.synchronize()
+        for _ in range(reps):
+            b.launch(tm.BATCH_GRAPH)
+        torch.cuda.synchronize()
+        b.close()
     elif t == "int":
         n = 2048
         A, B, C0 = inputs.int_elementwise(n)
@@ -737,7 +751,8 @@ def main():
     ap.add_argument("--flags", type=int, default=0)
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--profile-target", choices=["elementwise", "edm", "edm_fp32", "life", "int", "copy"],
+    ap.add_argument("--profile-target", choices=["elementwise", "edm", "edm_fp32", "life", "int", "copy",
+                                                 "batch"],
                     help="only launch this workload's kernels a few times (for rocprofv3 runs); "
                          "prints no JSON line")
     args = ap.parse_args()

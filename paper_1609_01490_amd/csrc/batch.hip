@@ -58,6 +58,8 @@ struct BatchStepArgs {
 };
 
 constexpr int kBatchThreads = 256;
+// generations per node of the bit-sliced Life body in the batch (its halo)
+constexpr int kBatchBitsGen = kLifeBitsStencilGen;
 constexpr int kPrefixLds = 1024;  // prefix entries kept in LDS (else searched in memory)
 
 template <int TL>
@@ -70,7 +72,7 @@ struct BatchLds {
     static constexpr int MULTI_BYTES = life_multi_bytes<TL>();
     // 64 x 64 Life tiles with several generations: one bit-sliced tile per wave
     static constexpr int BITS_BYTES =
-        TL == 64 ? kBatchThreads / 64 * 2 * LifeBitsShape<kLifeBitsMaxGen>::WORDS * 4 : 0;
+        TL == 64 ? kBatchThreads / 64 * 2 * LifeBitsShape<kBatchBitsGen>::WORDS * 4 : 0;
     static constexpr int B1 = EDM_BYTES > LIFE_BYTES ? EDM_BYTES : LIFE_BYTES;
     static constexpr int B2 = B1 > MULTI_BYTES ? B1 : MULTI_BYTES;
     static constexpr int BYTES = B2 > BITS_BYTES ? B2 : BITS_BYTES;
@@ -147,8 +149,8 @@ __global__ void __launch_bounds__(kBatchThreads, 4) k_batch_step(BatchStepArgs a
                         const LifeTile t{W.n, W.ld, (const uint8_t *)(even ? W.a : W.b),
                                          (uint8_t *)(even ? W.b : W.a)};
                         uint32_t *wl = (uint32_t *)body_lds +
-                                       wv * 2 * LifeBitsShape<kLifeBitsMaxGen>::WORDS;
-                        life_bits_wave_body<true, kLifeBitsMaxGen>(t, bi, bj, a.gens, wl);
+                                       wv * 2 * LifeBitsShape<kBatchBitsGen>::WORDS;
+                        life_bits_wave_body<true, kBatchBitsGen>(t, bi, bj, a.gens, wl);
                     }
                     continue;  // the loop's barrier precedes the next claim
                 }
@@ -184,10 +186,10 @@ __global__ void __launch_bounds__(kBatchThreads, 4) k_batch_step(BatchStepArgs a
                 if constexpr (BITS && TL == 64) {
                     // a Life item in a chunk that also holds distance items:
                     // the first wave takes it (nodes may advance up to
-                    // kLifeBitsMaxGen generations, beyond the byte-sliced body)
+                    // kBatchBitsGen generations, beyond the byte-sliced body)
                     if (a.gens > 0) {
                         if (threadIdx.x < 64)
-                            life_bits_wave_body<true, kLifeBitsMaxGen>(t, bi, bj, a.gens,
+                            life_bits_wave_body<true, kBatchBitsGen>(t, bi, bj, a.gens,
                                                                        (uint32_t *)body_lds);
                         done = true;
                     }
@@ -502,10 +504,10 @@ tri_status tri_batch_bind(tri_batch *b, void *const *host_a, void *const *host_b
         if (D.kind == TRI_KIND_LIFE && !(D.pad & kDescVec16)) bits = false;
     b->kernel = bits ? b->kernel_bits : b->kernel_bytes;
     b->grid = bits ? b->grid_bits : b->grid_bytes;
-    // the bit-sliced kernel advances up to kLifeBitsMaxGen generations per
+    // the bit-sliced kernel advances up to kBatchBitsGen generations per
     // node (fewer nodes than the plan's schedule, whose counters it reuses)
     if (b->temporal && b->steps > 0)
-        b->sched = life_multi_schedule(b->steps, bits ? kLifeBitsMaxGen : kLifeMaxGen);
+        b->sched = life_multi_schedule(b->steps, bits ? kBatchBitsGen : kLifeMaxGen);
     if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
     if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
     tri_status st = batch_build_graph(b);

@@ -464,6 +464,9 @@ def bench_edm(tm, torch, timer, check=True):
             res[f"{name}_err_pairs"] = cnt
         tag = f"edm_{name}_n{n}_d{d}_lambda_t128_f{best['flags']}"
         res[f"{name}_mfma_busy"] = profile_value(tag, "mfma_busy", digest)
+        hb = profile_value(tag, "hbm_bytes_per_launch", digest)
+        res[f"{name}_hbm_bytes_per_launch"] = hb
+        res[f"{name}_traffic_over_output"] = None if hb is None else round(hb / (4 * pairs), 4)
         del ws
     res["bf16x3_meets_1e-3"] = None if not check else res["bf16x3_max_rel_err"] <= 1e-3
     res["bf16_note"] = ("single BF16 rounds each centred coordinate to 8 significant bits: "

@@ -229,15 +229,13 @@ __device__ __forceinline__ uint32_t life_bits_mask(int32_t gi, int32_t jb, int32
     return upto & (0xFFFFFFFFu << lo);
 }
 
-// Four cells (bytes, nonzero = alive) to four bits, cell k to bit k: each
-// byte's bits are ORed into its bit 0, then one multiply gathers bit 0 of
-// byte k at bit 24 + k with no carries (the other partial products land
-// below bit 24 or beyond bit 31).
+// Four cells (bytes) to four bits, cell k to bit k: domain cells hold 0 or
+// 1, so bit 0 of each byte is the cell; one multiply gathers bit 0 of byte
+// k at bit 24 + k with no carries (the other partial products land below
+// bit 24 or beyond bit 31).  Bytes outside the domain may hold anything:
+// their bits are cleared by the domain masks after staging.
 __device__ __forceinline__ uint32_t life_cells4_to_bits(uint32_t x)
 {
-    x |= x >> 4;
-    x |= x >> 2;
-    x |= x >> 1;
     x &= 0x01010101u;
     return (x * 0x01020408u) >> 24;
 }

@@ -55,6 +55,32 @@ class Timer:
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / steps  # ms per call
 
+    def interleaved(self, fns, reps, warmup, reset=None):
+        """Medians of several functions timed in turn (one call of each per
+        round, each between its own pair of events), so that none of them
+        is favoured by its place in the run; reset() runs before every call,
+        outside the timed region."""
+        torch = self.torch
+        for _ in range(warmup):
+            for f in fns:
+                if reset:
+                    reset()
+                f()
+        torch.cuda.synchronize()
+        s = torch.cuda.current_stream()
+        times = [[] for _ in fns]
+        for _ in range(reps):
+            for k, f in enumerate(fns):
+                if reset:
+                    reset()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(s)
+                f()
+                e1.record(s)
+                torch.cuda.synchronize()
+                times[k].append(e0.elapsed_time(e1))
+        return [float(np.median(t)) for t in times]
+
     def median(self, fn, reps, warmup):
         """Median over `reps` calls, each between its own pair of events."""
         torch = self.torch
@@ -335,27 +361,34 @@ def bench_life(tm, torch, timer, steps=100, reps=7):
     tm.tune_cache_clear()
     _, table = tm.autotune(tm.TUNE_LIFE, n, steps, reps=5, use_cache=False)
     g = inputs.life(n, 0.3)
-    cur = torch.from_numpy(g).cuda()
+    g0 = torch.from_numpy(g).cuda()
+    cur = g0.clone()
     nxt = torch.zeros_like(cur)
+    reset = lambda: cur.copy_(g0)  # every timed call starts from generation 0
     out, one = {}, {}
     one_gen = [c for c in table if not c["flags"] & tm.FLAG_LIFE_TEMPORAL]
-    for map_name in ("lambda", "bb"):
-        ch = best_of(table, map_name)
-        p = tm.Plan(n, ch["tile"], map_name, flags=ch["flags"])
-        ms = timer.median(lambda: p.stencil(cur, nxt, steps), reps, 1)
-        out[map_name] = {"ms": round(ms, 4), "tile": ch["tile"], "flags": ch["flags"],
+    # lambda and BB timed in turn, each call from the same grid
+    chs = {m: best_of(table, m) for m in ("lambda", "bb")}
+    c1s = {m: best_of(one_gen, m) for m in ("lambda", "bb")}
+    plans = {m: tm.Plan(n, chs[m]["tile"], m, flags=chs[m]["flags"]) for m in chs}
+    plans1 = {m: tm.Plan(n, c1s[m]["tile"], m, flags=c1s[m]["flags"]) for m in c1s}
+    t = timer.interleaved([lambda: plans["lambda"].stencil(cur, nxt, steps),
+                           lambda: plans["bb"].stencil(cur, nxt, steps)], reps, 1, reset)
+    t1 = timer.interleaved([lambda: plans1["lambda"].stencil(cur, nxt, steps),
+                            lambda: plans1["bb"].stencil(cur, nxt, steps)], reps, 1, reset)
+    for k, map_name in enumerate(("lambda", "bb")):
+        ch, c1 = chs[map_name], c1s[map_name]
+        out[map_name] = {"ms": round(t[k], 4), "tile": ch["tile"], "flags": ch["flags"],
                          "tuned_ms_per_generation": round(ch["ms"], 5)}
-        # the paper's form: one generation per launch, tiles with a 1-cell halo
-        c1 = best_of(one_gen, map_name)
-        q = tm.Plan(n, c1["tile"], map_name, flags=c1["flags"])
-        ms1 = timer.median(lambda: q.stencil(cur, nxt, steps), reps, 1)
-        one[map_name] = {"ms": round(ms1, 4), "tile": c1["tile"], "flags": c1["flags"]}
+        one[map_name] = {"ms": round(t1[k], 4), "tile": c1["tile"], "flags": c1["flags"]}
     cells = n * (n + 1) // 2
-    del cur, nxt
+    del cur, nxt, g0
     torch.cuda.empty_cache()
     lam = out["lambda"]["ms"]
     lam1 = one["lambda"]["ms"]
-    return {"n": n, "steps": steps, "timing": f"median of {reps} calls of {steps} generations",
+    return {"n": n, "steps": steps,
+            "timing": f"median of {reps} calls of {steps} generations, lambda and BB in turn, "
+                      f"each call from the same initial grid",
             "ms_100_steps": out,
             "cell_updates_per_s": round(cells * steps / (lam * 1e-3), 1),
             "generation_work_GBps": round(2 * cells * steps / (lam * 1e-3) / 1e9, 1),

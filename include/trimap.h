@@ -84,6 +84,11 @@ enum {
  * before row i + 1), so that each strip's first tile column is a multiple
  * of G.  TRI_FLAG_STRIP_COLS takes precedence. */
 #define TRI_FLAG_STRIP_ALIGN 0x2000u
+/* Plan flag for the distance map's matrix-core modes (up to 128
+ * dimensions): the pipelined kernel, one workgroup per CU, the column
+ * operands of two tiles in LDS and each tile's stores interleaved with the
+ * next tile's products. */
+#define TRI_FLAG_EDM_PIPE 0x4000u
 
 /* Elementwise bodies. */
 enum {

@@ -1102,6 +1102,372 @@ __global__ void __launch_bounds__(256, 2) k_edm_lines(EdmLinesArgs a)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Pipelined strip kernel of the MFMA modes (up to 128 dimensions): one
+// workgroup of four waves per CU.
+//
+// The tiles, operands and line-aligned stores are those of k_edm_lines, with
+// three differences.  The column operands of two tiles sit in LDS (2 x 68
+// KiB at 128 dimensions): the next tile's are loaded while this tile's
+// products run, with one barrier per tile.  A wave computes all four column
+// blocks of a tile at once (64 accumulators).  And the distances, selects
+// and stores of the previous tile (when it is this tile's left neighbour and
+// lies wholly in the domain, the usual case along a strip) are interleaved
+// with this tile's products in one instruction stream, a few rows per
+// k-step, so that the vector ALU and the stores work in the shadow of the
+// matrix cores (one wave per SIMD: nothing else would fill it).  Other
+// tiles (first of a strip, last of a strip, diagonal or last-row tiles) take
+// the same steps one after the other.
+//
+// Near pairs: d = sqrt(max(-2 acc, 0)) below sqrt(thr) (a square that
+// rounding made negative gives 0) are recomputed directly in FP32 after the
+// tile's stores.
+// ---------------------------------------------------------------------------
+template <int MAP, bool SPLIT, int S>
+__global__ void __launch_bounds__(256, 1) k_edm_pipe(EdmLinesArgs a)
+{
+    constexpr int P = SPLIT ? 2 : 1;
+    constexpr int KP = S * P;                   // operand planes (k-step, hi / lo)
+    constexpr int kGroup = edm_group_vecs(KP);  // frag vectors per group of 32 points
+    constexpr int kBuf = (KP + 1) * 4 * 64;     // vectors of one tile's column operands
+    constexpr int RPS = 16 / S;                 // rows of the previous tile per k-step
+    // column operands of two tiles: vector (plane p, block c, lane) of
+    // buffer b at b kBuf + (p 4 + c) 64 + lane, plane KP the norm step
+    __shared__ bf16x8 sB[2 * kBuf];
+
+    const int t = threadIdx.x, l = t & 63, lo = l & 31, hf = l >> 5;
+    const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int32_t n = a.n;
+    const float sthr = __builtin_sqrtf(a.thr);  // near: d < sqrt(thr)
+    // misalignment of the output array within a 128-byte line, in floats
+    const uint32_t amod = (uint32_t)(((uintptr_t)a.out >> 2) & 31u);
+
+    const uint32_t first = strip_first<MAP>(a.g, a.sg);
+    int32_t bi, bj;
+    int k = strip_next<MAP>(a.g, a.sg, first, 0, bi, bj);
+    if (k >= a.sg.G) return;  // the whole strip maps to no tile (uniform)
+    bi = __builtin_amdgcn_readfirstlane(bi);
+    bj = __builtin_amdgcn_readfirstlane(bj);
+
+    // the wave's row operands: row R0 + 32 w + (l & 31), half l >> 5, and
+    // its norm step
+    bf16x8 A[S][P];
+    bf16x8 Ax;
+    auto load_rows = [&](int32_t rbi) {
+        const int32_t r0 = 1 + rbi * kEdmTile + 32 * w + lo;
+        const bf16x8 *rowp = a.frag + (int64_t)(r0 >> 5) * kGroup + hf * 32 + (r0 & 31);
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int pl = 0; pl < P; ++pl) A[s][pl] = rowp[(s * P + pl) * 64];
+        Ax = rowp[(KP + 1) * 64];
+    };
+    // a tile's column operands into buffer b: wave w loads block w, every
+    // plane (1 KiB of contiguous frag each, one 16-byte load per lane)
+    auto stage = [&](int b, int32_t cbj) {
+        const bf16x8 *src = a.frag + (int64_t)(4 * cbj + w) * kGroup + l;
+#pragma unroll
+        for (int p = 0; p <= KP; ++p)
+            __builtin_amdgcn_global_load_lds(
+                (const __attribute__((address_space(1))) void *)(src + p * 64),
+                (__attribute__((address_space(3))) void *)(sB + b * kBuf + (p * 4 + w) * 64), 16, 0,
+                0);
+    };
+
+    // store geometry of a tile row, as in k_edm_lines
+    uint32_t offw[16];
+    uint32_t wbits = 0;
+    char *orow = nullptr;
+    int32_t R0 = 0;
+    auto set_rows = [&](int32_t rbi) {
+        R0 = 1 + rbi * kEdmTile;
+        const uint64_t TR0 = (uint64_t)R0 * (uint64_t)(R0 - 1) / 2;
+        orow = (char *)(a.out + TR0);
+        const uint32_t rmod = (uint32_t)(TR0 & 31u) + amod;
+        wbits = 0;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int32_t i = R0 + 32 * w + 8 * (r >> 2) + 4 * hf + (r & 3);
+            const uint32_t ro = (uint32_t)((i - R0) * (i + R0 - 1)) / 2u;
+            const uint32_t wrap = (uint32_t)(lo + (int32_t)((ro + rmod) & 31u) >= 32);
+            offw[r] = (ro + (uint32_t)lo - 32u * wrap) << 2;
+            wbits |= wrap << r;
+        }
+    };
+    auto dist = [](float acc) { return __builtin_amdgcn_sqrtf(fmaxf(-2.f * acc, 0.f)); };
+
+    // products of one k-step (or the norm step) into acc[0..3]
+    auto ext_step = [&](f32x16 (&acc)[4], int b) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const f32x16 z{};
+            acc[e] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ax, sB[b * kBuf + (KP * 4 + e) * 64 + l],
+                                                             z, 0, 0, 0);
+        }
+    };
+
+    load_rows(bi);
+    set_rows(bi);
+    stage(0, bj);
+    __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
+    lds_barrier();
+
+    f32x16 carry{};           // distances of the previous tile's block 3
+    uint32_t carry_near = 0;  // which of them are near (bit r)
+    bool carry_ok = false;    // carry holds the left neighbour's block 3
+    f32x16 accP[4];           // a deferred tile's accumulators (its left neighbour's
+    bool pend = false;        // epilogue runs in this tile's products)
+    int buf = 0;
+
+    // Epilogue of a tile from its accumulators, step by step (any tile):
+    // distances, stores (lines 0..3, line 4 when it ends its strip's run),
+    // near-pair recompute; leaves block 3 in carry and its near bits in
+    // carry_near.
+    auto epilogue = [&](f32x16 (&acc)[4], char *obt, int32_t CW, bool full, bool c_ok,
+                        bool tail_self) {
+        auto st = [&](int r, uint32_t k128, float v) { *(float *)((obt + offw[r]) + k128) = v; };
+        auto inside = [&](int r, int32_t jt) {
+            const int32_t i = R0 + 32 * w + 8 * (r >> 2) + 4 * hf + (r & 3);
+            return i < n && CW + jt >= 0 && CW + jt < i;
+        };
+        float mn = 3.4e38f;
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                acc[e][r] = dist(acc[e][r]);
+                mn = fminf(mn, acc[e][r]);
+            }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const bool wrap = (wbits >> r) & 1u;
+            const float L0 = wrap ? carry[r] : acc[0][r], L1 = wrap ? acc[0][r] : acc[1][r];
+            const float L2 = wrap ? acc[1][r] : acc[2][r], L3 = wrap ? acc[2][r] : acc[3][r];
+            if (full) {
+                if (c_ok || !wrap) st(r, 0u, L0);
+                st(r, 128u, L1);
+                st(r, 256u, L2);
+                st(r, 384u, L3);
+                if (tail_self && wrap) st(r, 512u, acc[3][r]);
+            } else {
+                const int32_t jt = lo - 32 * (int32_t)wrap;
+                if ((c_ok || !wrap) && inside(r, jt)) st(r, 0u, L0);
+                if (inside(r, jt + 32)) st(r, 128u, L1);
+                if (inside(r, jt + 64)) st(r, 256u, L2);
+                if (inside(r, jt + 96)) st(r, 384u, L3);
+                if (tail_self && wrap && inside(r, 96 + lo)) st(r, 512u, acc[3][r]);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        const uint32_t cn = c_ok ? carry_near : 0u;
+        carry_near = 0;
+        if (__any(mn < sthr || cn != 0u)) {
+            // rare: which squares are near (bit e 16 + r), then recompute
+            // them directly in FP32 over the values just stored
+            uint64_t mk = 0;
+#pragma unroll
+            for (int e = 3; e >= 0; --e)
+#pragma unroll
+                for (int r = 15; r >= 0; --r) mk = (mk << 1) | (uint64_t)(acc[e][r] < sthr);
+            carry_near = (uint32_t)(mk >> 48);
+            uint32_t mc = cn;
+            while (mk | mc) {
+                int r, jt;
+                if (mk) {
+                    const int b = __builtin_ctzll(mk);
+                    mk &= mk - 1;
+                    r = b & 15;
+                    jt = 32 * (b >> 4) + lo;
+                    // block 3's tail goes to the next tile unless this tile stores it
+                    if ((b >> 4) == 3 && ((wbits >> r) & 1u) && !tail_self) continue;
+                } else {
+                    r = __builtin_ctz(mc);
+                    mc &= mc - 1;
+                    if (!((wbits >> r) & 1u)) continue;  // not a carried value
+                    jt = lo - 32;
+                }
+                if (!inside(r, jt)) continue;
+                const int32_t i = R0 + 32 * w + 8 * (r >> 2) + 4 * hf + (r & 3);
+                const uint32_t ro = (uint32_t)((i - R0) * (i + R0 - 1)) / 2u;
+                *(float *)(obt + 4u * (ro + (uint32_t)jt)) =
+                    __builtin_amdgcn_sqrtf(direct_d2(a.x, a.ldx, a.d, i, CW + jt));
+            }
+            __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
+        }
+        carry = acc[3];
+    };
+
+    for (;;) {
+        int32_t nbi = 0, nbj = 0;
+        const int nk = strip_next<MAP>(a.g, a.sg, first, k + 1, nbi, nbj);
+        const bool more = nk < a.sg.G;
+        nbi = __builtin_amdgcn_readfirstlane(nbi);
+        nbj = __builtin_amdgcn_readfirstlane(nbj);
+        const bool right = more && nbi == bi && nbj == bj + 1;  // the next tile continues the row
+
+        const int32_t CW = bj * kEdmTile;
+        char *const obt = orow + 4 * (int64_t)CW;  // the tile's row R0, column 0
+        const bool full = CW + kEdmTile - 1 < R0 && R0 + kEdmTile - 1 < n;
+
+        // the next tile's columns into the other buffer (every wave is done
+        // with it: the barrier at the end of the previous tile)
+        if (more) stage(buf ^ 1, nbj);
+
+        f32x16 acc[4];
+        bool fused = false;
+        if (pend) {
+            // this tile's products with the left neighbour's epilogue (a
+            // full tile with its carry; its stores go to obt - 512)
+            fused = true;
+            char *const pobt = obt - 512;
+            float mn = 3.4e38f;
+            bf16x8 B[2][P][4];  // [slot][part of the k-step][block]
+            auto read_b = [&](int s, int slot) {
+#pragma unroll
+                for (int pl = 0; pl < P; ++pl)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        B[slot][pl][e] = sB[buf * kBuf + ((s * P + pl) * 4 + e) * 64 + l];
+            };
+            read_b(0, 0);
+            ext_step(acc, buf);
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const int sl = s & 1;
+                if (s + 1 < S) read_b(s + 1, sl ^ 1);
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    acc[e] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[s][0], B[sl][0][e], acc[e], 0, 0, 0);
+                __builtin_amdgcn_sched_barrier(0);
+                // distances of this step's rows of the previous tile
+#pragma unroll
+                for (int q = 0; q < RPS; ++q) {
+                    const int r = s * RPS + q;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        accP[e][r] = dist(accP[e][r]);
+                        mn = fminf(mn, accP[e][r]);
+                    }
+                }
+                __builtin_amdgcn_sched_barrier(0);
+                if constexpr (SPLIT) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        acc[e] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[s][0], B[sl][1][e], acc[e], 0, 0, 0);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                // their four lines
+#pragma unroll
+                for (int q = 0; q < RPS; ++q) {
+                    const int r = s * RPS + q;
+                    const bool wrap = (wbits >> r) & 1u;
+                    char *const rp = pobt + offw[r];
+                    *(float *)(rp + 0u) = wrap ? carry[r] : accP[0][r];
+                    *(float *)(rp + 128u) = wrap ? accP[0][r] : accP[1][r];
+                    *(float *)(rp + 256u) = wrap ? accP[1][r] : accP[2][r];
+                    *(float *)(rp + 384u) = wrap ? accP[2][r] : accP[3][r];
+                }
+                __builtin_amdgcn_sched_barrier(0);
+                if constexpr (SPLIT) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        acc[e] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[s][P - 1], B[sl][0][e], acc[e], 0, 0, 0);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+            // near pairs of the previous tile (rare), after its stores
+            const uint32_t cn = carry_near;
+            carry_near = 0;
+            if (__any(mn < sthr || cn != 0u)) {
+                uint64_t mk = 0;
+#pragma unroll
+                for (int e = 3; e >= 0; --e)
+#pragma unroll
+                    for (int r = 15; r >= 0; --r) mk = (mk << 1) | (uint64_t)(accP[e][r] < sthr);
+                carry_near = (uint32_t)(mk >> 48);
+                uint32_t mc = cn;
+                const int32_t PCW = CW - kEdmTile;
+                while (mk | mc) {
+                    int r, jt;
+                    if (mk) {
+                        const int b = __builtin_ctzll(mk);
+                        mk &= mk - 1;
+                        r = b & 15;
+                        jt = 32 * (b >> 4) + lo;
+                        if ((b >> 4) == 3 && ((wbits >> r) & 1u)) continue;  // carried on
+                    } else {
+                        r = __builtin_ctz(mc);
+                        mc &= mc - 1;
+                        if (!((wbits >> r) & 1u)) continue;
+                        jt = lo - 32;
+                    }
+                    const int32_t i = R0 + 32 * w + 8 * (r >> 2) + 4 * hf + (r & 3);
+                    const uint32_t ro = (uint32_t)((i - R0) * (i + R0 - 1)) / 2u;
+                    *(float *)(pobt + 4u * (ro + (uint32_t)jt)) =
+                        __builtin_amdgcn_sqrtf(direct_d2(a.x, a.ldx, a.d, i, PCW + jt));
+                }
+                __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
+                fused = false;  // the wait drained the stores: count no younger operations
+            }
+            carry = accP[3];
+        } else {
+            ext_step(acc, buf);
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                bf16x8 Bh[4], Bl[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    Bh[e] = sB[buf * kBuf + ((s * P) * 4 + e) * 64 + l];
+                    if constexpr (SPLIT) Bl[e] = sB[buf * kBuf + ((s * P + 1) * 4 + e) * 64 + l];
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    acc[e] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[s][0], Bh[e], acc[e], 0, 0, 0);
+                if constexpr (SPLIT) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        acc[e] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[s][0], Bl[e], acc[e], 0, 0, 0);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        acc[e] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[s][P - 1], Bh[e], acc[e], 0, 0, 0);
+                }
+            }
+        }
+        // this tile: deferred to the next tile's products when that tile
+        // continues the row and this one is full with its carry; else now
+        const bool defer = right && full && carry_ok;
+        bool waited = false;
+        if (defer) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) accP[e] = acc[e];
+        } else {
+            epilogue(acc, obt, CW, full, carry_ok, !right);
+            waited = true;  // counted as such below (stores of any number)
+        }
+        pend = defer;
+        carry_ok = right;
+        if (!more) break;
+
+        // The next tile's columns are complete in every wave, and every
+        // wave is done with this tile's buffer.  A fused tile issued its 64
+        // stores after those loads (so at most 63 younger operations may
+        // remain); otherwise wait for everything.
+        if (fused && !waited) __builtin_amdgcn_s_waitcnt(waitcnt_vm(63));
+        else __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
+        lds_barrier();
+        if (nbi != bi) {
+            load_rows(nbi);
+            set_rows(nbi);
+            __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
+        }
+        k = nk;
+        bi = nbi;
+        bj = nbj;
+        buf ^= 1;
+    }
+}
+
 // Workgroups that share a group of strips (1: each workgroup's tiles are
 // consecutive, so the carry passes from tile to tile).
 constexpr int32_t kEdmStripGroup = 1;
@@ -1122,7 +1488,10 @@ static void edm_lines_launch(const tri_plan *p, const EdmLinesArgs &a0, hipStrea
     EdmLinesArgs a = a0;
     dim3 grid;
     a.sg = strip_grid(MAP, a.g.m, a.g.flags, a.g.T, p->gx, p->gy, strip_len(p), kEdmStripGroup, grid);
-    k_edm_lines<MAP, SPLIT, S><<<grid, 256, 0, s>>>(a);
+    if (p->flags & TRI_FLAG_EDM_PIPE)
+        k_edm_pipe<MAP, SPLIT, S><<<grid, 256, 0, s>>>(a);
+    else
+        k_edm_lines<MAP, SPLIT, S><<<grid, 256, 0, s>>>(a);
 }
 
 template <bool SPLIT, int S>

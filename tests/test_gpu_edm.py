@@ -200,6 +200,34 @@ def test_edm_mfma_strips(mode, map_name, flags, strip):
 
 
 @pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("map_name,flags", [("lambda", 0x1400), ("lambda", 0x1001), ("lambda", 0x2501),
+                                            ("lambda", 0x0300), ("lambda", 0x0100), ("bb", 0x0400),
+                                            ("rb", 0x0400), ("rec", 0x0300)])
+def test_edm_pipe_kernel(mode, map_name, flags):
+    """The pipelined kernel (TRI_FLAG_EDM_PIPE: one workgroup per CU, two
+    tiles' column operands in LDS, each tile's stores inside the next
+    tile's products): whole rows against the FP64 oracle, and bit for bit
+    the line kernel's result, at n where strips start and end mid-row, the
+    last tile row is ragged and d takes all three k-step counts."""
+    tm = _tm()
+    cases = ((1025, 128), (2049, 33)) if map_name == "rec" else ((900, 128), (1500, 4), (2100, 40),
+                                                                  (1300, 64))
+    for n, d in cases:
+        X, _ = inputs.points(n, d, dup_frac=0.02, seed=5400 + n + d)
+        p = tm.Plan(n, 128, map_name, include_diag=False, flags=flags | tm.FLAG_EDM_PIPE)
+        note("edm pipe", mode, map_name, flags, n, d)
+        got = host(_edm_mfma(tm, p, X, mode))
+        assert (got >= 0).all()
+        if mode == 1:
+            _check_rows(X, got, list(range(n)), MFMA_TOL[mode])
+        else:
+            _check_rows_bf16(X, got, list(range(n)))
+        q = tm.Plan(n, 128, map_name, include_diag=False, flags=flags)
+        ref = host(_edm_mfma(tm, q, X, mode))
+        assert (got.view(np.uint32) == ref.view(np.uint32)).all()
+
+
+@pytest.mark.parametrize("mode", [1, 2])
 def test_edm_mfma_beyond_128_dims(mode):
     """d above 128: the chunked kernel (row-major planes, 64 dimensions per
     LDS chunk)."""

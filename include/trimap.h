@@ -89,6 +89,14 @@ enum {
  * operands of two tiles in LDS and each tile's stores interleaved with the
  * next tile's products. */
 #define TRI_FLAG_EDM_PIPE 0x4000u
+/* Plan flag for the elementwise strip kernels (tiles 16 and 32, strips of
+ * G >= 4 tiles): two-row bands.  A strip holds G / 2 columns of two
+ * consecutive tile rows (lambda) or grid rows (BB, RB, REC), so that a
+ * workgroup meets each 2 x 2 block of tiles at once; every tile is still
+ * located by the map on its own (under lambda, tile (2p + r, c) is omega
+ * T_{2p+r} + c).  TRI_FLAG_STRIP_COLS and TRI_FLAG_STRIP_ALIGN take
+ * precedence.  The distance map and the stencil reject it. */
+#define TRI_FLAG_STRIP_BAND 0x8000u
 
 /* Elementwise bodies. */
 enum {

@@ -130,6 +130,10 @@ static std::vector<Candidate> candidates(int workload, int64_t n)
                 c.push_back({t, TRI_MAP_LAMBDA, st | (uint32_t)TRI_FLAG_XCD_SWIZZLE});
                 c.push_back({t, TRI_MAP_LAMBDA, st | (uint32_t)TRI_FLAG_STRIP_ALIGN});
                 c.push_back({t, TRI_MAP_LAMBDA, st | (uint32_t)(TRI_FLAG_STRIP_ALIGN | TRI_FLAG_ORDER_PAIRS)});
+                // two-row bands (2 x 2 tile blocks at tile 16)
+                c.push_back({t, TRI_MAP_BB, st | (uint32_t)TRI_FLAG_STRIP_BAND});
+                c.push_back({t, TRI_MAP_LAMBDA, st | (uint32_t)TRI_FLAG_STRIP_BAND});
+                c.push_back({t, TRI_MAP_LAMBDA, st | (uint32_t)(TRI_FLAG_STRIP_BAND | TRI_FLAG_ORDER_PAIRS)});
             }
     if (workload == TRI_TUNE_EDM_BF16X3)  // column-major strips of 16 and 32 tiles, both schedules
         for (uint32_t st : {(uint32_t)TRI_FLAG_STRIP(4), (uint32_t)TRI_FLAG_STRIP(5)}) {

@@ -1552,6 +1552,8 @@ static tri_status edm_check(const tri_plan *p, int64_t d, int mode)
     if (p->diag) return fail(TRI_E_INVAL, "tri_edm: the plan must exclude the diagonal");
     if (p->map == TRI_MAP_UTM) return fail(TRI_E_UNSUPPORTED, "tri_edm: UTM is not supported");
     if (d < 1 || d > 4096) return fail(TRI_E_RANGE, "tri_edm: d = %lld not in [1, 4096]", (long long)d);
+    if (p->flags & TRI_FLAG_STRIP_BAND)
+        return fail(TRI_E_UNSUPPORTED, "tri_edm: two-row band strips are for the elementwise kernels");
     if (mode == TRI_EDM_FP32) {
         if (p->tile != 16 && p->tile != 32 && p->tile != 64 && p->tile != 128)
             return fail(TRI_E_UNSUPPORTED, "tri_edm: FP32 mode needs tile 16, 32, 64 or 128");

@@ -360,6 +360,143 @@ __global__ void __launch_bounds__(256) k_axpyt_strip_pairs(ElemArgs p, StripGrid
     }
 }
 
+// Tile 16 in two-row band strips (TRI_FLAG_STRIP_BAND): a wave moves a
+// 2 x 2 block of tiles at once (tiles 4 q .. 4 q + 3 of the strip, rows
+// 2 p and 2 p + 1, columns c and c + 1, q = w, w + 4, ...), each of the
+// four located by the map on its own.  Within the block every row of X and
+// C is a whole 128-byte line across two tiles, and so is every row of the
+// mirror block of Y across the two tile rows; the block moves as one
+// 32 x 32 transpose through the wave's LDS buffer.  Tile (r, c) of the
+// block is tile 4 q + 2 c + r; a lane's 16-byte vector at block row R,
+// column C belongs to tile (R / 16, C / 16) for X and C and to tile
+// (C / 16, R / 16) for Y, whose rows are the tiles' columns.  A missing
+// tile (above the diagonal, past the last row or the strip) loads from
+// tile (0, 0) and stores nothing.  Same arithmetic and operation order as
+// k_axpyt.
+template <int MAP>
+__global__ void __launch_bounds__(256) k_axpyt_strip_quads(ElemArgs p, StripGrid sg)
+{
+    constexpr int TILE = 16, BLK = 32, VPR = BLK / 4, RPP = 64 / VPR, PASSES = BLK / RPP;
+    __shared__ float ysh[4][BLK][BLK + 1];
+    const int l = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    float (*ys)[BLK + 1] = ysh[w];
+    const int tr = l / VPR, tc = (l % VPR) * 4;  // block row (pass 0), block column
+    const int lc = tc / TILE, tcl = tc % TILE;    // the lane's tile column, column in it
+    const int32_t n = p.n;
+    const int64_t ld = p.ld;
+    const float *X = (const float *)p.x;
+    const float *Y = (const float *)p.y;
+    float *C = (float *)p.c;
+    const float a = p.a;
+    const int32_t cmax = (int32_t)(ld - 4);
+    const uint32_t first = strip_first<MAP>(p.g, sg);
+
+    struct Quad {
+        int32_t bi[2][2], bj[2][2];  // [r][c]
+        bool v[2][2];
+    };
+    auto locate = [&](int q, Quad &Q) {
+        bool any = false;
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const int k = 4 * q + 2 * c + r;
+                int32_t bi = 0, bj = 0;
+                bool v = k < sg.G && strip_tile<MAP>(p.g, sg, first, k, bi, bj);
+                if (!v) bi = bj = 0;
+                Q.bi[r][c] = __builtin_amdgcn_readfirstlane(bi);
+                Q.bj[r][c] = __builtin_amdgcn_readfirstlane(bj);
+                Q.v[r][c] = v;
+                any = any || v;
+            }
+        return any;
+    };
+    f4 xv[PASSES], yv[PASSES];
+    auto load = [&](const Quad &Q) {
+#pragma unroll
+        for (int ps = 0; ps < PASSES; ++ps) {
+            const int R = tr + ps * RPP, rt = R / TILE, rl = R % TILE;
+            // X: tile (rt, lc), row rl, columns tcl ..
+            const int32_t bi = lc ? Q.bi[rt][1] : Q.bi[rt][0];
+            const int32_t bj = lc ? Q.bj[rt][1] : Q.bj[rt][0];
+            const bool full = (bj < bi) && (bi * TILE + TILE <= n);
+            int32_t i = bi * TILE + rl, jc = bj * TILE + tcl;
+            if (!full) {
+                i = i < n ? i : n - 1;
+                jc = jc < cmax ? jc : cmax;
+            }
+            xv[ps] = __builtin_nontemporal_load((const f4 *)(X + (int64_t)i * ld + jc));
+        }
+#pragma unroll
+        for (int ps = 0; ps < PASSES; ++ps) {
+            const int R = tr + ps * RPP, rt = R / TILE, rl = R % TILE;
+            // Y: the mirror of tile (lc, rt): Y row bj * 16 + rl, columns bi * 16 + tcl ..
+            const int32_t bi = rt ? Q.bi[lc][1] : Q.bi[lc][0];
+            const int32_t bj = rt ? Q.bj[lc][1] : Q.bj[lc][0];
+            const bool full = (bj < bi) && (bi * TILE + TILE <= n);
+            int32_t jr = bj * TILE + rl, ic = bi * TILE + tcl;
+            if (!full) {
+                jr = jr < n ? jr : n - 1;
+                ic = ic < cmax ? ic : cmax;
+            }
+            yv[ps] = __builtin_nontemporal_load((const f4 *)(Y + (int64_t)jr * ld + ic));
+        }
+    };
+
+    int q = w;
+    Quad Q;
+    bool v = locate(q, Q);
+    while (4 * q < sg.G && !v) v = locate(q += 4, Q);
+    if (4 * q >= sg.G) return;
+    load(Q);
+    while (4 * q < sg.G) {
+#pragma unroll
+        for (int ps = 0; ps < PASSES; ++ps) {
+            const int R = tr + ps * RPP;
+            ys[R][tc + 0] = yv[ps].x;
+            ys[R][tc + 1] = yv[ps].y;
+            ys[R][tc + 2] = yv[ps].z;
+            ys[R][tc + 3] = yv[ps].w;
+        }
+        f4 xc[PASSES];
+#pragma unroll
+        for (int ps = 0; ps < PASSES; ++ps) xc[ps] = xv[ps];
+        const Quad cq = Q;
+        // the next block's loads, in flight during this block's stores
+        int nq = q + 4;
+        bool nv = false;
+        while (4 * nq < sg.G && !(nv = locate(nq, Q))) nq += 4;
+        if (4 * nq < sg.G) load(Q);
+#pragma unroll
+        for (int ps = 0; ps < PASSES; ++ps) {
+            const int R = tr + ps * RPP, rt = R / TILE, rl = R % TILE;
+            const int32_t bi = lc ? cq.bi[rt][1] : cq.bi[rt][0];
+            const int32_t bj = lc ? cq.bj[rt][1] : cq.bj[rt][0];
+            const bool tv = lc ? cq.v[rt][1] : cq.v[rt][0];
+            const bool full = tv && (bj < bi) && (bi * TILE + TILE <= n);
+            const int32_t i = bi * TILE + rl, jc = bj * TILE + tcl;
+            if (!tv || (!full && (i >= n || jc > i))) continue;
+            float *crow = C + (int64_t)i * ld + jc;
+            f4 o;
+            o.x = __fadd_rn(__fmul_rn(a, xc[ps].x), ys[tc + 0][R]);
+            o.y = __fadd_rn(__fmul_rn(a, xc[ps].y), ys[tc + 1][R]);
+            o.z = __fadd_rn(__fmul_rn(a, xc[ps].z), ys[tc + 2][R]);
+            o.w = __fadd_rn(__fmul_rn(a, xc[ps].w), ys[tc + 3][R]);
+            if (full || jc + 3 <= i) {
+                __builtin_nontemporal_store(o, (f4 *)crow);
+            } else {  // the vector straddles the diagonal
+                crow[0] = o.x;
+                if (jc + 1 <= i) crow[1] = o.y;
+                if (jc + 2 <= i) crow[2] = o.z;
+            }
+        }
+        q = nq;
+        (void)nv;
+    }
+}
+
 template <int MAP, int TILE, bool VECTOR>
 __global__ void __launch_bounds__((ElemShape<TILE, VECTOR>::NT)) k_xormul(ElemArgs p)
 {
@@ -533,9 +670,10 @@ static void launch_axpyt_strip(const tri_plan *p, const ElemArgs &args, hipStrea
     dim3 grid;
     const StripGrid sg = strip_grid(MAP, args.g.m, args.g.flags, args.g.T, p->gx, p->gy,
                                     strip_flag_len(p->flags), 1, grid);
-    if constexpr (TILE == 16)
-        k_axpyt_strip_pairs<MAP><<<grid, 256, 0, s>>>(args, sg);
-    else
+    if constexpr (TILE == 16) {
+        if (strip_band(p->flags)) k_axpyt_strip_quads<MAP><<<grid, 256, 0, s>>>(args, sg);
+        else k_axpyt_strip_pairs<MAP><<<grid, 256, 0, s>>>(args, sg);
+    } else
         k_axpyt_strip<MAP, TILE><<<grid, 256, 0, s>>>(args, sg);
 }
 
@@ -595,6 +733,8 @@ extern "C" tri_status tri_launch_elementwise(const tri_plan *p, int op, const vo
         return fail(TRI_E_INVAL, "tri_launch_elementwise: NULL buffer");
     if (ld < p->n) return fail(TRI_E_INVAL, "tri_launch_elementwise: ld %lld < n %lld",
                                (long long)ld, (long long)p->n);
+    if (strip_band(p->flags) && strip_flag_len(p->flags) && strip_flag_len(p->flags) < 4)
+        return fail(TRI_E_INVAL, "tri_launch_elementwise: two-row band strips need G >= 4 tiles");
     const uintptr_t cx = (uintptr_t)c, xx = (uintptr_t)x, yx = (uintptr_t)y;
     if ((cx | xx | yx) & 3) return fail(TRI_E_INVAL, "tri_launch_elementwise: unaligned buffer");
     if (op == TRI_OP_EDM4_F32 && (xx & 15))

@@ -276,12 +276,23 @@ __device__ __forceinline__ bool tile_of_block(const TileGrid &g, int32_t &bi, in
 // row group a = floor((sqrt(8 s / G + 1) - 1) / 2) (lambda on s / G, with
 // the integer correction), row a G + o / (a + 1), strip o mod (a + 1), for
 // o = s - G a (a + 1) / 2.
+//
+// Two-row bands (TRI_FLAG_STRIP_BAND, K = 1, G >= 4): a strip holds G / 2
+// columns of two consecutive tile rows (lambda) or grid rows (BB, RB,
+// REC), and its tile k lies in row 2 p + (k & 1), column c0 + (k >> 1), so
+// that tiles 4 q .. 4 q + 3 form a 2 x 2 block.  Under lambda the bands
+// are row pairs p (rows 2 p, 2 p + 1, columns 0 .. 2 p + 1), cut at
+// multiples of H = G / 2 columns: pair p has ceil((p + 1) / Q) strips, Q =
+// H / 2, which is the aligned order above with rows read as row pairs and
+// G as Q; the two tiles of column c are omega T_2p + c and T_2p+1 + c,
+// each mapped by lambda on its own.
 // ---------------------------------------------------------------------------
 struct StripGrid {
     uint32_t strips;  // lambda: workgroups in the launch (gridDim.x)
     int32_t G;        // tiles per workgroup
     int32_t K;        // workgroups per group
     int32_t gx;       // BB / RB / REC: columns of the map's grid
+    int32_t gy;       // BB / RB / REC: rows of the map's grid
 };
 
 __host__ __device__ __forceinline__ uint64_t strip_cols_prefix(uint32_t c, uint32_t m, uint32_t G)
@@ -321,13 +332,35 @@ __device__ __forceinline__ uint32_t strip_align_first(uint32_t s, uint32_t G)
     return (uint32_t)(i * (i + 1) / 2 + c * G);
 }
 
+// First omega of two-row band strip s under lambda (s below the strip
+// count, G >= 4): the omega of the band's top-left tile, row 2 p, column
+// c H.
+__device__ __forceinline__ uint32_t strip_band_first(uint32_t s, uint32_t G)
+{
+    const uint32_t H = G / 2, Q = G / 4;
+    const double x = 8.0 * (double)s / (double)Q + 1.0;
+    uint64_t a = (uint64_t)((__builtin_sqrt(x) - 1.0) * 0.5);
+    while (a > 0 && (uint64_t)Q * a * (a + 1) / 2 > s) --a;
+    while ((uint64_t)Q * (a + 1) * (a + 2) / 2 <= s) ++a;
+    const uint64_t o = s - (uint64_t)Q * a * (a + 1) / 2;
+    const uint64_t pr = a * Q + o / (a + 1), c = o % (a + 1);
+    return (uint32_t)(pr * (2 * pr + 1) + c * H);
+}
+
+// True when a plan's flags select the two-row band order (the column-major
+// and row-major aligned orders take precedence).
+__host__ __device__ __forceinline__ bool strip_band(uint32_t flags)
+{
+    return (flags & TRI_FLAG_STRIP_BAND) && !(flags & (TRI_FLAG_STRIP_COLS | TRI_FLAG_STRIP_ALIGN));
+}
+
 // Launch grid of a strip kernel for a plan's map, tile grid (m tiles a side,
-// flags) and map grid (gx, gy).
+// flags) and map grid (gx, gy).  The two-row band order needs G >= 4.
 __host__ __forceinline__ StripGrid strip_grid(int map, int32_t m, uint32_t flags, uint64_t T,
                                               uint32_t gx, uint32_t gy, int32_t G, int32_t K,
                                               dim3 &grid)
 {
-    StripGrid s{0u, G, K, (int32_t)gx};
+    StripGrid s{0u, G, K, (int32_t)gx, (int32_t)gy};
     const uint64_t span = (uint64_t)G * (uint64_t)K;  // tile numbers per group
     if (map == TRI_MAP_LAMBDA && (flags & TRI_FLAG_STRIP_COLS)) {
         s.K = 1;
@@ -337,6 +370,14 @@ __host__ __forceinline__ StripGrid strip_grid(int map, int32_t m, uint32_t flags
         s.K = 1;
         s.strips = (uint32_t)strip_align_prefix((uint32_t)m, (uint32_t)G);
         grid = dim3(s.strips, 1);
+    } else if (strip_band(flags) && map == TRI_MAP_LAMBDA) {
+        s.K = 1;
+        s.strips = (uint32_t)strip_align_prefix((uint32_t)((m + 1) / 2), (uint32_t)(G / 4));
+        grid = dim3(s.strips, 1);
+    } else if (strip_band(flags)) {
+        s.K = 1;
+        const uint32_t H = (uint32_t)G / 2;
+        grid = dim3((gx + H - 1) / H, (gy + 1) / 2);
     } else if (map == TRI_MAP_LAMBDA) {
         s.strips = (uint32_t)((T + span - 1) / span * (uint64_t)K);
         grid = dim3(s.strips, 1);
@@ -364,8 +405,10 @@ __device__ __forceinline__ uint32_t strip_first(const TileGrid &g, const StripGr
         else if (g.flags & TRI_FLAG_ORDER_PAIRS) G2 = (grp & 1) ? ng - 1 - (grp >> 1) : (grp >> 1);
         if (g.flags & TRI_FLAG_STRIP_COLS) return strip_cols_first(G2, (uint32_t)g.m, (uint32_t)sg.G);
         if (g.flags & TRI_FLAG_STRIP_ALIGN) return strip_align_first(G2, (uint32_t)sg.G);
+        if (g.flags & TRI_FLAG_STRIP_BAND) return strip_band_first(G2, (uint32_t)sg.G);
         return G2 * K * (uint32_t)sg.G + k;
     } else {
+        if (strip_band(g.flags)) return L * (uint32_t)(sg.G / 2);
         const uint32_t K = (uint32_t)sg.K;
         return (L / K) * K * (uint32_t)sg.G + L % K;
     }
@@ -379,17 +422,32 @@ __device__ __forceinline__ bool strip_tile(const TileGrid &g, const StripGrid &s
                                            int k, int32_t &bi, int32_t &bj)
 {
     if constexpr (MAP == MAP_LAMBDA) {
-        const uint32_t w = first + (uint32_t)k * (uint32_t)sg.K;
-        if (w >= (uint32_t)g.T) return false;
-        if (g.T <= (1ull << 24)) lambda_tile_24(w, bi, bj);
-        else lambda_tile_32(w, bi, bj);
+        uint64_t w = first + (uint64_t)k * (uint32_t)sg.K;
+        int kc = k;  // the tile's column offset within its strip
+        if (strip_band(g.flags)) {
+            // column c0 + k / 2 of row 2 p + (k & 1): T_2p+1 = T_2p + 2 p + 1
+            int32_t r0, c0;
+            if (g.T <= (1ull << 24)) lambda_tile_24(first, r0, c0);
+            else lambda_tile_32(first, r0, c0);
+            kc = k >> 1;
+            w = first + (uint64_t)kc + (uint64_t)(k & 1) * (uint32_t)(r0 + 1);
+        }
+        if (w >= g.T) return false;
+        if (g.T <= (1ull << 24)) lambda_tile_24((uint32_t)w, bi, bj);
+        else lambda_tile_32((uint32_t)w, bi, bj);
         // an aligned strip ends with its row: tile k of the strip has
-        // column bj0 + k >= k, the next row's tiles columns below k
-        if ((g.flags & (TRI_FLAG_STRIP_COLS | TRI_FLAG_STRIP_ALIGN)) && bj < k) return false;
+        // column bj0 + kc >= kc, the next row's tiles columns below kc
+        if ((g.flags & (TRI_FLAG_STRIP_COLS | TRI_FLAG_STRIP_ALIGN | TRI_FLAG_STRIP_BAND)) && bj < kc)
+            return false;
     } else {
-        const int32_t bx = (int32_t)first + k * sg.K;
+        int32_t bx = (int32_t)first + k * sg.K, by = (int32_t)blockIdx.y;
+        if (strip_band(g.flags)) {
+            bx = (int32_t)first + (k >> 1);
+            by = 2 * by + (k & 1);
+            if (by >= sg.gy) return false;
+        }
         if (bx >= sg.gx) return false;
-        if (!tile_at_xy<MAP>(g, bx, (int32_t)blockIdx.y, bi, bj)) return false;
+        if (!tile_at_xy<MAP>(g, bx, by, bi, bj)) return false;
     }
     return (uint32_t)bi < (uint32_t)g.m && (uint32_t)bj <= (uint32_t)bi;
 }

@@ -55,11 +55,12 @@ static TileGrid tile_grid(const tri_plan *p)
     uint32_t f = p->flags;
     if (p->map == TRI_MAP_LAMBDA && p->gy == 1 && (uint64_t)p->gx == (uint64_t)p->T &&
         p->T <= (1ll << 24) &&
-        (f & ~(uint32_t)(TRI_FLAG_XCD_SWIZZLE | TRI_FLAG_STRIP_MASK | TRI_FLAG_STRIP_COLS | TRI_FLAG_STRIP_ALIGN | TRI_FLAG_EDM_PIPE)) == 0)
+        (f & ~(uint32_t)(TRI_FLAG_XCD_SWIZZLE | TRI_FLAG_STRIP_MASK | TRI_FLAG_STRIP_COLS | TRI_FLAG_STRIP_ALIGN |
+                        TRI_FLAG_STRIP_BAND | TRI_FLAG_EDM_PIPE)) == 0)
         f |= kLambda24;
     else if (p->map == TRI_MAP_LAMBDA && p->gy > 1 && p->gx == (1u << 16) &&
              (f & ~(uint32_t)(TRI_FLAG_STRIP_MASK | TRI_FLAG_STRIP_COLS | TRI_FLAG_STRIP_ALIGN |
-                             TRI_FLAG_EDM_PIPE)) == 0 && p->T < (1ll << 32))
+                             TRI_FLAG_STRIP_BAND | TRI_FLAG_EDM_PIPE)) == 0 && p->T < (1ll << 32))
         f |= kLambda32;
     return TileGrid{(int32_t)p->m, f, (uint64_t)p->T};
 }
@@ -144,7 +145,7 @@ tri_status tri_map_plan(tri_plan **out, int64_t n, int tile, int map, int includ
                             TRI_FLAG_ORDER_REVERSE | TRI_FLAG_ORDER_PAIRS |
                             TRI_FLAG_LIFE_TEMPORAL | TRI_FLAG_SQRT_NEWTON |
                             TRI_FLAG_SQRT_EPS | TRI_FLAG_STRIP_MASK | TRI_FLAG_STRIP_COLS |
-                            TRI_FLAG_STRIP_ALIGN | TRI_FLAG_EDM_PIPE))
+                            TRI_FLAG_STRIP_ALIGN | TRI_FLAG_EDM_PIPE | TRI_FLAG_STRIP_BAND))
         return fail(TRI_E_INVAL, "tri_map_plan: unknown flags 0x%x", flags);
     if (((flags & TRI_FLAG_STRIP_MASK) >> 8) > 6)
         return fail(TRI_E_INVAL, "tri_map_plan: strip length beyond 32 tiles (flags 0x%x)", flags);

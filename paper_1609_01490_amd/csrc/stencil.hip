@@ -402,7 +402,9 @@ extern "C" tri_status tri_launch_stencil(const tri_plan *p, uint8_t *cur, uint8_
         return fail(TRI_E_UNSUPPORTED, "tri_launch_stencil: tile %d > 64", p->tile);
     if (p->map == TRI_MAP_UTM && (p->flags & TRI_FLAG_LIFE_TEMPORAL))
         return fail(TRI_E_UNSUPPORTED, "tri_launch_stencil: UTM has no tile for temporal blocking");
-    if (steps < 0) return fail(TRI_E_INVAL, "tri_launch_stencil: steps < 0");
+    if (p->flags & TRI_FLAG_STRIP_BAND)
+        return fail(TRI_E_UNSUPPORTED, "tri_launch_stencil: two-row band strips are for the elementwise kernels");
+        if (steps < 0) return fail(TRI_E_INVAL, "tri_launch_stencil: steps < 0");
     if (p->n == 0 || steps == 0) return TRI_OK;
     if (!cur || !nxt || cur == nxt) return fail(TRI_E_INVAL, "tri_launch_stencil: bad buffers");
     if (ld < p->n || ld % 4) return fail(TRI_E_INVAL, "tri_launch_stencil: ld must be >= n and a multiple of 4");

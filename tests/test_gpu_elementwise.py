@@ -75,14 +75,16 @@ def test_axpyt_f32_bit_exact(map_name, tile):
 @pytest.mark.parametrize("tile", [16, 32])
 @pytest.mark.parametrize("strip,flags", [(0, 0), (2, 0), (4, 0), (5, 0), (4, 16), (4, 1),
                                          (4, 0x1000), (3, 0x1001), (2, 0x2000), (3, 0x2010),
-                                         (5, 0x2001)])
+                                         (5, 0x2001), (2, 0x8000), (4, 0x8000), (5, 0x8010),
+                                         (3, 0x8001), (3, 0x9000)])
 def test_axpyt_f32_strips_bit_exact(map_name, tile, strip, flags):
     """Workgroups of four waves walking strips of 1, 4, 16 and 32 tiles (each
     wave every fourth tile, its next tile's loads in flight), in row order
-    or aligned to tile rows (column-major 0x1000, row-major 0x2000) and
-    under the lambda orders: bit-exact at ragged
-    n with 16-byte rows, the upper part untouched."""
-    if map_name != "lambda" and flags:
+    or aligned to tile rows (column-major 0x1000, row-major 0x2000), over
+    two-row bands (0x8000: at tile 16 a wave moves 2 x 2 blocks of tiles)
+    and under the lambda orders: bit-exact at ragged n with 16-byte rows,
+    the upper part untouched."""
+    if map_name != "lambda" and flags & ~0x8000:
         pytest.skip("orders and column-major strips are lambda flags")
     tm = _tm()
     for n in (1, 17, 100, 257, 300, 1024, 1500):
@@ -99,6 +101,27 @@ def test_axpyt_f32_strips_bit_exact(map_name, tile, strip, flags):
         p.elementwise(tm.OP_AXPYT_F32, dev(X), dev(Y), c, ld=ld, a=float(a))
         got = host(c)
         assert (got.view(np.uint32) == exp.view(np.uint32)).all(), (map_name, tile, strip, flags, n)
+
+
+def test_band_strips_need_four_tiles():
+    """Two-row band strips need strips of at least 4 tiles in the
+    elementwise kernels; the distance map and the stencil refuse them."""
+    import torch
+    tm = _tm()
+    n = 64
+    a, X, Y, C0 = inputs.f32_elementwise(n, seed=7, ld=n)
+    c = dev(C0)
+    p = tm.Plan(n, 16, "lambda", flags=tm.FLAG_STRIP_BAND | tm.FLAG_STRIP(1))
+    with pytest.raises(tm.TrimapError):
+        p.elementwise(tm.OP_AXPYT_F32, dev(X), dev(Y), c, ld=n, a=float(a))
+    pts = torch.rand((n, 4), device="cuda")
+    out = torch.empty(n * (n - 1) // 2, device="cuda")
+    with pytest.raises(tm.TrimapError):
+        tm.Plan(n, 16, "lambda", include_diag=False,
+                flags=tm.FLAG_STRIP_BAND | tm.FLAG_STRIP(2)).edm(pts, out, mode=tm.EDM_FP32)
+    g = torch.zeros((n, n), dtype=torch.uint8, device="cuda")
+    with pytest.raises(tm.TrimapError):
+        tm.Plan(n, 16, "lambda", flags=tm.FLAG_STRIP_BAND | tm.FLAG_STRIP(2)).stencil(g, g.clone(), 1)
 
 
 def test_empty_domain_is_a_no_op():

@@ -287,11 +287,21 @@ __device__ __forceinline__ void life_bits_wave_body(const LifeTile &p, int32_t b
     // the update's word layout: lane = 4 * band + column, and band b owns
     // staged rows b * RB .. b * RB + RB - 1 of one word column
     const int wc = lane & 3, rb0 = (lane >> 2) * RB;
+    // a tile whose staged window (rows i0 - K .. i0 + 63 + K, the four
+    // words' cells j0 - 32 .. j0 + 95) lies inside the domain needs no
+    // masks: every word then has 0 <= j <= i for all its cells
+    static_assert(2 * T >= 96 + K, "inner tiles are two tile columns off the diagonal");
+    const bool inner = bj >= 1 && bi - bj >= 2 && i0 + T + K <= n;
     uint32_t msk[RB];
+    if (inner) {
 #pragma unroll
-    for (int k = 0; k < RB; ++k) {
-        const int r = rb0 + k;
-        msk[k] = r < S::R ? life_bits_mask(i0 - K + r, j0 - 32 + 32 * wc, n) : 0u;
+        for (int k = 0; k < RB; ++k) msk[k] = rb0 + k < S::R ? ~0u : 0u;
+    } else {
+#pragma unroll
+        for (int k = 0; k < RB; ++k) {
+            const int r = rb0 + k;
+            msk[k] = r < S::R ? life_bits_mask(i0 - K + r, j0 - 32 + 32 * wc, n) : 0u;
+        }
     }
     if constexpr (VEC) {
         typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
@@ -309,7 +319,11 @@ __device__ __forceinline__ void life_bits_wave_body(const LifeTile &p, int32_t b
         for (int r = 0; r < RND; ++r) {
             const int32_t gi = i0 - K + 16 * r + rr;
             const int32_t gic = gi < 0 ? 0 : (gi >= n ? n - 1 : gi);
-            cv[r] = *(const u32x4 *)(p.cur + (int64_t)gic * ld + col);
+            // rows past the staged window (last round) are not loaded
+            if (S::R % 16 == 0 || r + 1 < RND || 16 * r + rr < S::R)
+                cv[r] = *(const u32x4 *)(p.cur + (int64_t)gic * ld + col);
+            else
+                cv[r] = u32x4{0u, 0u, 0u, 0u};
         }
 #pragma unroll
         for (int k = 0; k < HR; ++k) {
@@ -359,9 +373,11 @@ __device__ __forceinline__ void life_bits_wave_body(const LifeTile &p, int32_t b
         // grid, cells above the diagonal or left of column 0, clamped loads)
         __builtin_amdgcn_s_waitcnt(0xc07f);
         __builtin_amdgcn_wave_barrier();
+        if (!inner) {
 #pragma unroll
-        for (int k = 0; k < RB; ++k)
-            if (rb0 + k < S::R) A[(rb0 + k + 1) * S::WPR + wc] &= msk[k];
+            for (int k = 0; k < RB; ++k)
+                if (rb0 + k < S::R) A[(rb0 + k + 1) * S::WPR + wc] &= msk[k];
+        }
     } else {
     // halo cells of all rows: lane covers row 8 q + lane / 8, cell lane % 8
     uint64_t hb[HG];
@@ -440,6 +456,47 @@ __device__ __forceinline__ void life_bits_wave_body(const LifeTile &p, int32_t b
         s1 = h1 | (x & h0);
     };
     constexpr bool FULL = S::R % 16 == 0;  // every band holds RB rows
+    if constexpr (KH == 1) {
+        // one generation: only the tile's own words (1 and 2 of staged rows
+        // 1 .. 64) are needed, two rows of one word per lane; no output
+        // mask, since only cells of the domain are written back
+        const int c1 = 1 + (lane & 1), r1 = 1 + 2 * (lane >> 1);
+        const auto sums_at = [&](int r, uint32_t &s0, uint32_t &s1, uint32_t &h0, uint32_t &h1,
+                                 uint32_t &x) {
+            const uint32_t *row = A + (r + 1) * S::WPR;
+            const uint32_t w = row[c1 - 1], e = row[c1 + 1];
+            x = row[c1];
+            const uint32_t W = __builtin_amdgcn_alignbit(x, w, 31),
+                           E = __builtin_amdgcn_alignbit(e, x, 1);
+            h0 = W ^ E;
+            h1 = W & E;
+            s0 = h0 ^ x;
+            s1 = h1 | (x & h0);
+        };
+        uint32_t u0, u1, m0, m1, mc, q0, q1, z0, z1, z2;
+        sums_at(r1 - 1, u0, u1, z0, z1, z2);
+        sums_at(r1, q0, q1, m0, m1, mc);
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int r = r1 + k;
+            uint32_t d0, d1, n0, n1, nc;
+            sums_at(r + 1, d0, d1, n0, n1, nc);
+            const uint32_t t0 = u0 ^ d0 ^ m0;
+            const uint32_t c0 = (u0 & d0) | (m0 & (u0 ^ d0));
+            const uint32_t x1 = u1 ^ d1 ^ m1 ^ c0;
+            const uint32_t h2 = ((u1 & d1) | (m1 & (u1 ^ d1))) | (c0 & (u1 | d1 | m1));
+            B[(r + 1) * S::WPR + c1] = x1 & ~h2 & (t0 | mc);
+            u0 = q0; u1 = q1;
+            q0 = d0; q1 = d1;
+            m0 = n0; m1 = n1; mc = nc;
+        }
+        (void)gens;
+        __builtin_amdgcn_s_waitcnt(0xc07f);
+        __builtin_amdgcn_wave_barrier();
+        uint32_t *t = A;
+        A = B;
+        B = t;
+    } else
     for (int g = 0; g < gens; ++g) {
         if (FULL || rb0 < S::R) {
             uint32_t u0, u1, m0, m1, mc, q0, q1, z0, z1, z2;

@@ -84,6 +84,16 @@ struct BatchLds {
 // same instance: its range and descriptor are kept until an item leaves it.
 constexpr int kChunk = 4;
 
+// A workgroup-uniform 64-bit value read from LDS, made wave-uniform for the
+// compiler (a value loaded from LDS counts as divergent, and so would every
+// index, tile coordinate and branch derived from it)
+__device__ __forceinline__ int64_t uniform64(int64_t v)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // BITS (64 x 64 Life tiles, every Life grid of the batch with 16-byte rows):
 // chunks of Life items go one per wave through the bit-sliced body.
 // Four waves per SIMD bound the registers at 128 (the bit-sliced body alone
@@ -112,7 +122,7 @@ __global__ void __launch_bounds__(kBatchThreads, 4) k_batch_step(BatchStepArgs a
             if ((int64_t)next < a.total) next = atomicAdd(a.head, (uint32_t)kChunk);
         }
         __syncthreads();
-        const int64_t g0 = slot;
+        const int64_t g0 = uniform64(slot);
         if (g0 >= a.total) return;  // uniform over the workgroup
         if constexpr (BITS && TL == 64 && kChunk == kBatchThreads / 64) {
             // A chunk of Life items only, several generations, grids whose
@@ -134,17 +144,16 @@ __global__ void __launch_bounds__(kBatchThreads, 4) k_batch_step(BatchStepArgs a
                         else hi = mid;
                     }
                     lo = __builtin_amdgcn_readfirstlane(lo);  // wave-uniform: scalar loads
-                    wlo = in_lds ? pfx[lo] : a.prefix[lo];
-                    wlo = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(
-                                         (int32_t)((uint64_t)wlo >> 32)) << 32) |
-                                    (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)wlo));
+                    wlo = uniform64(in_lds ? pfx[lo] : a.prefix[lo]);
                     W = a.desc[a.idx ? __builtin_amdgcn_readfirstlane(a.idx[lo]) : lo];
                 }
                 const bool life = g >= a.total || (W.kind == TRI_KIND_LIFE && (W.pad & kDescVec16));
-                if (__syncthreads_and(life)) {
+                if (__builtin_amdgcn_readfirstlane(__syncthreads_and(life))) {
                     if (g < a.total) {
                         int32_t bi, bj;
                         lambda_tile((uint64_t)(g - wlo), 0u, bi, bj);
+                        bi = __builtin_amdgcn_readfirstlane(bi);
+                        bj = __builtin_amdgcn_readfirstlane(bj);
                         const bool even = (a.step & 1) == 0;
                         const LifeTile t{W.n, W.ld, (const uint8_t *)(even ? W.a : W.b),
                                          (uint8_t *)(even ? W.b : W.a)};
@@ -168,13 +177,16 @@ __global__ void __launch_bounds__(kBatchThreads, 4) k_batch_step(BatchStepArgs a
                     if (pm <= g) lo = mid;
                     else hi = mid;
                 }
-                lo_g = in_lds ? pfx[lo] : a.prefix[lo];
-                hi_g = in_lds ? pfx[lo + 1] : a.prefix[lo + 1];
-                D = a.desc[a.idx ? a.idx[lo] : lo];
+                lo = __builtin_amdgcn_readfirstlane(lo);  // uniform over the workgroup
+                lo_g = uniform64(in_lds ? pfx[lo] : a.prefix[lo]);
+                hi_g = uniform64(in_lds ? pfx[lo + 1] : a.prefix[lo + 1]);
+                D = a.desc[a.idx ? __builtin_amdgcn_readfirstlane(a.idx[lo]) : lo];
             }
             if (c > 0) __syncthreads();  // LDS reuse between items of a chunk
             int32_t bi, bj;
             lambda_tile((uint64_t)(g - lo_g), 0u, bi, bj);
+            bi = __builtin_amdgcn_readfirstlane(bi);
+            bj = __builtin_amdgcn_readfirstlane(bj);
             if (D.kind == TRI_KIND_EDM) {
                 const EdmTile t{D.n, D.d, D.ld, (const float *)D.a, (float *)D.b};
                 edm_f32_tile_body<TE, kEdmStageLoop>(t, bi, bj, (float *)body_lds);
@@ -188,7 +200,7 @@ __global__ void __launch_bounds__(kBatchThreads, 4) k_batch_step(BatchStepArgs a
                     // the first wave takes it (nodes may advance up to
                     // kBatchBitsGen generations, beyond the byte-sliced body)
                     if (a.gens > 0) {
-                        if (threadIdx.x < 64)
+                        if (__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) == 0)
                             life_bits_wave_body<true, kBatchBitsGen>(t, bi, bj, a.gens,
                                                                        (uint32_t *)body_lds);
                         done = true;
@@ -200,7 +212,10 @@ __global__ void __launch_bounds__(kBatchThreads, 4) k_batch_step(BatchStepArgs a
                         done = true;
                     }
                 }
-                if (!done) life_tile_body<TL, kBatchThreads, false>(t, bi, bj, (uint32_t *)body_lds);
+                // (the bit-sliced kernel is bound only to temporal plans,
+                // whose nodes all advance at least one generation)
+                if constexpr (!BITS)
+                    if (!done) life_tile_body<TL, kBatchThreads, false>(t, bi, bj, (uint32_t *)body_lds);
             }
         }
     }

@@ -684,10 +684,12 @@ def bench_batch(tm, torch, timer, steps=20, d=32, tiles=None):
     autotuner (tri_batch_autotune) unless given; then one hipGraph launch of
     the persistent queue vs the same bodies launched per instance."""
     spec, kinds, A, B, b, te, tl, fl, tune_ms, pairs, cells = make_batch(tm, torch, steps, d, tiles)
-    res = {}
-    for how, name in ((tm.BATCH_GRAPH, "graph"), (tm.BATCH_STREAM, "stream"),
-                      (tm.BATCH_PER_INSTANCE, "per_instance")):
-        res[name] = round(timer.run(lambda: b.launch(how), 3, 1), 4)
+    # the three forms timed in turn, after two warm-up rounds (the first
+    # launches on fresh buffers run slower, whichever form comes first)
+    modes = ((tm.BATCH_GRAPH, "graph"), (tm.BATCH_STREAM, "stream"),
+             (tm.BATCH_PER_INSTANCE, "per_instance"))
+    med = timer.interleaved([(lambda h=how: b.launch(h)) for how, _ in modes], reps=5, warmup=2)
+    res = {name: round(ms, 4) for (_, name), ms in zip(modes, med)}
     info = b.info
     nodes = info["graph_nodes"]
     n_edm = sum(1 for k in kinds if k == tm.KIND_EDM)
@@ -702,7 +704,8 @@ def bench_batch(tm, torch, timer, steps=20, d=32, tiles=None):
                "tri_batch_autotune" if tiles is None else "given"),
            "life_steps": steps, "d": d, "edm_pairs": pairs, "life_cells": cells,
            "launches_per_instance_mode": launches,
-           "ms": res, "speedup_graph_vs_per_instance": round(res["per_instance"] / res["graph"], 3),
+           "ms": res, "timing": "median of 5 rounds, the three forms in turn after 2 warm-up rounds",
+           "speedup_graph_vs_per_instance": round(res["per_instance"] / res["graph"], 3),
            # 4 B per distance plus 2 B per cell and generation: the work as if
            # every generation went through HBM, not a bandwidth (temporal
            # blocking moves a Life cell through HBM once per node)

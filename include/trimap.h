@@ -68,9 +68,11 @@ enum {
 
 /* Plan flags, bits 8..11: the number of consecutive tiles of the map that one
  * workgroup walks in the kernels that take strips (the distance map's MFMA
- * modes): TRI_FLAG_STRIP(k) asks for G = 2^k tiles (k = 0..5, G = 1..32);
- * none of these bits set: G chosen from the tile count.  Kernels without
- * strips ignore them. */
+ * modes, the fp32 elementwise kernel at tiles 16 and 32 with 16-byte rows,
+ * the bit-sliced Life kernel at tile 64 with 16-byte rows):
+ * TRI_FLAG_STRIP(k) asks for G = 2^k tiles (k = 0..5, G = 1..32); none of
+ * these bits set: G chosen from the tile count in the distance map, one
+ * tile per workgroup elsewhere.  Kernels without strips ignore them. */
 #define TRI_FLAG_STRIP_MASK 0xF00u
 #define TRI_FLAG_STRIP(k) ((uint32_t)((k) + 1) << 8)
 /* Plan flag for the same kernels under lambda: strips aligned to tile rows

@@ -142,13 +142,20 @@ static std::vector<Candidate> candidates(int workload, int64_t n)
             c.push_back({128, TRI_MAP_LAMBDA, (uint32_t)TRI_FLAG_STRIP_COLS | TRI_FLAG_EDM_PIPE | st});
         }
     if (workload == TRI_TUNE_LIFE)  // tile 64 in strips of 4 and 8 tiles, both forms
-        for (uint32_t st : {(uint32_t)TRI_FLAG_STRIP(2), (uint32_t)TRI_FLAG_STRIP(3)})
+        for (uint32_t st : {(uint32_t)TRI_FLAG_STRIP(2), (uint32_t)TRI_FLAG_STRIP(3)}) {
             for (uint32_t tf : {0u, (uint32_t)TRI_FLAG_LIFE_TEMPORAL}) {
                 c.push_back({64, TRI_MAP_BB, st | tf});
                 c.push_back({64, TRI_MAP_LAMBDA, st | tf});
                 c.push_back({64, TRI_MAP_LAMBDA, st | tf | (uint32_t)TRI_FLAG_STRIP_ALIGN});
                 c.push_back({64, TRI_MAP_LAMBDA, st | tf | (uint32_t)TRI_FLAG_XCD_SWIZZLE});
             }
+            // one generation, neighbouring tiles moved in pairs
+            const uint32_t w = (uint32_t)TRI_FLAG_LIFE_WIDE;
+            c.push_back({64, TRI_MAP_BB, st | w});
+            c.push_back({64, TRI_MAP_LAMBDA, st | w | (uint32_t)(TRI_FLAG_STRIP_ALIGN | TRI_FLAG_XCD_SWIZZLE)});
+            c.push_back({64, TRI_MAP_LAMBDA, st | w | (uint32_t)(TRI_FLAG_STRIP_ALIGN | TRI_FLAG_XCD_SWIZZLE |
+                                                              TRI_FLAG_ORDER_PAIRS)});
+        }
     if (workload == TRI_TUNE_LIFE)  // temporal blocking (tiles 16..64)
         for (int t : {16, 32, 64}) {
             c.push_back({t, TRI_MAP_BB, (uint32_t)TRI_FLAG_LIFE_TEMPORAL});

@@ -562,6 +562,167 @@ __device__ __forceinline__ void life_bits_wave_body(const LifeTile &p, int32_t b
     }
 }
 
+// One generation of two neighbouring 64 x 64 tiles, (bi, bj) and (bi, bj + 1),
+// by one wave, bit-sliced as above, with 16-byte row moves: the window is
+// 64 rows x 128 cells, so every row segment the wave loads or stores is a
+// whole 128-byte line where bj is even (a 64-cell tile alone moves 64-byte
+// halves, the other half belonging to the neighbouring tile and another
+// wave).  The staged window (rows i0 - 1 .. i0 + 64) is kept as six words
+// per row: word 0 holds cells j0 - 4 .. j0 - 1 in its top bits, words 1 to
+// 4 the 128 cells, word 5 cells j0 + 128 .. j0 + 131 in its low bits.
+// Only cells of the domain are written back, so cells of the second tile
+// above the diagonal (when it is not a tile of the map) are not touched.
+// lds: at least LifeBits1Pair::WORDS words (ld a multiple of 16, 16-byte
+// aligned grids).
+struct LifeBits1Pair {
+    static constexpr int R = 66;            // staged rows
+    static constexpr int PR = R + 2;        // plus a zero row above and below
+    static constexpr int WPR = 6;           // words per row
+    static constexpr int BUF = PR * WPR;
+    static constexpr int WORDS = 2 * BUF;
+    static constexpr int RND = (R + 7) / 8; // rounds of 8 rows (8 lanes per row)
+    static constexpr int HR = (2 * R + 63) / 64;  // rounds of 64 halo words
+};
+
+__device__ __forceinline__ void life_bits1_pair_body(const LifeTile &p, int32_t bi, int32_t bj,
+                                                     uint32_t *lds)
+{
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    using S = LifeBits1Pair;
+    constexpr int T = 64, WPR = S::WPR;
+    uint32_t *A = lds, *B = lds + S::BUF;
+    const int32_t n = p.n;
+    const int64_t ld = p.ld;
+    const int32_t ldi = (int32_t)ld;
+    const int32_t i0 = bi * T, j0 = bj * T;
+    const int lane = threadIdx.x & 63;
+
+    // loads: lane = 8 * row + chunk, chunk q of 16 cells; every address
+    // clamped into the grid, values outside the domain masked after staging
+    const int q = lane & 7, rr = lane >> 3;
+    const int32_t col = j0 + 16 * q < ldi - 16 ? j0 + 16 * q : ldi - 16;
+    u32x4 cv[S::RND];
+    uint32_t hv[S::HR];
+#pragma unroll
+    for (int r = 0; r < S::RND; ++r) {
+        const int row = 8 * r + rr;
+        const int32_t gi = i0 - 1 + row;
+        const int32_t gic = gi < 0 ? 0 : (gi >= n ? n - 1 : gi);
+        if (r + 1 < S::RND || row < S::R)
+            cv[r] = *(const u32x4 *)(p.cur + (int64_t)gic * ld + col);
+        else
+            cv[r] = u32x4{0u, 0u, 0u, 0u};
+    }
+#pragma unroll
+    for (int k = 0; k < S::HR; ++k) {
+        const int t = lane + 64 * k;  // halo word t: row t / 2, west or east
+        const int row = (t >> 1) < S::R ? (t >> 1) : S::R - 1;
+        const int32_t gi = i0 - 1 + row;
+        const int32_t gic = gi < 0 ? 0 : (gi >= n ? n - 1 : gi);
+        int32_t hc = (t & 1) ? j0 + 2 * T : j0 - 4;
+        hc = hc < 0 ? 0 : (hc > ldi - 4 ? ldi - 4 : hc);
+        hv[k] = *(const uint32_t *)(p.cur + (int64_t)gic * ld + hc);
+    }
+    // the zero rows above and below the window
+    if (lane < WPR) {
+        A[lane] = 0u;
+        A[(S::PR - 1) * WPR + lane] = 0u;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    uint16_t *A16 = (uint16_t *)A;
+#pragma unroll
+    for (int r = 0; r < S::RND; ++r) {
+        const int row = 8 * r + rr;
+        if (row < S::R) {
+            const uint32_t b16 = life_cells4_to_bits(cv[r].x) |
+                                 (life_cells4_to_bits(cv[r].y) << 4) |
+                                 (life_cells4_to_bits(cv[r].z) << 8) |
+                                 (life_cells4_to_bits(cv[r].w) << 12);
+            A16[((row + 1) * WPR + 1 + (q >> 1)) * 2 + (q & 1)] = (uint16_t)b16;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < S::HR; ++k) {
+        const int t = lane + 64 * k;
+        if (t < 2 * S::R) {
+            const uint32_t hb = life_cells4_to_bits(hv[k]);
+            A[((t >> 1) + 1) * WPR + ((t & 1) ? 5 : 0)] = (t & 1) ? hb : hb << 28;
+        }
+    }
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+    __builtin_amdgcn_wave_barrier();
+    // staged bits outside the domain cleared, unless the whole window
+    // (cells j0 - 32 .. j0 + 159 of rows i0 - 1 .. i0 + 64) lies inside it
+    const bool inner = bj >= 1 && bi - bj >= 3 && i0 + T + 1 <= n;
+    if (!inner) {
+        for (int idx = lane; idx < S::R * WPR; idx += 64) {
+            const int row = idx / WPR, c = idx - row * WPR;
+            A[(row + 1) * WPR + c] &= life_bits_mask(i0 - 1 + row, j0 - 32 + 32 * c, n);
+        }
+        __builtin_amdgcn_s_waitcnt(0xc07f);
+        __builtin_amdgcn_wave_barrier();
+    }
+    // the update: words 1 .. 4 of staged rows 1 .. 64, four rows of one
+    // word per lane (lane = 4 * band + word - 1)
+    const int c1 = 1 + (lane & 3), r1 = 1 + 4 * (lane >> 2);
+    const auto sums_at = [&](int r, uint32_t &s0, uint32_t &s1, uint32_t &h0, uint32_t &h1,
+                             uint32_t &x) {
+        const uint32_t *row = A + (r + 1) * WPR;
+        const uint32_t w = row[c1 - 1], e = row[c1 + 1];
+        x = row[c1];
+        const uint32_t W = __builtin_amdgcn_alignbit(x, w, 31), E = __builtin_amdgcn_alignbit(e, x, 1);
+        h0 = W ^ E;
+        h1 = W & E;
+        s0 = h0 ^ x;
+        s1 = h1 | (x & h0);
+    };
+    {
+        uint32_t u0, u1, m0, m1, mc, q0, q1, z0, z1, z2;
+        sums_at(r1 - 1, u0, u1, z0, z1, z2);
+        sums_at(r1, q0, q1, m0, m1, mc);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int r = r1 + k;
+            uint32_t d0, d1, n0, n1, nc;
+            sums_at(r + 1, d0, d1, n0, n1, nc);
+            // 0..8 live neighbours: bit 0 t0, bit 1 x1, 4 or more h2
+            const uint32_t t0 = u0 ^ d0 ^ m0;
+            const uint32_t c0 = (u0 & d0) | (m0 & (u0 ^ d0));
+            const uint32_t x1 = u1 ^ d1 ^ m1 ^ c0;
+            const uint32_t h2 = ((u1 & d1) | (m1 & (u1 ^ d1))) | (c0 & (u1 | d1 | m1));
+            B[(r + 1) * WPR + c1] = x1 & ~h2 & (t0 | mc);
+            u0 = q0; u1 = q1;
+            q0 = d0; q1 = d1;
+            m0 = n0; m1 = n1; mc = nc;
+        }
+    }
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+    __builtin_amdgcn_wave_barrier();
+    // unpack and store: lane = 8 * row + chunk, 8 rounds of 8 rows
+    const int32_t jc = j0 + 16 * q;
+#pragma unroll
+    for (int r0 = 0; r0 < T; r0 += 8) {
+        const int tr = r0 + rr;
+        const int32_t gi = i0 + tr;
+        if (gi >= n) continue;
+        const uint32_t b16 = (B[(tr + 2) * WPR + 1 + (q >> 1)] >> (16 * (q & 1))) & 0xFFFFu;
+        if (jc > gi) continue;  // the chunk lies above the diagonal
+        u32x4 o;
+        o.x = life_bits4_to_cells(b16 & 0xFu);
+        o.y = life_bits4_to_cells((b16 >> 4) & 0xFu);
+        o.z = life_bits4_to_cells((b16 >> 8) & 0xFu);
+        o.w = life_bits4_to_cells(b16 >> 12);
+        uint8_t *dst = p.nxt + (int64_t)gi * ld + jc;
+        if (jc + 15 <= gi) {
+            *(u32x4 *)dst = o;
+        } else {  // the chunk meets the diagonal: cells jc .. gi only
+#pragma unroll
+            for (int e = 0; e < 16; ++e)
+                if (jc + e <= gi) dst[e] = (uint8_t)((b16 >> e) & 1u);
+        }
+    }
+}
+
 // lds: 2 * LifeMultiShape<TILE>::WORDS words; 256 threads; 1 <= gens <= 4;
 // HOIST as for life_tile_body
 template <int TILE, bool HOIST = true>

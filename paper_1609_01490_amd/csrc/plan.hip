@@ -145,7 +145,8 @@ tri_status tri_map_plan(tri_plan **out, int64_t n, int tile, int map, int includ
                             TRI_FLAG_ORDER_REVERSE | TRI_FLAG_ORDER_PAIRS |
                             TRI_FLAG_LIFE_TEMPORAL | TRI_FLAG_SQRT_NEWTON |
                             TRI_FLAG_SQRT_EPS | TRI_FLAG_STRIP_MASK | TRI_FLAG_STRIP_COLS |
-                            TRI_FLAG_STRIP_ALIGN | TRI_FLAG_EDM_PIPE | TRI_FLAG_STRIP_BAND))
+                            TRI_FLAG_STRIP_ALIGN | TRI_FLAG_EDM_PIPE | TRI_FLAG_STRIP_BAND |
+                            TRI_FLAG_LIFE_WIDE))
         return fail(TRI_E_INVAL, "tri_map_plan: unknown flags 0x%x", flags);
     if (((flags & TRI_FLAG_STRIP_MASK) >> 8) > 6)
         return fail(TRI_E_INVAL, "tri_map_plan: strip length beyond 32 tiles (flags 0x%x)", flags);

@@ -108,6 +108,38 @@ __global__ void __launch_bounds__(256) k_life_bits_strip(LifeArgs p, int gens, S
     }
 }
 
+// One generation in strips with TRI_FLAG_LIFE_WIDE: wave w takes tiles 2 j
+// and 2 j + 1 of the strip (j = w, w + 4, ...) together, as one 64 x 128
+// window, when they are neighbours in a tile row (each still located by
+// the map on its own), and one at a time otherwise.
+template <int MAP>
+__global__ void __launch_bounds__(256) k_life_bits_strip_wide(LifeArgs p, int gens, StripGrid sg)
+{
+    (void)gens;  // one generation (the signature of k_life_bits_strip)
+    constexpr int WB = 2 * LifeBitsShape<1>::WORDS;
+    constexpr int WW = LifeBits1Pair::WORDS > WB ? LifeBits1Pair::WORDS : WB;
+    __shared__ __attribute__((aligned(16))) uint32_t buf[4][WW];
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t first = strip_first<MAP>(p.g, sg);
+    for (int j = w; 2 * j < sg.G; j += 4) {
+        int32_t ai = 0, aj = 0, ci = 0, cj = 0;
+        const bool va = __builtin_amdgcn_readfirstlane(
+            (int)strip_tile<MAP>(p.g, sg, first, 2 * j, ai, aj));
+        const bool vc = __builtin_amdgcn_readfirstlane(
+            (int)(2 * j + 1 < sg.G && strip_tile<MAP>(p.g, sg, first, 2 * j + 1, ci, cj)));
+        ai = __builtin_amdgcn_readfirstlane(ai);
+        aj = __builtin_amdgcn_readfirstlane(aj);
+        ci = __builtin_amdgcn_readfirstlane(ci);
+        cj = __builtin_amdgcn_readfirstlane(cj);
+        if (va && vc && ci == ai && cj == aj + 1) {
+            life_bits1_pair_body(p.t, ai, aj, buf[w]);
+        } else {
+            if (va) life_bits_wave_body<true, 1>(p.t, ai, aj, 1, buf[w]);
+            if (vc) life_bits_wave_body<true, 1>(p.t, ci, cj, 1, buf[w]);
+        }
+    }
+}
+
 // One generation of 64 x 64 tiles with the 1-cell halo of the paper's tiles,
 // bit-sliced, one wave per tile, 16-byte row moves
 template <int MAP>
@@ -151,7 +183,10 @@ static bool life_tile(const tri_plan *p, const LifeArgs &a, hipStream_t s)
         if (life_vec16(a.t) && strip_flag_len(p->flags)) {
             dim3 sgrid;
             const StripGrid sg = life_strip_grid(p, a.g, sgrid);
-            k_life_bits_strip<MAP, 1><<<sgrid, 256, 0, s>>>(a, 1, sg);
+            if (p->flags & TRI_FLAG_LIFE_WIDE)
+                k_life_bits_strip_wide<MAP><<<sgrid, 256, 0, s>>>(a, 1, sg);
+            else
+                k_life_bits_strip<MAP, 1><<<sgrid, 256, 0, s>>>(a, 1, sg);
         } else if (life_vec16(a.t)) {
             k_life_bits1<MAP><<<grid, 64, 0, s>>>(a);
         } else {
@@ -193,8 +228,9 @@ static bool life_multi_kernel_tile(int tile, uint64_t tiles, bool vec, const voi
 }
 
 template <int MAP>
-static const void *life_strip_kernel(int kh)
+static const void *life_strip_kernel(int kh, bool wide)
 {
+    if (kh == 1 && wide) return (const void *)k_life_bits_strip_wide<MAP>;
     return kh == 1 ? (const void *)k_life_bits_strip<MAP, 1>
                    : (const void *)k_life_bits_strip<MAP, kLifeBitsStencilGen>;
 }
@@ -202,11 +238,12 @@ static const void *life_strip_kernel(int kh)
 // the strip kernel of a plan (kh = 1: one generation; else the temporal one)
 static const void *life_strip_fn(const tri_plan *p, int kh)
 {
+    const bool wide = (p->flags & TRI_FLAG_LIFE_WIDE) != 0;
     switch (p->map) {
-    case TRI_MAP_BB: return life_strip_kernel<MAP_BB>(kh);
-    case TRI_MAP_RB: return life_strip_kernel<MAP_RB>(kh);
-    case TRI_MAP_REC: return life_strip_kernel<MAP_REC>(kh);
-    case TRI_MAP_LAMBDA: return life_strip_kernel<MAP_LAMBDA>(kh);
+    case TRI_MAP_BB: return life_strip_kernel<MAP_BB>(kh, wide);
+    case TRI_MAP_RB: return life_strip_kernel<MAP_RB>(kh, wide);
+    case TRI_MAP_REC: return life_strip_kernel<MAP_REC>(kh, wide);
+    case TRI_MAP_LAMBDA: return life_strip_kernel<MAP_LAMBDA>(kh, wide);
     }
     return nullptr;
 }

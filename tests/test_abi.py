@@ -58,7 +58,7 @@ def test_plan_validation_on_host():
             tm.Plan(*bad)
         assert ei.value.status == code
     with pytest.raises(tm.TrimapError) as ei:
-        tm.Plan(100, 16, "lambda", flags=1 << 16)
+        tm.Plan(100, 16, "lambda", flags=1 << 17)
     assert ei.value.status == tm.E_INVAL
     assert tm.status_str(tm.E_RANGE) == "TRI_E_RANGE"
 

@@ -169,13 +169,17 @@ def test_life_graph_mode_matches_eager_and_replays(map_name, tile, multiple):
 
 
 @pytest.mark.parametrize("map_name,flags", [("lambda", 0), ("lambda", 17), ("lambda", 0x2000),
-                                            ("lambda", 0x1001), ("bb", 0), ("rb", 0), ("rec", 0)])
+                                            ("lambda", 0x1001), ("bb", 0), ("rb", 0), ("rec", 0),
+                                            ("lambda", 0x10000), ("lambda", 0x12000),
+                                            ("lambda", 0x12011), ("bb", 0x10000), ("rb", 0x10000),
+                                            ("rec", 0x10000)])
 @pytest.mark.parametrize("strip", [0, 2, 3, 5])
 @pytest.mark.parametrize("temporal", [False, True])
 def test_life_strips_bit_exact(map_name, flags, strip, temporal):
     """Tile 64 with 16-byte rows in strips of 1, 4, 8 and 32 tiles per
-    workgroup (each wave its own tiles): one generation per launch (eager
-    and in a graph) and the temporal kernel, bit-exact against the oracle,
+    workgroup (each wave its own tiles, or with 0x10000 neighbouring pairs
+    of tiles as one 64 x 128 window): one generation per launch (eager and
+    in a graph) and the temporal kernel, bit-exact against the oracle,
     upper triangle untouched."""
     import torch
     tm = _tm()

@@ -45,6 +45,7 @@ struct BatchDesc {
 };
 
 constexpr int32_t kDescVec16 = 1;  // ld % 16 == 0 and 16-byte aligned grids
+constexpr int32_t kDescEdmVec4 = 2;  // distance map: coordinates staged as 16-byte vectors
 
 struct BatchStepArgs {
     const BatchDesc *desc;
@@ -189,7 +190,10 @@ __global__ void __launch_bounds__(kBatchThreads, 4) k_batch_step(BatchStepArgs a
             bj = __builtin_amdgcn_readfirstlane(bj);
             if (D.kind == TRI_KIND_EDM) {
                 const EdmTile t{D.n, D.d, D.ld, (const float *)D.a, (float *)D.b};
-                edm_f32_tile_body<TE, kEdmStageLoop>(t, bi, bj, (float *)body_lds);
+                if (D.pad & kDescEdmVec4)
+                    edm_f32_tile_body<TE, kEdmStageVec4>(t, bi, bj, (float *)body_lds);
+                else
+                    edm_f32_tile_body<TE, kEdmStageLoop>(t, bi, bj, (float *)body_lds);
             } else {
                 const bool even = (a.step & 1) == 0;
                 const LifeTile t{D.n, D.ld, (const uint8_t *)(even ? D.a : D.b),
@@ -502,6 +506,11 @@ tri_status tri_batch_bind(tri_batch *b, void *const *host_a, void *const *host_b
         if (D.kind == TRI_KIND_EDM) {
             if (D.ld < D.d || (((uintptr_t)D.a | (uintptr_t)D.b) & 3))
                 return fail(TRI_E_INVAL, "tri_batch_bind: instance %d: ldx < d or unaligned", k);
+            // 16-byte staging loads where every row starts on 16 bytes and
+            // the byte offsets fit 32 bits (as for the single FP32 kernel)
+            if (D.d % 4 == 0 && D.ld % 4 == 0 && ((uintptr_t)D.a & 15) == 0 &&
+                (uint64_t)D.n * (uint64_t)D.ld * 4 < (1ull << 31))
+                D.pad = kDescEdmVec4;
         } else {
             if (D.ld < D.n || D.ld % 4 || (((uintptr_t)D.a | (uintptr_t)D.b) & 3))
                 return fail(TRI_E_INVAL,

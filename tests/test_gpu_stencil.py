@@ -107,19 +107,24 @@ def test_life_errors():
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("map_name,tile", [("lambda", 32), ("bb", 32), ("utm", 16)])
-def test_life_full_size_windows(map_name, tile):
-    """n = 16384, density 0.3, 100 steps.  The oracle recomputes 64 x 64 cell
-    blocks from their light cones (the initial state within 100 cells):
-    at the diagonal, the bottom edge, the left edge, a corner and inside."""
+@pytest.mark.parametrize("map_name,tile,flags", [("lambda", 32, 0), ("bb", 32, 0), ("utm", 16, 0),
+                                                 ("lambda", 64, 0x12301), ("bb", 64, 0x10300),
+                                                 ("lambda", 64, 0x301)])
+def test_life_full_size_windows(map_name, tile, flags):
+    """n = 16384, density 0.3, 100 steps, one generation per launch (tile 64
+    with 16-byte rows: the bit-sliced strips, one tile per wave or with
+    0x10000 neighbouring tiles in pairs).  The oracle recomputes 64 x 64
+    cell blocks from their light cones (the initial state within 100
+    cells): at the diagonal, the bottom edge, the left edge, a corner and
+    inside."""
     import torch
     tm = _tm()
     n, steps = 16384, 100
     g = inputs.life(n, 0.3)
-    note("life full", map_name, tile, n, steps)
+    note("life full", map_name, tile, flags, n, steps)
     cur = dev(g)
     nxt = torch.zeros_like(cur)
-    p = tm.Plan(n, tile, map_name)
+    p = tm.Plan(n, tile, map_name, flags=flags)
     p.stencil(cur, nxt, steps)
     res = cur if steps % 2 == 0 else nxt
     torch.cuda.synchronize()

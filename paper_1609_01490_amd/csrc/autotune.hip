@@ -149,12 +149,14 @@ static std::vector<Candidate> candidates(int workload, int64_t n)
                 c.push_back({64, TRI_MAP_LAMBDA, st | tf | (uint32_t)TRI_FLAG_STRIP_ALIGN});
                 c.push_back({64, TRI_MAP_LAMBDA, st | tf | (uint32_t)TRI_FLAG_XCD_SWIZZLE});
             }
-            // one generation, neighbouring tiles moved in pairs
+            // neighbouring tiles moved in pairs, both forms
             const uint32_t w = (uint32_t)TRI_FLAG_LIFE_WIDE;
-            c.push_back({64, TRI_MAP_BB, st | w});
-            c.push_back({64, TRI_MAP_LAMBDA, st | w | (uint32_t)(TRI_FLAG_STRIP_ALIGN | TRI_FLAG_XCD_SWIZZLE)});
-            c.push_back({64, TRI_MAP_LAMBDA, st | w | (uint32_t)(TRI_FLAG_STRIP_ALIGN | TRI_FLAG_XCD_SWIZZLE |
-                                                              TRI_FLAG_ORDER_PAIRS)});
+            for (uint32_t tf : {0u, (uint32_t)TRI_FLAG_LIFE_TEMPORAL}) {
+                c.push_back({64, TRI_MAP_BB, st | w | tf});
+                c.push_back({64, TRI_MAP_LAMBDA, st | w | tf | (uint32_t)(TRI_FLAG_STRIP_ALIGN | TRI_FLAG_XCD_SWIZZLE)});
+                c.push_back({64, TRI_MAP_LAMBDA, st | w | tf | (uint32_t)(TRI_FLAG_STRIP_ALIGN | TRI_FLAG_XCD_SWIZZLE |
+                                                                       TRI_FLAG_ORDER_PAIRS)});
+            }
         }
     if (workload == TRI_TUNE_LIFE)  // temporal blocking (tiles 16..64)
         for (int t : {16, 32, 64}) {

@@ -723,6 +723,171 @@ __device__ __forceinline__ void life_bits1_pair_body(const LifeTile &p, int32_t 
     }
 }
 
+// Up to 16 generations of two neighbouring 64 x 64 tiles, (bi, bj) and
+// (bi, bj + 1), by one wave, bit-sliced, with 16-byte row moves.  The
+// window is rows i0 - 16 .. i0 + 79 and cells j0 - 16 .. j0 + 143: five
+// words per row, the 16 halo cells on each side sharing the edge words with
+// the tiles (a single tile's window needs four words per row for 64 cells,
+// half of two of them halo), so a generation updates 5 words of 96 rows for
+// 128 cells instead of 8 for two tiles.  After g generations every cell at
+// least g cells inside the window is exact (the light cone grows by one
+// cell per generation), whatever the cells outside it hold: the edge words
+// read across the row boundary without a test.  Cells outside the domain
+// are forced dead after every generation; only cells of the domain are
+// written back.  Lanes 0 .. 59 update: lane = 5 * band + word, band b owns
+// rows 8 b .. 8 b + 7.  lds: at least LifeBits16Pair::WORDS words (ld a
+// multiple of 16, 16-byte aligned grids); 1 <= gens <= 16.
+struct LifeBits16Pair {
+    static constexpr int K = 16;                  // halo rows and cells
+    static constexpr int R = 64 + 2 * K;          // staged rows
+    static constexpr int PR = R + 2;              // plus a zero row above and below
+    static constexpr int WPR = 5;                 // words per row
+    static constexpr int BUF = PR * WPR;
+    static constexpr int WORDS = 2 * BUF + 3;     // two buffers between three zero guard words
+    static constexpr int CH = 10;                 // 16-cell chunks per row
+    static constexpr int NCH = R * CH;
+    static constexpr int RNDS = (NCH + 63) / 64;  // load rounds, in batches
+    static constexpr int BANDS = 12, RB = 8;
+    static_assert(BANDS * RB == R && BANDS * WPR <= 64, "update layout");
+};
+
+__device__ __forceinline__ void life_bits16_pair_body(const LifeTile &p, int32_t bi, int32_t bj,
+                                                      int gens, uint32_t *lds)
+{
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    using S = LifeBits16Pair;
+    constexpr int T = 64, K = S::K, WPR = S::WPR;
+    uint32_t *A = lds + 1, *B = lds + 2 + S::BUF;
+    const int32_t n = p.n;
+    const int64_t ld = p.ld;
+    const int32_t ldi = (int32_t)ld;
+    const int32_t i0 = bi * T, j0 = bj * T, jw = j0 - K;
+    const int lane = threadIdx.x & 63;
+
+    if (lane < WPR) {
+        A[lane] = A[(S::PR - 1) * WPR + lane] = 0u;
+        B[lane] = B[(S::PR - 1) * WPR + lane] = 0u;
+        if (lane < 3) lds[lane * (S::BUF + 1)] = 0u;
+    }
+    // staging: chunk idx = 10 * row + k (16 cells at jw + 16 k), loaded from
+    // clamped addresses, NB rounds of 64 chunks per batch
+    constexpr int NB = 5;
+    uint16_t *A16 = (uint16_t *)A;
+#pragma unroll
+    for (int b0 = 0; b0 < S::RNDS; b0 += NB) {
+        u32x4 v[NB];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const int idx = lane + 64 * (b0 + u);
+            const int row = idx / S::CH, k = idx - row * S::CH;
+            const int32_t gi = i0 - K + (row < S::R ? row : S::R - 1);
+            const int32_t gic = gi < 0 ? 0 : (gi >= n ? n - 1 : gi);
+            int32_t c = jw + 16 * k;
+            c = c < 0 ? 0 : (c > ldi - 16 ? ldi - 16 : c);
+            if (b0 + u < S::RNDS && idx < S::NCH)
+                v[u] = *(const u32x4 *)(p.cur + (int64_t)gic * ld + c);
+            else
+                v[u] = u32x4{0u, 0u, 0u, 0u};
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const int idx = lane + 64 * (b0 + u);
+            if (b0 + u < S::RNDS && idx < S::NCH) {
+                const int row = idx / S::CH, k = idx - row * S::CH;
+                const uint32_t b16 = life_cells4_to_bits(v[u].x) |
+                                     (life_cells4_to_bits(v[u].y) << 4) |
+                                     (life_cells4_to_bits(v[u].z) << 8) |
+                                     (life_cells4_to_bits(v[u].w) << 12);
+                A16[((row + 1) * WPR + (k >> 1)) * 2 + (k & 1)] = (uint16_t)b16;
+            }
+        }
+    }
+    // domain masks, unless the window (cells j0 - 16 .. j0 + 143 of rows
+    // i0 - 16 .. i0 + 79) lies inside the domain
+    const int wc = lane % WPR, band = lane / WPR;
+    const bool act = band < S::BANDS;
+    const int rb0 = band * S::RB;
+    const bool inner = bj >= 1 && bi - bj >= 3 && i0 + T + K <= n;
+    uint32_t msk[S::RB];
+#pragma unroll
+    for (int k = 0; k < S::RB; ++k)
+        msk[k] = !act ? 0u : (inner ? ~0u : life_bits_mask(i0 - K + rb0 + k, jw + 32 * wc, n));
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+    __builtin_amdgcn_wave_barrier();
+    if (!inner) {
+        if (act) {
+#pragma unroll
+            for (int k = 0; k < S::RB; ++k) A[(rb0 + k + 1) * WPR + wc] &= msk[k];
+        }
+        __builtin_amdgcn_s_waitcnt(0xc07f);
+        __builtin_amdgcn_wave_barrier();
+    }
+    const auto row_sums = [&](const uint32_t *src, int r, uint32_t &s0, uint32_t &s1,
+                              uint32_t &h0, uint32_t &h1, uint32_t &x) {
+        const uint32_t *row = src + (r + 1) * WPR;
+        const uint32_t w = row[wc - 1], e = row[wc + 1];
+        x = row[wc];
+        const uint32_t W = __builtin_amdgcn_alignbit(x, w, 31), E = __builtin_amdgcn_alignbit(e, x, 1);
+        h0 = W ^ E;
+        h1 = W & E;
+        s0 = h0 ^ x;
+        s1 = h1 | (x & h0);
+    };
+    for (int g = 0; g < gens; ++g) {
+        if (act) {
+            uint32_t u0, u1, m0, m1, mc, q0, q1, z0, z1, z2;
+            row_sums(A, rb0 - 1, u0, u1, z0, z1, z2);
+            row_sums(A, rb0, q0, q1, m0, m1, mc);
+#pragma unroll
+            for (int k = 0; k < S::RB; ++k) {
+                const int r = rb0 + k;
+                uint32_t d0, d1, n0, n1, nc;
+                row_sums(A, r + 1, d0, d1, n0, n1, nc);
+                // 0..8 live neighbours: bit 0 t0, bit 1 x1, 4 or more h2
+                const uint32_t t0 = u0 ^ d0 ^ m0;
+                const uint32_t c0 = (u0 & d0) | (m0 & (u0 ^ d0));
+                const uint32_t x1 = u1 ^ d1 ^ m1 ^ c0;
+                const uint32_t h2 = ((u1 & d1) | (m1 & (u1 ^ d1))) | (c0 & (u1 | d1 | m1));
+                B[(r + 1) * WPR + wc] = x1 & ~h2 & (t0 | mc) & msk[k];
+                u0 = q0; u1 = q1;
+                q0 = d0; q1 = d1;
+                m0 = n0; m1 = n1; mc = nc;
+            }
+        }
+        __builtin_amdgcn_s_waitcnt(0xc07f);
+        __builtin_amdgcn_wave_barrier();
+        uint32_t *t = A;
+        A = B;
+        B = t;
+    }
+    // the tiles' cells: rows i0 .. i0 + 63 (staged K ..), chunks 1 .. 8
+    const int q = lane & 7, rr = lane >> 3;
+    const int ch = 1 + q;
+    const int32_t jc = j0 + 16 * q;
+#pragma unroll
+    for (int r0 = 0; r0 < T; r0 += 8) {
+        const int tr = r0 + rr;
+        const int32_t gi = i0 + tr;
+        if (gi >= n) continue;
+        const uint32_t b16 = (A[(tr + K + 1) * WPR + (ch >> 1)] >> (16 * (ch & 1))) & 0xFFFFu;
+        if (jc > gi) continue;  // the chunk lies above the diagonal
+        u32x4 o;
+        o.x = life_bits4_to_cells(b16 & 0xFu);
+        o.y = life_bits4_to_cells((b16 >> 4) & 0xFu);
+        o.z = life_bits4_to_cells((b16 >> 8) & 0xFu);
+        o.w = life_bits4_to_cells(b16 >> 12);
+        uint8_t *dst = p.nxt + (int64_t)gi * ld + jc;
+        if (jc + 15 <= gi) {
+            *(u32x4 *)dst = o;
+        } else {  // the chunk meets the diagonal: cells jc .. gi only
+#pragma unroll
+            for (int e = 0; e < 16; ++e)
+                if (jc + e <= gi) dst[e] = (uint8_t)((b16 >> e) & 1u);
+        }
+    }
+}
+
 // lds: 2 * LifeMultiShape<TILE>::WORDS words; 256 threads; 1 <= gens <= 4;
 // HOIST as for life_tile_body
 template <int TILE, bool HOIST = true>

@@ -108,16 +108,18 @@ __global__ void __launch_bounds__(256) k_life_bits_strip(LifeArgs p, int gens, S
     }
 }
 
-// One generation in strips with TRI_FLAG_LIFE_WIDE: wave w takes tiles 2 j
-// and 2 j + 1 of the strip (j = w, w + 4, ...) together, as one 64 x 128
-// window, when they are neighbours in a tile row (each still located by
-// the map on its own), and one at a time otherwise.
-template <int MAP>
+// Strips with TRI_FLAG_LIFE_WIDE: wave w takes tiles 2 j and 2 j + 1 of the
+// strip (j = w, w + 4, ...) together, as one window two tiles wide, when
+// they are neighbours in a tile row (each still located by the map on its
+// own), and one at a time otherwise.  KH = 1: one generation with the
+// 1-cell halo; else up to KH = 16 generations.
+template <int MAP, int KH>
 __global__ void __launch_bounds__(256) k_life_bits_strip_wide(LifeArgs p, int gens, StripGrid sg)
 {
-    (void)gens;  // one generation (the signature of k_life_bits_strip)
-    constexpr int WB = 2 * LifeBitsShape<1>::WORDS;
-    constexpr int WW = LifeBits1Pair::WORDS > WB ? LifeBits1Pair::WORDS : WB;
+    static_assert(KH == 1 || KH == LifeBits16Pair::K, "halo");
+    constexpr int WB = 2 * LifeBitsShape<KH>::WORDS;
+    constexpr int WP = KH == 1 ? LifeBits1Pair::WORDS : LifeBits16Pair::WORDS;
+    constexpr int WW = WP > WB ? WP : WB;
     __shared__ __attribute__((aligned(16))) uint32_t buf[4][WW];
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t first = strip_first<MAP>(p.g, sg);
@@ -132,10 +134,11 @@ __global__ void __launch_bounds__(256) k_life_bits_strip_wide(LifeArgs p, int ge
         ci = __builtin_amdgcn_readfirstlane(ci);
         cj = __builtin_amdgcn_readfirstlane(cj);
         if (va && vc && ci == ai && cj == aj + 1) {
-            life_bits1_pair_body(p.t, ai, aj, buf[w]);
+            if constexpr (KH == 1) life_bits1_pair_body(p.t, ai, aj, buf[w]);
+            else life_bits16_pair_body(p.t, ai, aj, gens, buf[w]);
         } else {
-            if (va) life_bits_wave_body<true, 1>(p.t, ai, aj, 1, buf[w]);
-            if (vc) life_bits_wave_body<true, 1>(p.t, ci, cj, 1, buf[w]);
+            if (va) life_bits_wave_body<true, KH>(p.t, ai, aj, KH == 1 ? 1 : gens, buf[w]);
+            if (vc) life_bits_wave_body<true, KH>(p.t, ci, cj, KH == 1 ? 1 : gens, buf[w]);
         }
     }
 }
@@ -184,7 +187,7 @@ static bool life_tile(const tri_plan *p, const LifeArgs &a, hipStream_t s)
             dim3 sgrid;
             const StripGrid sg = life_strip_grid(p, a.g, sgrid);
             if (p->flags & TRI_FLAG_LIFE_WIDE)
-                k_life_bits_strip_wide<MAP><<<sgrid, 256, 0, s>>>(a, 1, sg);
+                k_life_bits_strip_wide<MAP, 1><<<sgrid, 256, 0, s>>>(a, 1, sg);
             else
                 k_life_bits_strip<MAP, 1><<<sgrid, 256, 0, s>>>(a, 1, sg);
         } else if (life_vec16(a.t)) {
@@ -230,7 +233,9 @@ static bool life_multi_kernel_tile(int tile, uint64_t tiles, bool vec, const voi
 template <int MAP>
 static const void *life_strip_kernel(int kh, bool wide)
 {
-    if (kh == 1 && wide) return (const void *)k_life_bits_strip_wide<MAP>;
+    if (wide)
+        return kh == 1 ? (const void *)k_life_bits_strip_wide<MAP, 1>
+                       : (const void *)k_life_bits_strip_wide<MAP, kLifeBitsStencilGen>;
     return kh == 1 ? (const void *)k_life_bits_strip<MAP, 1>
                    : (const void *)k_life_bits_strip<MAP, kLifeBitsStencilGen>;
 }

@@ -274,26 +274,33 @@ def _gol_whole(g, n, steps, bands=16):
     return out
 
 
+_WHOLE = {}
+
+
 @pytest.mark.slow
-def test_life_temporal_full_size_whole_grid():
-    """The benchmarked launch (n = 16384, density 0.3, 100 generations,
-    lambda tile 64 with the XCD swizzle and temporal blocking: the
-    bit-sliced kernel): the whole final grid, bit for bit, against the
-    oracle's."""
+@pytest.mark.parametrize("flags", [0x21, 0x31, 0x12421, 0x12431])
+def test_life_temporal_full_size_whole_grid(flags):
+    """The benchmarked launches (n = 16384, density 0.3, 100 generations,
+    lambda tile 64, temporal blocking: the bit-sliced kernels, one tile per
+    workgroup with the XCD swizzle and pairs order, or in aligned strips of
+    8 with neighbouring tiles moved in pairs): the whole final grid, bit
+    for bit, against the oracle's (computed once for all of them)."""
     import torch
     tm = _tm()
     n, steps = 16384, 100
     g = inputs.life(n, 0.3)
-    note("life temporal whole grid", n, steps)
+    note("life temporal whole grid", n, steps, flags)
     cur = dev(g)
     nxt = torch.zeros_like(cur)
-    p = tm.Plan(n, 64, "lambda", flags=tm.FLAG_LIFE_TEMPORAL | tm.FLAG_XCD_SWIZZLE)
+    p = tm.Plan(n, 64, "lambda", flags=flags)
     p.stencil(cur, nxt, steps)
     torch.cuda.synchronize()
     got = cur.cpu().numpy()
     del cur, nxt
     torch.cuda.empty_cache()
-    exp = _gol_whole(g, n, steps)
+    if "exp" not in _WHOLE:
+        _WHOLE["exp"] = _gol_whole(g, n, steps)
+    exp = _WHOLE["exp"]
     bad = np.argwhere(got != exp)
     assert bad.shape[0] == 0, (bad.shape[0], bad[:4].tolist())
 

@@ -570,10 +570,10 @@ __device__ __forceinline__ void life_bits_wave_body(const LifeTile &p, int32_t b
 // wave).  The staged window (rows i0 - 1 .. i0 + 64) is kept as six words
 // per row: word 0 holds cells j0 - 4 .. j0 - 1 in its top bits, words 1 to
 // 4 the 128 cells, word 5 cells j0 + 128 .. j0 + 131 in its low bits.
-// Only cells of the domain are written back, so cells of the second tile
-// above the diagonal (when it is not a tile of the map) are not touched.
-// lds: at least LifeBits1Pair::WORDS words (ld a multiple of 16, 16-byte
-// aligned grids).
+// Only cells of the domain are written back, and with two == false only
+// those of the first tile (the second then belongs to another window or
+// lies outside the domain).  lds: at least LifeBits1Pair::WORDS words (ld
+// a multiple of 16, 16-byte aligned grids).
 struct LifeBits1Pair {
     static constexpr int R = 66;            // staged rows
     static constexpr int PR = R + 2;        // plus a zero row above and below
@@ -585,7 +585,7 @@ struct LifeBits1Pair {
 };
 
 __device__ __forceinline__ void life_bits1_pair_body(const LifeTile &p, int32_t bi, int32_t bj,
-                                                     uint32_t *lds)
+                                                     bool two, uint32_t *lds)
 {
     typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
     using S = LifeBits1Pair;
@@ -706,7 +706,7 @@ __device__ __forceinline__ void life_bits1_pair_body(const LifeTile &p, int32_t 
         const int32_t gi = i0 + tr;
         if (gi >= n) continue;
         const uint32_t b16 = (B[(tr + 2) * WPR + 1 + (q >> 1)] >> (16 * (q & 1))) & 0xFFFFu;
-        if (jc > gi) continue;  // the chunk lies above the diagonal
+        if (jc > gi || (!two && q >= 4)) continue;  // above the diagonal, or not this window's
         u32x4 o;
         o.x = life_bits4_to_cells(b16 & 0xFu);
         o.y = life_bits4_to_cells((b16 >> 4) & 0xFu);
@@ -734,7 +734,8 @@ __device__ __forceinline__ void life_bits1_pair_body(const LifeTile &p, int32_t 
 // cell per generation), whatever the cells outside it hold: the edge words
 // read across the row boundary without a test.  Cells outside the domain
 // are forced dead after every generation; only cells of the domain are
-// written back.  Lanes 0 .. 59 update: lane = 5 * band + word, band b owns
+// written back, and with two == false only those of the first tile.
+// Lanes 0 .. 59 update: lane = 5 * band + word, band b owns
 // rows 8 b .. 8 b + 7.  lds: at least LifeBits16Pair::WORDS words (ld a
 // multiple of 16, 16-byte aligned grids); 1 <= gens <= 16.
 struct LifeBits16Pair {
@@ -752,7 +753,7 @@ struct LifeBits16Pair {
 };
 
 __device__ __forceinline__ void life_bits16_pair_body(const LifeTile &p, int32_t bi, int32_t bj,
-                                                      int gens, uint32_t *lds)
+                                                      bool two, int gens, uint32_t *lds)
 {
     typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
     using S = LifeBits16Pair;
@@ -871,7 +872,7 @@ __device__ __forceinline__ void life_bits16_pair_body(const LifeTile &p, int32_t
         const int32_t gi = i0 + tr;
         if (gi >= n) continue;
         const uint32_t b16 = (A[(tr + K + 1) * WPR + (ch >> 1)] >> (16 * (ch & 1))) & 0xFFFFu;
-        if (jc > gi) continue;  // the chunk lies above the diagonal
+        if (jc > gi || (!two && q >= 4)) continue;  // above the diagonal, or not this window's
         u32x4 o;
         o.x = life_bits4_to_cells(b16 & 0xFu);
         o.y = life_bits4_to_cells((b16 >> 4) & 0xFu);

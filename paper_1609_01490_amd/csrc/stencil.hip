@@ -111,15 +111,15 @@ __global__ void __launch_bounds__(256) k_life_bits_strip(LifeArgs p, int gens, S
 // Strips with TRI_FLAG_LIFE_WIDE: wave w takes tiles 2 j and 2 j + 1 of the
 // strip (j = w, w + 4, ...) together, as one window two tiles wide, when
 // they are neighbours in a tile row (each still located by the map on its
-// own), and one at a time otherwise.  KH = 1: one generation with the
-// 1-cell halo; else up to KH = 16 generations.
+// own), and otherwise each in a window of its own whose second half is not
+// written back (one body, so that the registers are those of the paired
+// body alone).  KH = 1: one generation with the 1-cell halo; else up to
+// KH = 16 generations.
 template <int MAP, int KH>
 __global__ void __launch_bounds__(256) k_life_bits_strip_wide(LifeArgs p, int gens, StripGrid sg)
 {
     static_assert(KH == 1 || KH == LifeBits16Pair::K, "halo");
-    constexpr int WB = 2 * LifeBitsShape<KH>::WORDS;
-    constexpr int WP = KH == 1 ? LifeBits1Pair::WORDS : LifeBits16Pair::WORDS;
-    constexpr int WW = WP > WB ? WP : WB;
+    constexpr int WW = KH == 1 ? LifeBits1Pair::WORDS : LifeBits16Pair::WORDS;
     __shared__ __attribute__((aligned(16))) uint32_t buf[4][WW];
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t first = strip_first<MAP>(p.g, sg);
@@ -133,12 +133,14 @@ __global__ void __launch_bounds__(256) k_life_bits_strip_wide(LifeArgs p, int ge
         aj = __builtin_amdgcn_readfirstlane(aj);
         ci = __builtin_amdgcn_readfirstlane(ci);
         cj = __builtin_amdgcn_readfirstlane(cj);
-        if (va && vc && ci == ai && cj == aj + 1) {
-            if constexpr (KH == 1) life_bits1_pair_body(p.t, ai, aj, buf[w]);
-            else life_bits16_pair_body(p.t, ai, aj, gens, buf[w]);
-        } else {
-            if (va) life_bits_wave_body<true, KH>(p.t, ai, aj, KH == 1 ? 1 : gens, buf[w]);
-            if (vc) life_bits_wave_body<true, KH>(p.t, ci, cj, KH == 1 ? 1 : gens, buf[w]);
+        // up to two windows: the pair, or each valid tile alone
+        const bool pair = va && vc && ci == ai && cj == aj + 1;
+        const int nw = pair ? 1 : (int)va + (int)vc;
+        for (int u = 0; u < nw; ++u) {
+            const bool first = u == 0 && va;
+            const int32_t bi = first ? ai : ci, bj = first ? aj : cj;
+            if constexpr (KH == 1) life_bits1_pair_body(p.t, bi, bj, pair, buf[w]);
+            else life_bits16_pair_body(p.t, bi, bj, pair, gens, buf[w]);
         }
     }
 }

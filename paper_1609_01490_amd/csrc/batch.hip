@@ -71,9 +71,10 @@ struct BatchLds {
     static constexpr int EDM_BYTES = EdmF32Shape<TE>::LDS_FLOATS * 4;
     static constexpr int LIFE_BYTES = LifeShape<TL, kBatchThreads>::LDS_WORDS * 4;
     static constexpr int MULTI_BYTES = life_multi_bytes<TL>();
-    // 64 x 64 Life tiles with several generations: one bit-sliced tile per wave
+    // 64 x 64 Life tiles with several generations: one bit-sliced window of
+    // two tiles per wave
     static constexpr int BITS_BYTES =
-        TL == 64 ? kBatchThreads / 64 * 2 * LifeBitsShape<kBatchBitsGen>::WORDS * 4 : 0;
+        TL == 64 ? kBatchThreads / 64 * LifeBits16Pair::WORDS * 4 : 0;
     static constexpr int B1 = EDM_BYTES > LIFE_BYTES ? EDM_BYTES : LIFE_BYTES;
     static constexpr int B2 = B1 > MULTI_BYTES ? B1 : MULTI_BYTES;
     static constexpr int BYTES = B2 > BITS_BYTES ? B2 : BITS_BYTES;
@@ -95,13 +96,10 @@ __device__ __forceinline__ int64_t uniform64(int64_t v)
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-// BITS (64 x 64 Life tiles, every Life grid of the batch with 16-byte rows):
-// chunks of Life items go one per wave through the bit-sliced body.
-// Four waves per SIMD bound the registers at 128 (the bit-sliced body alone
-// would take about 160, three waves) with no spills; the grid is sized from
-// the occupancy this gives, and the extra resident wave hides more of the
-// memory latency of the persistent loop.
-template <int TE, int TL, bool BITS>
+// Every item through a workgroup-wide body (byte-sliced Life); four waves
+// per SIMD bound the registers at 128 with no spills, and the grid is sized
+// from the occupancy this gives.
+template <int TE, int TL>
 __global__ void __launch_bounds__(kBatchThreads, 4) k_batch_step(BatchStepArgs a)
 {
     __shared__ __attribute__((aligned(16))) unsigned char body_lds[BatchLds<TE, TL>::BYTES];
@@ -125,47 +123,6 @@ __global__ void __launch_bounds__(kBatchThreads, 4) k_batch_step(BatchStepArgs a
         __syncthreads();
         const int64_t g0 = uniform64(slot);
         if (g0 >= a.total) return;  // uniform over the workgroup
-        if constexpr (BITS && TL == 64 && kChunk == kBatchThreads / 64) {
-            // A chunk of Life items only, several generations, grids whose
-            // rows move as 16-byte vectors: each wave takes one item with the
-            // bit-sliced body, instead of the workgroup taking the four in
-            // turn with the byte-sliced one (which other grids keep: moved
-            // byte by byte, the bit-sliced body is slower at these sizes).
-            if (a.gens > 0) {
-                const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-                const int64_t g = g0 + wv;
-                int64_t wlo = 0;
-                BatchDesc W{};
-                if (g < a.total) {
-                    int lo = 0, hi = a.count;
-                    while (hi - lo > 1) {
-                        const int mid = (lo + hi) >> 1;
-                        const int64_t pm = in_lds ? pfx[mid] : a.prefix[mid];
-                        if (pm <= g) lo = mid;
-                        else hi = mid;
-                    }
-                    lo = __builtin_amdgcn_readfirstlane(lo);  // wave-uniform: scalar loads
-                    wlo = uniform64(in_lds ? pfx[lo] : a.prefix[lo]);
-                    W = a.desc[a.idx ? __builtin_amdgcn_readfirstlane(a.idx[lo]) : lo];
-                }
-                const bool life = g >= a.total || (W.kind == TRI_KIND_LIFE && (W.pad & kDescVec16));
-                if (__builtin_amdgcn_readfirstlane(__syncthreads_and(life))) {
-                    if (g < a.total) {
-                        int32_t bi, bj;
-                        lambda_tile((uint64_t)(g - wlo), 0u, bi, bj);
-                        bi = __builtin_amdgcn_readfirstlane(bi);
-                        bj = __builtin_amdgcn_readfirstlane(bj);
-                        const bool even = (a.step & 1) == 0;
-                        const LifeTile t{W.n, W.ld, (const uint8_t *)(even ? W.a : W.b),
-                                         (uint8_t *)(even ? W.b : W.a)};
-                        uint32_t *wl = (uint32_t *)body_lds +
-                                       wv * 2 * LifeBitsShape<kBatchBitsGen>::WORDS;
-                        life_bits_wave_body<true, kBatchBitsGen>(t, bi, bj, a.gens, wl);
-                    }
-                    continue;  // the loop's barrier precedes the next claim
-                }
-            }
-        }
         for (int c = 0; c < kChunk; ++c) {
             const int64_t g = g0 + c;
             if (g >= a.total) break;
@@ -199,28 +156,134 @@ __global__ void __launch_bounds__(kBatchThreads, 4) k_batch_step(BatchStepArgs a
                 const LifeTile t{D.n, D.ld, (const uint8_t *)(even ? D.a : D.b),
                                  (uint8_t *)(even ? D.b : D.a)};
                 bool done = false;
-                if constexpr (BITS && TL == 64) {
-                    // a Life item in a chunk that also holds distance items:
-                    // the first wave takes it (nodes may advance up to
-                    // kBatchBitsGen generations, beyond the byte-sliced body)
-                    if (a.gens > 0) {
-                        if (__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) == 0)
-                            life_bits_wave_body<true, kBatchBitsGen>(t, bi, bj, a.gens,
-                                                                       (uint32_t *)body_lds);
-                        done = true;
-                    }
-                }
-                if constexpr (TL >= 16 && !BITS) {
+                if constexpr (TL >= 16) {
                     if (a.gens > 0) {
                         life_multi_tile_body<TL, true>(t, bi, bj, a.gens, (uint32_t *)body_lds);
                         done = true;
                     }
                 }
-                // (the bit-sliced kernel is bound only to temporal plans,
-                // whose nodes all advance at least one generation)
-                if constexpr (!BITS)
-                    if (!done) life_tile_body<TL, kBatchThreads, false>(t, bi, bj, (uint32_t *)body_lds);
+                if (!done) life_tile_body<TL, kBatchThreads, false>(t, bi, bj, (uint32_t *)body_lds);
             }
+        }
+    }
+}
+
+// 64 x 64 Life tiles, every Life grid of the batch with 16-byte rows, and
+// nodes of several generations (temporal plans): items are taken
+// kChunkBits at a time.  The workgroup first runs the chunk's distance
+// items one after the other, then each wave takes two consecutive items,
+// 2 w and 2 w + 1, through the bit-sliced window of two tiles: as one
+// window when they are neighbours in a tile row of one instance (as
+// consecutive lambda blocks mostly are), else each in a window of its own
+// with the second half not written back.  One call site per body keeps the
+// registers at those of the larger body.  VEC4: every distance instance
+// stages its coordinates as 16-byte vectors (chosen at bind time, so that
+// the kernel holds one distance body).
+constexpr int kChunkBits = 2 * kBatchThreads / 64;
+
+template <int TE, bool VEC4>
+__global__ void __launch_bounds__(kBatchThreads, 4) k_batch_step_bits(BatchStepArgs a)
+{
+    constexpr int EDM_BYTES = EdmF32Shape<TE>::LDS_FLOATS * 4;
+    constexpr int PAIR_BYTES = kBatchThreads / 64 * LifeBits16Pair::WORDS * 4;
+    static_assert(kBatchBitsGen == LifeBits16Pair::K, "halo of the paired window");
+    __shared__ __attribute__((aligned(16)))
+    unsigned char body_lds[EDM_BYTES > PAIR_BYTES ? EDM_BYTES : PAIR_BYTES];
+    __shared__ int64_t pfx[kPrefixLds];
+    __shared__ int64_t slot;
+
+    const bool in_lds = a.count + 1 <= kPrefixLds;
+    if (in_lds)
+        for (int k = threadIdx.x; k <= a.count; k += kBatchThreads) pfx[k] = a.prefix[k];
+    uint32_t next = 0;  // thread 0: first item of the chunk claimed ahead
+    if (threadIdx.x == 0) next = atomicAdd(a.head, (uint32_t)kChunkBits);
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    uint32_t *wl = (uint32_t *)body_lds + wv * LifeBits16Pair::WORDS;
+
+    // the instance of item g (wave-uniform): the largest q with prefix[q] <= g
+    const auto locate = [&](int64_t g, int64_t &lo_g, int64_t &hi_g, BatchDesc &D) {
+        int lo = 0, hi = a.count;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            const int64_t pm = in_lds ? pfx[mid] : a.prefix[mid];
+            if (pm <= g) lo = mid;
+            else hi = mid;
+        }
+        lo = __builtin_amdgcn_readfirstlane(lo);
+        lo_g = uniform64(in_lds ? pfx[lo] : a.prefix[lo]);
+        hi_g = uniform64(in_lds ? pfx[lo + 1] : a.prefix[lo + 1]);
+        D = a.desc[a.idx ? __builtin_amdgcn_readfirstlane(a.idx[lo]) : lo];
+    };
+    int64_t lo_g = 0, hi_g = 0;  // item range of the cached instance
+    BatchDesc D{};
+    for (;;) {
+        __syncthreads();  // the previous chunk is done with the LDS and with slot
+        if (threadIdx.x == 0) {
+            slot = (int64_t)next;
+            if ((int64_t)next < a.total) next = atomicAdd(a.head, (uint32_t)kChunkBits);
+        }
+        __syncthreads();
+        const int64_t g0 = uniform64(slot);
+        if (g0 >= a.total) return;  // uniform over the workgroup
+        // the chunk's distance items, the whole workgroup each
+        bool used = false;
+        for (int c = 0; c < kChunkBits; ++c) {
+            const int64_t g = g0 + c;
+            if (g >= a.total) break;
+            if (g < lo_g || g >= hi_g) locate(g, lo_g, hi_g, D);
+            if (D.kind != TRI_KIND_EDM) continue;
+            if (used) __syncthreads();  // LDS reuse between items
+            used = true;
+            int32_t bi, bj;
+            lambda_tile((uint64_t)(g - lo_g), 0u, bi, bj);
+            bi = __builtin_amdgcn_readfirstlane(bi);
+            bj = __builtin_amdgcn_readfirstlane(bj);
+            const EdmTile t{D.n, D.d, D.ld, (const float *)D.a, (float *)D.b};
+            edm_f32_tile_body<TE, VEC4 ? kEdmStageVec4 : kEdmStageLoop>(t, bi, bj, (float *)body_lds);
+        }
+        if (used) __syncthreads();  // the windows below reuse the LDS
+        // the chunk's Life items: wave w takes items 2 w and 2 w + 1
+        bool life[2];
+        int32_t ti[2], tj[2];
+        int64_t tl[2];
+        BatchDesc TD[2];
+        int64_t l0 = 0, h0 = 0;  // the instance range of item 2 w
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int64_t g = g0 + 2 * wv + e;
+            life[e] = false;
+            ti[e] = tj[e] = 0;
+            tl[e] = -1;
+            if (g < a.total) {
+                int64_t l, h;
+                if (e == 1 && g < h0) {  // in the instance of item 2 w (g - 1 < total, so l0 is set)
+                    l = l0;
+                    TD[1] = TD[0];
+                } else {
+                    locate(g, l, h, TD[e]);
+                    if (e == 0) {
+                        l0 = l;
+                        h0 = h;
+                    }
+                }
+                if (TD[e].kind == TRI_KIND_LIFE) {
+                    life[e] = true;
+                    tl[e] = l;
+                    lambda_tile((uint64_t)(g - l), 0u, ti[e], tj[e]);
+                    ti[e] = __builtin_amdgcn_readfirstlane(ti[e]);
+                    tj[e] = __builtin_amdgcn_readfirstlane(tj[e]);
+                }
+            }
+        }
+        const bool pair = life[0] && life[1] && tl[0] == tl[1] && ti[1] == ti[0] && tj[1] == tj[0] + 1;
+        const int nw = pair ? 1 : (int)life[0] + (int)life[1];
+        const bool even = (a.step & 1) == 0;
+        for (int u = 0; u < nw; ++u) {
+            const int e = (u == 0 && life[0]) ? 0 : 1;
+            const BatchDesc &W = TD[e];
+            const LifeTile t{W.n, W.ld, (const uint8_t *)(even ? W.a : W.b),
+                             (uint8_t *)(even ? W.b : W.a)};
+            life_bits16_pair_body(t, ti[e], tj[e], pair, a.gens, wl);
         }
     }
 }
@@ -233,25 +296,28 @@ __global__ void k_batch_reset(uint32_t *heads, int32_t count)
 typedef void (*StepKernel)(BatchStepArgs);
 
 template <int TE>
-static StepKernel step_kernel_te(int tl, bool bits)
+static StepKernel step_kernel_te(int tl, bool bits, bool vec4)
 {
     switch (tl) {
-    case 8: return k_batch_step<TE, 8, false>;
-    case 16: return k_batch_step<TE, 16, false>;
-    case 32: return k_batch_step<TE, 32, false>;
-    case 64: return bits ? k_batch_step<TE, 64, true> : k_batch_step<TE, 64, false>;
+    case 8: return k_batch_step<TE, 8>;
+    case 16: return k_batch_step<TE, 16>;
+    case 32: return k_batch_step<TE, 32>;
+    case 64:
+        if (!bits) return k_batch_step<TE, 64>;
+        return vec4 ? k_batch_step_bits<TE, true> : k_batch_step_bits<TE, false>;
     }
     return nullptr;
 }
 
-// bits: the bit-sliced variant (tile 64 only; null otherwise)
-static StepKernel step_kernel(int te, int tl, bool bits = false)
+// bits: the bit-sliced variant (tile 64 only; null otherwise), vec4: its
+// form for batches whose distance instances all stage 16-byte vectors
+static StepKernel step_kernel(int te, int tl, bool bits = false, bool vec4 = false)
 {
     if (bits && tl != 64) return nullptr;
     switch (te) {
-    case 16: return step_kernel_te<16>(tl, bits);
-    case 32: return step_kernel_te<32>(tl, bits);
-    case 64: return step_kernel_te<64>(tl, bits);
+    case 16: return step_kernel_te<16>(tl, bits, vec4);
+    case 32: return step_kernel_te<32>(tl, bits, vec4);
+    case 64: return step_kernel_te<64>(tl, bits, vec4);
     }
     return nullptr;
 }
@@ -524,9 +590,15 @@ tri_status tri_batch_bind(tri_batch *b, void *const *host_a, void *const *host_b
     // the bit-sliced kernel when every Life grid has 16-byte rows and the
     // nodes advance several generations
     bool bits = b->kernel_bits != nullptr && b->temporal;
-    for (const BatchDesc &D : desc)
+    bool vec4 = true;  // every distance instance stages 16-byte vectors
+    for (const BatchDesc &D : desc) {
         if (D.kind == TRI_KIND_LIFE && !(D.pad & kDescVec16)) bits = false;
-    b->kernel = bits ? b->kernel_bits : b->kernel_bytes;
+        if (D.kind == TRI_KIND_EDM && !(D.pad & kDescEdmVec4)) vec4 = false;
+    }
+    // (the two forms of the bit-sliced kernel have the same launch bound and
+    // LDS, so the same persistent grid)
+    b->kernel = bits ? (vec4 ? step_kernel(b->edm_tile, b->life_tile, true, true) : b->kernel_bits)
+                     : b->kernel_bytes;
     b->grid = bits ? b->grid_bits : b->grid_bytes;
     // the bit-sliced kernel advances up to kBatchBitsGen generations per
     // node (fewer nodes than the plan's schedule, whose counters it reuses)

@@ -230,24 +230,10 @@ __device__ __forceinline__ float direct_d2(const float *x, int64_t ldx, int32_t 
 {
     const float *xi = x + (int64_t)i * ldx, *xj = x + (int64_t)j * ldx;
     float s = 0.f;
-    int32_t k = 0;
-    // eight loads in flight per step, the sum still taken in dimension order
+    // one dimension at a time: the recompute is rare (near pairs only), and
+    // more loads in flight here cost the whole kernel registers
 #pragma unroll 1
-    for (; k + 4 <= d; k += 4) {
-        float a[4], b[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            a[e] = xi[k + e];
-            b[e] = xj[k + e];
-        }
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const float df = a[e] - b[e];
-            s = __builtin_fmaf(df, df, s);
-        }
-    }
-#pragma unroll 1
-    for (; k < d; ++k) {
+    for (int32_t k = 0; k < d; ++k) {
         const float df = xi[k] - xj[k];
         s = __builtin_fmaf(df, df, s);
     }

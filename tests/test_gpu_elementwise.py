@@ -168,7 +168,9 @@ def full_inputs():
                                                  ("lambda", 16, 0), ("lambda", 16, 0x500),
                                                  ("lambda", 32, 0x500), ("bb", 16, 0x500),
                                                  ("lambda", 16, 0x511), ("lambda", 32, 0x601),
-                                                 ("lambda", 16, 0x2300), ("lambda", 32, 0x2410)])
+                                                 ("lambda", 16, 0x2300), ("lambda", 32, 0x2410),
+                                                 ("lambda", 16, 0x8510), ("lambda", 16, 0x8500),
+                                                 ("bb", 16, 0x8500), ("lambda", 32, 0x8310)])
 def test_axpyt_full_size_sampled_rows(full_inputs, map_name, tile, flags):
     """n = 32768 (12 GiB of operands), the configuration the benchmark times
     (lambda, tile 128, pairs order) and its neighbours; 64 sampled rows plus

@@ -135,8 +135,9 @@ static std::vector<Candidate> candidates(int workload, int64_t n)
                 c.push_back({t, TRI_MAP_LAMBDA, st | (uint32_t)TRI_FLAG_STRIP_BAND});
                 c.push_back({t, TRI_MAP_LAMBDA, st | (uint32_t)(TRI_FLAG_STRIP_BAND | TRI_FLAG_ORDER_PAIRS)});
             }
-    if (workload == TRI_TUNE_EDM_BF16X3)  // column-major strips of 16 and 32 tiles, both schedules
-        for (uint32_t st : {(uint32_t)TRI_FLAG_STRIP(4), (uint32_t)TRI_FLAG_STRIP(5)}) {
+    if (workload == TRI_TUNE_EDM_BF16X3)  // column-major strips of 8, 16 and 32 tiles, both schedules
+        for (uint32_t st : {(uint32_t)TRI_FLAG_STRIP(3), (uint32_t)TRI_FLAG_STRIP(4),
+                            (uint32_t)TRI_FLAG_STRIP(5)}) {
             c.push_back({128, TRI_MAP_LAMBDA, (uint32_t)TRI_FLAG_STRIP_COLS | st});
             c.push_back({128, TRI_MAP_LAMBDA, (uint32_t)TRI_FLAG_STRIP_COLS | TRI_FLAG_XCD_SWIZZLE | st});
             c.push_back({128, TRI_MAP_LAMBDA, (uint32_t)TRI_FLAG_STRIP_COLS | TRI_FLAG_EDM_PIPE | st});

@@ -99,12 +99,16 @@ enum {
  * T_{2p+r} + c).  TRI_FLAG_STRIP_COLS and TRI_FLAG_STRIP_ALIGN take
  * precedence.  The distance map and the stencil reject it. */
 #define TRI_FLAG_STRIP_BAND 0x8000u
-/* Plan flag for the bit-sliced one-generation Life strips (tile 64, 16-byte
- * rows): a wave moves tiles 2 j and 2 j + 1 of its strip together when
- * they are neighbours in a tile row (64 x 128 cells: every row segment a
- * whole 128-byte line), each still located by the map on its own; other
- * tiles one at a time.  Section 5's shared-memory test with the paper's
- * 1-cell halo; the pairing is a scheduling choice outside the paper. */
+/* Plan flag for the bit-sliced Life strips (tile 64, 16-byte rows), in
+ * both forms (one generation with the paper's 1-cell halo, and with
+ * TRI_FLAG_LIFE_TEMPORAL up to 16 generations with a 16-cell halo): a wave
+ * moves tiles 2 j and 2 j + 1 of its strip as one window two tiles wide
+ * when they are neighbours in a tile row (every row segment a whole
+ * 128-byte line; the temporal window's halo shares the edge words with the
+ * tiles), each tile still located by the map on its own; any other tile
+ * in a window of its own, of which only that tile is written back.
+ * Section 5's shared-memory test; the pairing is a scheduling choice
+ * outside the paper. */
 #define TRI_FLAG_LIFE_WIDE 0x10000u
 
 /* Elementwise bodies. */

@@ -33,7 +33,7 @@ def FLAG_STRIP(k: int) -> int:
 FLAG_STRIP_COLS = 0x1000  # lambda strips aligned to tile rows, taken column by column
 FLAG_STRIP_ALIGN = 0x2000  # lambda strips aligned to tile rows, taken row by row
 FLAG_STRIP_BAND = 0x8000  # elementwise strips over two-row bands (2 x 2 tile blocks)
-FLAG_LIFE_WIDE = 0x10000  # one-generation Life strips: neighbouring tiles moved in pairs
+FLAG_LIFE_WIDE = 0x10000  # bit-sliced Life strips: neighbouring tiles moved in pairs
 FLAG_EDM_PIPE = 0x4000  # distance map: the pipelined matrix-core kernel
 OP_XORMUL_I32, OP_AXPYT_F32, OP_EDM4_F32 = 0, 1, 2
 EDM_FP32, EDM_BF16X3, EDM_BF16 = 0, 1, 2

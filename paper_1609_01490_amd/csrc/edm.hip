@@ -845,7 +845,9 @@ __global__ void __launch_bounds__(256, 2) k_edm_lines(EdmLinesArgs a)
         const int32_t CW = bj * kEdmTile;
         char *const obt = orow + 4 * (int64_t)CW;  // the tile's row R0, column 0
         // store of line k (byte offset 128 k) of the row of register r
-        auto st = [&](int r, uint32_t k128, float v) { *(float *)((obt + offw[r]) + k128) = v; };
+        auto st = [&](int r, uint32_t k128, float v) {
+            __builtin_nontemporal_store(v, (float *)((obt + offw[r]) + k128));
+        };
         const bool tail_self = !(more && nbi == bi && nbj == bj + 1);
         const bool full = CW + kEdmTile - 1 < R0 && R0 + kEdmTile - 1 < n;
         // per-lane test of pair (row of register r, tile column jt), for
@@ -912,8 +914,8 @@ __global__ void __launch_bounds__(256, 2) k_edm_lines(EdmLinesArgs a)
 #pragma unroll
                     for (int q = 0; q < kRows; ++q) {
                         const int r = s * kRows + q;
-                        if (sv0) *(float *)((sbase + offw[r]) + k0) = V0[r];
-                        *(float *)((sbase + offw[r]) + k1) = V1[r];
+                        if (sv0) __builtin_nontemporal_store(V0[r], (float *)((sbase + offw[r]) + k0));
+                        __builtin_nontemporal_store(V1[r], (float *)((sbase + offw[r]) + k1));
                     }
                 }
                 __builtin_amdgcn_sched_barrier(0);
@@ -1211,7 +1213,9 @@ __global__ void __launch_bounds__(256, 1) k_edm_pipe(EdmLinesArgs a)
     // carry_near.
     auto epilogue = [&](f32x16 (&acc)[4], char *obt, int32_t CW, bool full, bool c_ok,
                         bool tail_self) {
-        auto st = [&](int r, uint32_t k128, float v) { *(float *)((obt + offw[r]) + k128) = v; };
+        auto st = [&](int r, uint32_t k128, float v) {
+            __builtin_nontemporal_store(v, (float *)((obt + offw[r]) + k128));
+        };
         auto inside = [&](int r, int32_t jt) {
             const int32_t i = R0 + 32 * w + 8 * (r >> 2) + 4 * hf + (r & 3);
             return i < n && CW + jt >= 0 && CW + jt < i;
@@ -1349,10 +1353,10 @@ __global__ void __launch_bounds__(256, 1) k_edm_pipe(EdmLinesArgs a)
                     const int r = s * RPS + q;
                     const bool wrap = (wbits >> r) & 1u;
                     char *const rp = pobt + offw[r];
-                    *(float *)(rp + 0u) = wrap ? carry[r] : accP[0][r];
-                    *(float *)(rp + 128u) = wrap ? accP[0][r] : accP[1][r];
-                    *(float *)(rp + 256u) = wrap ? accP[1][r] : accP[2][r];
-                    *(float *)(rp + 384u) = wrap ? accP[2][r] : accP[3][r];
+                    __builtin_nontemporal_store(wrap ? carry[r] : accP[0][r], (float *)(rp + 0u));
+                    __builtin_nontemporal_store(wrap ? accP[0][r] : accP[1][r], (float *)(rp + 128u));
+                    __builtin_nontemporal_store(wrap ? accP[1][r] : accP[2][r], (float *)(rp + 256u));
+                    __builtin_nontemporal_store(wrap ? accP[2][r] : accP[3][r], (float *)(rp + 384u));
                 }
                 __builtin_amdgcn_sched_barrier(0);
                 if constexpr (SPLIT) {

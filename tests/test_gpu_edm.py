@@ -390,3 +390,65 @@ def test_edm_mfma_rec_full_size_sampled_rows(mode):
             assert (np.abs(g - e) <= 2.0 ** -7 * (nrm[r] + nrm[:r])).all(), r
     del out
     torch.cuda.empty_cache()
+
+
+@pytest.fixture(scope="module")
+def plain_edm():
+    """The one-tile-per-workgroup full-size output of the last mode asked
+    for, shared by the strip-order cases and freed after the module."""
+    cache = {}
+    yield cache
+    cache.clear()
+    import torch
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("mode,flags", [(1, 0x1400), (1, 0x1401), (1, 0x1500), (1, 0x1501),
+                                        (1, 0x1600), (1, 0x1601), (1, 0x5400), (1, 0x5500),
+                                        (1, 0x5600), (2, 0x1500), (2, 0x1601)])
+def test_edm_mfma_full_size_strip_orders(mode, flags, plain_edm):
+    """n = 65536, d = 128 in the launch configurations the autotuner times
+    for the distance map: lambda in column-major strips of 8, 16 and 32
+    tiles aligned to tile rows, with and without the XCD swizzle, and the
+    one-wave-per-SIMD kernel.  The whole output is bit-identical to one
+    tile per workgroup (each tile's arithmetic is the same; only the order
+    and the carried stores differ), and sampled whole rows (first, last, 8
+    seeded random, 8 near-duplicate rows) meet the mode's bound against the
+    FP64 oracle."""
+    import torch
+    tm = _tm()
+    n, d = 65536, 128
+    X, pairs = inputs.points(n, d)
+    if plain_edm.get("mode") != mode:
+        plain_edm.clear()
+        torch.cuda.empty_cache()
+        note("edm full plain", mode, n, d)
+        plain_edm["mode"] = mode
+        plain_edm["out"] = _edm_mfma(tm, tm.Plan(n, 128, "lambda", include_diag=False), X, mode)
+    p = tm.Plan(n, 128, "lambda", include_diag=False, flags=flags)
+    note("edm full strips", mode, hex(flags), n, d)
+    out = _edm_mfma(tm, p, X, mode)
+    torch.cuda.synchronize()
+    assert torch.equal(out.view(torch.int32), plain_edm["out"].view(torch.int32))
+    rng = np.random.default_rng(18 + flags)
+    rows = sorted(set([1, n - 1] + rng.choice(np.arange(1, n), 8, replace=False).tolist()
+                      + pairs[:8].max(axis=1).tolist()))
+    sub = np.concatenate([out[r * (r - 1) // 2: r * (r - 1) // 2 + r].cpu().numpy()
+                          for r in rows])
+    offs = np.cumsum([0] + rows[:-1])
+    view = {r: sub[o:o + r] for r, o in zip(rows, offs)}
+    exp = oracle.edm_rows(X, rows)
+    if mode == 1:
+        for r, e in zip(rows, exp):
+            g = view[r].astype(np.float64)
+            nz = e > 0
+            assert (np.abs(g[nz] - e[nz]) / e[nz]).max() <= 1e-3, r
+    else:
+        Xc = X.astype(np.float64) - X.astype(np.float64).mean(axis=0)
+        nrm = np.sqrt((Xc ** 2).sum(axis=1))
+        for r, e in zip(rows, exp):
+            g = view[r].astype(np.float64)
+            assert (np.abs(g - e) <= 2.0 ** -7 * (nrm[r] + nrm[:r])).all(), r
+    del out
+    torch.cuda.empty_cache()

@@ -367,7 +367,7 @@ __device__ __forceinline__ void edm_store_block(char *ob, const f32x16 (&acc)[2]
                     // which the max turns into 0
                     const float dd = fmaxf(__builtin_amdgcn_sqrtf(acc[a][b][4 * q + u]), 0.f);
                     if (FULL || (i < n && jl + 32 * b < i))
-                        *(float *)(ob + ((off + 32u * b) << 2)) = dd;
+                        __builtin_nontemporal_store(dd, (float *)(ob + ((off + 32u * b) << 2)));
                 }
                 off += (uint32_t)i;  // start of row i + 1
                 ++i;
@@ -415,7 +415,8 @@ __device__ __forceinline__ void edm_epilogue(const EdmMfmaArgs &p, f32x16 (&acc)
     else
         edm_store_block<false>(ob, acc, R0, C0 + lr, n, l);
     // near-duplicates (rare): recompute those squares directly in FP32 and
-    // store them over the values just written (same lane, same address)
+    // store them over the values just written (same lane, same address, the
+    // same non-temporal policy)
     if (__any(near)) {
         uint64_t m = 0;
 #pragma unroll
@@ -432,8 +433,9 @@ __device__ __forceinline__ void edm_epilogue(const EdmMfmaArgs &p, f32x16 (&acc)
             const int32_t i = R0 + 32 * a + 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
             const int32_t j = C0 + 32 * b + lr;
             if (i < n && j < i)
-                *(float *)(ob + (((uint32_t)((i - R0) * (i + R0 - 1)) / 2u + (uint32_t)j) << 2)) =
-                    __builtin_amdgcn_sqrtf(direct_d2(p.x, p.ldx, p.d, i, j));
+                __builtin_nontemporal_store(
+                    __builtin_amdgcn_sqrtf(direct_d2(p.x, p.ldx, p.d, i, j)),
+                    (float *)(ob + (((uint32_t)((i - R0) * (i + R0 - 1)) / 2u + (uint32_t)j) << 2)));
         }
     }
 }
@@ -502,7 +504,8 @@ __device__ __forceinline__ void edm_distances_to_lds(const EdmMfmaArgs &p, f32x1
 // + row, column point CW + column).  A store covers two rows, 32 lanes with
 // four consecutive pairs each: a 512-byte run of the condensed array per
 // row.  Row i starts at i (i - 1) / 2, any word, hence the 4-byte aligned
-// vector type.
+// vector type.  The output is written once and not read back here:
+// non-temporal stores.
 typedef float f32x4u __attribute__((ext_vector_type(4), aligned(4)));
 
 __device__ __forceinline__ void edm_store_tile_rows(const EdmMfmaArgs &p, const float *D,
@@ -523,11 +526,11 @@ __device__ __forceinline__ void edm_store_tile_rows(const EdmMfmaArgs &p, const 
             if (i >= n) continue;
             float *const orow = p.out + (uint64_t)i * (uint64_t)(i - 1) / 2 + j0;
             if (j0 + 3 < i) {
-                *(f32x4u *)orow = v[k];
+                __builtin_nontemporal_store(v[k], (f32x4u *)orow);
             } else {
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
-                    if (j0 + e < i) orow[e] = v[k][e];
+                    if (j0 + e < i) __builtin_nontemporal_store(v[k][e], orow + e);
             }
         }
     }

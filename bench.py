@@ -741,17 +741,18 @@ def profile_target(tm, torch, args):
         p = tm.Plan(n, args.tile or 64, args.map, flags=args.flags)
         for _ in range(reps):
             p.elementwise(tm.OP_AXPYT_F32, xd, yd, c, ld=n, a=float(a))
-    elif t == "edm":
+    elif t in ("edm", "edm_bf16"):
+        # BF16X3 (edm) or single BF16 (edm_bf16) on the matrix cores
+        mode = tm.EDM_BF16X3 if t == "edm" else tm.EDM_BF16
         n, d = 65536, 128
         X, _ = inputs.points(n, d)
         xd = torch.from_numpy(X).cuda()
         out = torch.empty((n * (n - 1) // 2,), dtype=torch.float32, device="cuda")
         q = tm.Plan(n, 128, "lambda", include_diag=False,
                     flags=args.flags or tm.FLAG_XCD_SWIZZLE)
-        ws = torch.empty(q.edm_workspace_size(d, tm.EDM_BF16X3), dtype=torch.uint8,
-                         device="cuda")
+        ws = torch.empty(q.edm_workspace_size(d, mode), dtype=torch.uint8, device="cuda")
         for _ in range(reps):
-            q.edm(xd, out, mode=tm.EDM_BF16X3, fixup_thr=1e-2, ws=ws)
+            q.edm(xd, out, mode=mode, fixup_thr=1e-2, ws=ws)
     elif t == "edm_fp32":
         n, d = 65536, 128
         X, _ = inputs.points(n, d)
@@ -795,8 +796,8 @@ def main():
     ap.add_argument("--flags", type=int, default=0)
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--profile-target", choices=["elementwise", "edm", "edm_fp32", "life", "int", "copy",
-                                                 "batch"],
+    ap.add_argument("--profile-target", choices=["elementwise", "edm", "edm_bf16", "edm_fp32", "life",
+                                                 "int", "copy", "batch"],
                     help="only launch this workload's kernels a few times (for rocprofv3 runs); "
                          "prints no JSON line")
     args = ap.parse_args()

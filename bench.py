@@ -386,6 +386,7 @@ def bench_life(tm, torch, timer, steps=100, reps=7):
     torch.cuda.empty_cache()
     lam = out["lambda"]["ms"]
     lam1 = one["lambda"]["ms"]
+    copy = same_size_copy(tm, torch, cells)
     return {"n": n, "steps": steps,
             "timing": f"median of {reps} calls of {steps} generations, lambda and BB in turn, "
                       f"each call from the same initial grid",
@@ -400,8 +401,46 @@ def bench_life(tm, torch, timer, steps=100, reps=7):
             "one_generation_GBps": round(2 * cells * steps / (lam1 * 1e-3) / 1e9, 1),
             "one_generation_frac_of_hbm": round(2 * cells * steps / (lam1 * 1e-3) / 1e9
                                                 / HBM_PEAK_GBS, 4),
+            # a plain copy of one generation's bytes, back to back in ping-pong
+            # as the generations run: the rate a launch of this size reaches
+            "copy_same_size": copy,
+            "one_generation_frac_of_same_size_copy": round(
+                2 * cells * steps / (lam1 * 1e-3) / 1e9 / copy["best_GBps"], 4),
             "per_generation_ms_by_map_tile": {f"{c['map']}/t{c['tile']}/f{c['flags']}":
                                               round(c["ms"], 5) for c in table}}
+
+
+def same_size_copy(tm, torch, nbytes, pairs=50):
+    """The streaming probe's copy over nbytes (read and written), launched
+    back to back in ping-pong (a -> c, c -> a) like the generations of a
+    grid, at unroll 1, 256 or 512 threads, cached or non-temporal: the best
+    rate, counting 2 nbytes per launch."""
+    cnt = nbytes // 4
+    a = torch.rand(cnt, device="cuda")
+    c = torch.empty_like(a)
+    table = {}
+    for threads in (256, 512):
+        for nt in (False, True):
+            def pair():
+                tm.stream_probe(tm.PROBE_COPY, c, a, unroll=1, threads=threads, nontemporal=nt)
+                tm.stream_probe(tm.PROBE_COPY, a, c, unroll=1, threads=threads, nontemporal=nt)
+            for _ in range(5):
+                pair()
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(pairs):
+                pair()
+            e1.record()
+            torch.cuda.synchronize()
+            us = e0.elapsed_time(e1) * 1e3 / (2 * pairs)
+            table[f"t{threads}/{'nt' if nt else 'c'}"] = round(2 * 4 * cnt / (us * 1e-6) / 1e9, 1)
+    del a, c
+    torch.cuda.empty_cache()
+    best = max(table, key=table.get)
+    return {"bytes_each_way": 4 * cnt, "best": best, "best_GBps": table[best],
+            "best_frac_of_hbm": round(table[best] / HBM_PEAK_GBS, 4), "GBps": table}
 
 
 def edm_sample_rows(n, pairs):
